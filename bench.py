@@ -1,0 +1,206 @@
+#!/usr/bin/env python3
+"""Throughput of the MI355X absolute-value preconditioned MINRES solver.
+
+Workload (one "step"): the batched-shift configuration -- 64 complex-shifted
+2-D systems (K + lambda_j I) z_j = f_j, 16 each on grids n = 63, 127, 255,
+511, coefficient a = 1 + 0.5 sin(2 pi x) sin(2 pi y), shifts of an
+alpha-circulant all-at-once time discretisation (tau = 1/64, gamma = 1e-2),
+right-hand sides N(0,1) + i N(0,1), zero initial guess, stop at relative
+residual 1e-8.  The step solves all 64 systems with one replay of a captured
+hipGraph of the persistent solver kernel, FP32 sine transforms and mode
+scaling in the preconditioner, FP64 everywhere else.  Inputs are resident in
+HBM before timing starts.
+
+Also measured (reported beside the main figure): the same 64 systems solved
+one after another by the plain FP64 solver (one persistent launch each), the
+HBM roofline fraction of the solver kernel, and the CPU oracle on a bounded
+sample of the systems.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "MINRES solves/s at relres 1e-8: batched mixed-precision vs plain FP64, 1 GPU"
+PEAK_HBM_GBS = 8000.0
+# Algorithmic HBM bytes per grid point per MINRES iteration (2-D, FP32
+# preconditioner): stencil 40 + Lanczos/w/x updates 160 + 3 sine-transform
+# passes of 16 bytes read + written.
+BYTES_PER_POINT_ITER_2D_FP32P = 248.0
+BYTES_PER_POINT_ITER_2D_FP64 = 296.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--plain-reps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=8,
+                    help="systems of the batch timed with the CPU oracle")
+    ap.add_argument("--count", type=int, default=64)
+    return ap.parse_args()
+
+
+def cpu_baseline(workload, systems_idx, gpu_solutions):
+    """Time the CPU oracle (single-threaded NumPy/SciPy FP64) on a sample of
+    the batch; the sample keeps the batch's mix of grid sizes."""
+    from oracle import csl_oracle as O
+    t_total = 0.0
+    errs = []
+    iters = []
+    for j in systems_idx:
+        s = workload.systems[j]
+        t0 = time.perf_counter()
+        po = O.Problem(s.a, s.lam.real, s.lam.imag)
+        zo, io = po.solve(s.f, tol=1e-8)
+        t_total += time.perf_counter() - t0
+        iters.append(io["iters"])
+        zg = gpu_solutions[j]
+        errs.append(float(np.linalg.norm(zg - zo) / np.linalg.norm(zo)))
+    return t_total, errs, iters
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this solver runs on one GPU only; multi-GPU runs are "
+                                   "not part of this build (shard by system across GPUs)"}))
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU available"}))
+        sys.exit(1)
+    import paper_2408_00488_amd as C
+    from paper_2408_00488_amd import workloads as WL
+    C.load_library()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    w = WL.workload("c4", count_override=args.count)
+    log(WL.describe(w))
+    A = [torch.from_numpy(s.a).to(dev) for s in w.systems]
+    F = [torch.from_numpy(s.f).to(dev) for s in w.systems]
+    points = int(sum(s.a.size for s in w.systems))
+
+    # ---------------- batched mixed precision (the measured step)
+    probs32 = [C.Problem(a, s.lam.real, s.lam.imag, pinv_fp32=True) for a, s in zip(A, w.systems)]
+    batch = C.Batch(probs32, tol=1e-8, maxit=1000, check_true=True, use_graph=True)
+    Z = [torch.empty_like(f) for f in F]
+    stream = torch.cuda.current_stream()
+    zs, infos = batch.solve(F, Z)
+    log("batch iters:", [i["iters"] for i in infos])
+    for _ in range(args.warmup):
+        batch.solve(F, Z, want_info=False)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        batch.solve(F, Z, want_info=False)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_ms = [a.elapsed_time(b) for a, b in ev]
+    ms_per_step = wall * 1e3 / args.steps
+    value = len(w.systems) * args.steps / wall
+    zs, infos = batch.solve(F, Z)
+    iters = [i["iters"] for i in infos]
+    relres = [i["relres_true"] for i in infos]
+    statuses = [i["status"] for i in infos]
+    Zcpu = [z.cpu().numpy() for z in Z]
+
+    # algorithmic bytes of one launch (per-iteration model x iterations)
+    alg_bytes = sum(it * s.a.size * BYTES_PER_POINT_ITER_2D_FP32P
+                    for it, s in zip(iters, w.systems))
+    avg_launch_s = float(np.mean(launch_ms)) * 1e-3
+    achieved = alg_bytes / avg_launch_s / 1e9
+
+    # ---------------- plain FP64, one solve after another
+    probs64 = [C.Problem(a, s.lam.real, s.lam.imag, pinv_fp32=False)
+               for a, s in zip(A, w.systems)]
+    Z64 = [torch.empty_like(f) for f in F]
+    for p, f, z in zip(probs64, F, Z64):
+        C.minres_solve(p, f, z, want_info=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.plain_reps):
+        for p, f, z in zip(probs64, F, Z64):
+            C.minres_solve(p, f, z, want_info=False)
+    torch.cuda.synchronize()
+    plain_wall = (time.perf_counter() - t0) / args.plain_reps
+    plain_value = len(w.systems) / plain_wall
+    iters64 = []
+    for p, f, z in zip(probs64, F, Z64):
+        _, inf = C.minres_solve(p, f, z)
+        iters64.append(inf["iters"])
+
+    # ---------------- CPU oracle on a bounded sample
+    cpu = None
+    err_vs_oracle = None
+    if not args.no_cpu_baseline:
+        k = max(4, min(args.cpu_sample, len(w.systems)))
+        idx = list(range(k))
+        t_cpu, errs, it_o = cpu_baseline(w, idx, Zcpu)
+        cpu = {"value": k / t_cpu, "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {k} systems of the batch (n = 63,127,255,511 in turn), "
+                         f"FP64 NumPy/SciPy single thread, {t_cpu:.1f} s"}
+        err_vs_oracle = max(errs)
+        log("oracle iters", it_o, "gpu", iters[:k], "max rel err vs oracle", err_vs_oracle)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": "batched shifts: 64 2-D systems, n in {63,127,255,511} "
+                               "(16 each), a=1+0.5 sin(2 pi x) sin(2 pi y), alpha-circulant "
+                               "shifts tau=1/64 gamma=1e-2, FP32 preconditioner, tol 1e-8, "
+                               "one hipGraph replay",
+                   "systems": len(w.systems), "points": points},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "kernel": "solve_kernel", "avg_launch_ms": avg_launch_s * 1e3,
+                     "alg_bytes_per_launch": alg_bytes},
+        "cpu_baseline": cpu,
+        "plain_fp64": {"value": plain_value, "unit": "solves/s",
+                       "ms_per_64": plain_wall * 1e3,
+                       "iters_min": min(iters64), "iters_max": max(iters64)},
+        "speedup_vs_plain_fp64": value / plain_value,
+        "iters": {"min": min(iters), "max": max(iters), "sum": int(sum(iters))},
+        "max_relres_true": max(relres),
+        "all_converged": all(s == 0 for s in statuses),
+        "max_rel_err_vs_fp64_oracle": err_vs_oracle,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,205 @@
+/*
+ * csl.h -- C ABI of the MI355X (gfx950) solver for complex-shifted
+ * Laplacian systems with the absolute-value preconditioner of
+ * Lin, Li & Hon, "Absolute-value based preconditioner for complex-shifted
+ * Laplacian systems" (arXiv:2408.00488).
+ *
+ * Problem (Section 1, Eq. (1)):  (K + lambda I) z = f,  lambda = alpha + i beta,
+ * K the 5-point (2-D) or 7-point (3-D) finite-difference matrix of
+ * -div(a grad) on a uniform grid of a rectangular domain, homogeneous
+ * Dirichlet boundary.  Face coefficients are harmonic means of the nodal
+ * samples of a; a face on the boundary carries the adjacent nodal value.
+ *
+ * Solver: preconditioned MINRES on the real symmetric 2x2 block form
+ * (Eq. (2), read as A = [[K + alpha I, beta I], [beta I, -(K + alpha I)]]
+ * acting on [Re z; -Im z]) with the preconditioner
+ * P = blkdiag(sqrt((abar L + alpha I)^2 + beta^2 I)) twice (Eq. (4)),
+ * applied through multi-axis sine transforms (Section 2.3).
+ *
+ * Data layout.  Every vector is a DEVICE array of M = n_0 * ... * n_{d-1}
+ * complex numbers stored as interleaved (re, im) double pairs, indexed by
+ * interior grid node in C order (last axis contiguous).  The real block
+ * vector [x1; x2] is stored as x1 + i x2.  The nodal coefficient is a DEVICE
+ * array of M doubles in the same order.  Grid axis k has n[k] interior
+ * points with n[k] + 1 a power of two, 2 <= n[k] + 1 <= 1024 (n in
+ * {3, 7, ..., 1023}), mesh width h_k = length[k] / (n[k] + 1).
+ *
+ * Ownership.  The caller owns every vector and coefficient buffer and keeps
+ * it alive while work that uses it is queued.  A problem handle owns a copy
+ * of the coefficient, the per-axis eigenvalue tables and all workspaces,
+ * allocated in create_problem and freed in destroy_problem; solves allocate
+ * nothing.  A problem (and a batch) may be used by one solve at a time.
+ *
+ * Streams.  Every call takes a hipStream_t (0 = default stream) and orders
+ * its device work on it.  Calls that return a solve info (info != NULL)
+ * synchronise that stream before returning.
+ *
+ * Errors.  Every entry point returns a csl_status and never aborts;
+ * csl_last_error() returns a thread-local message for the last non-OK
+ * status.  Non-convergence is a status: the output holds the last iterate
+ * and the info records iterations and residuals.
+ */
+#ifndef CSL_H
+#define CSL_H
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum csl_status {
+    CSL_OK = 0,
+    CSL_ERR_ARG = 1,            /* invalid argument (message says which)        */
+    CSL_ERR_SINGULAR = 2,       /* preconditioner singular: beta = 0 and
+                                   abar*mu_k + alpha = 0 for some mode k        */
+    CSL_ERR_NOT_CONVERGED = 3,  /* maxit reached; output = last iterate          */
+    CSL_ERR_BREAKDOWN = 4,      /* <z, v> < 0 in the Lanczos process
+                                   (preconditioner not positive definite)       */
+    CSL_ERR_NONFINITE = 5,      /* NaN / Inf in the data or the recurrences     */
+    CSL_ERR_HIP = 6,            /* a HIP runtime call failed                     */
+    CSL_ERR_OOM = 7,            /* device allocation failed                      */
+    CSL_ERR_TIMEOUT = 8         /* the solver kernel exceeded its time limit     */
+} csl_status;
+
+typedef struct csl_problem_s *csl_problem;
+typedef struct csl_batch_s *csl_batch;
+
+/* Grid of the rectangular domain (Section 1): dim in {2, 3}; n[k] interior
+ * points along axis k (axis dim-1 contiguous); length[k] > 0 the side
+ * length (a value <= 0 means 1).  Unused entries are ignored. */
+typedef struct csl_grid {
+    int dim;
+    int n[3];
+    double length[3];
+} csl_grid;
+
+/* How abar of K_bar = abar L is chosen (Eq. (4) uses sqrt(a_min a_max)). */
+enum {
+    CSL_ABAR_MEAN = 0,      /* arithmetic mean of the nodal samples (default) */
+    CSL_ABAR_GEOMEAN = 1,   /* sqrt(min c_e * max c_e) over face coefficients  */
+    CSL_ABAR_GIVEN = 2      /* csl_problem_opts.abar                            */
+};
+
+/* Arithmetic of the preconditioner's sine transforms and mode scaling. */
+enum {
+    CSL_PREC_FP64 = 0,      /* everything FP64                                  */
+    CSL_PREC_FP32 = 1       /* transforms and scaling in FP32; Lanczos vectors,
+                               inner products, norms and rotations stay FP64   */
+};
+
+typedef struct csl_problem_opts {
+    int abar_rule;          /* CSL_ABAR_*                                       */
+    int pinv_prec;          /* CSL_PREC_*                                       */
+    double abar;            /* used when abar_rule == CSL_ABAR_GIVEN            */
+    int reserved[4];
+} csl_problem_opts;
+
+typedef struct csl_solve_opts {
+    double tol;             /* relative tolerance (default 1e-8 when <= 0)      */
+    int maxit;              /* iteration limit (default 1000 when <= 0)         */
+    int check_true_residual;/* 1: also require ||f - (K+lambda I) z|| / ||f||
+                               <= tol once the recurrence estimate passed      */
+    int timeout_ms;         /* kernel time limit (default 60000 when <= 0)      */
+    int reserved[3];
+} csl_solve_opts;
+
+typedef struct csl_solve_info {
+    int status;             /* csl_status of this system                        */
+    int iters;              /* MINRES iterations (one A and one P^{-1} each)    */
+    double relres_est;      /* |eta_k| / |eta_0|: P^{-1}-norm residual ratio     */
+    double relres_true;     /* ||f - (K + lambda I) z||_2 / ||f||_2             */
+} csl_solve_info;
+
+/* Create a problem: copies a (device, M doubles, all finite and > 0),
+ * computes the face-coefficient bounds and abar, the per-axis eigenvalues
+ * mu_k = (4/h^2) sin^2(k pi / (2(n+1))) of L (Section 2.3), checks that P is
+ * nonsingular, and allocates the workspaces.  Synchronises `s`.
+ * opts may be NULL (defaults: mean rule, FP64). */
+csl_status create_problem(const csl_grid *grid, const double *a_nodal,
+                          double alpha, double beta,
+                          const csl_problem_opts *opts, hipStream_t s,
+                          csl_problem *out);
+
+csl_status destroy_problem(csl_problem p);
+
+/* Query: abar used by P, and the face-coefficient bounds a_min, a_max
+ * (Lemma 3).  Any pointer may be NULL. */
+csl_status problem_info(csl_problem p, double *abar, double *a_min,
+                        double *a_max);
+
+/* y = A x for the block matrix of Eq. (2); in complex storage
+ * y = (K + lambda I) conj(x).  x, y: device, M complex; must not alias. */
+csl_status apply_A(csl_problem p, const double *x, double *y, hipStream_t s);
+
+/* y = P^{-1} x with P of Eq. (4) (the same real operator on Re and Im),
+ * through forward sine transforms along every axis, the per-mode factor
+ * 1/sqrt((abar mu + alpha)^2 + beta^2) and inverse transforms
+ * (Section 2.3).  x, y: device, M complex; may alias. */
+csl_status apply_Pinv(csl_problem p, const double *x, double *y,
+                      hipStream_t s);
+
+/* Solve (K + lambda I) z = f by preconditioned MINRES on the block system
+ * from z0 = 0 (Section 3).  f, z: device, M complex, must not alias.
+ * Stops after iteration k when |eta_k|/|eta_0| <= tol and (if requested)
+ * the true relative residual <= tol.  One persistent kernel launch.
+ * If info != NULL, synchronises `s`, fills info and returns its status;
+ * otherwise returns CSL_OK once the work is queued. */
+csl_status minres_solve(csl_problem p, const double *f, double *z,
+                        const csl_solve_opts *opts, csl_solve_info *info,
+                        hipStream_t s);
+
+/* Adjoint of z = (K + lambda I)^{-1} f for a real loss L(z).
+ * gz = dL/dRe z + i dL/dIm z (device, M complex).  One extra MINRES solve
+ * y = (K + conj(lambda) I)^{-1} gz on the same symmetric block matrix, then
+ *   gf = y (device, M complex, written),
+ *   *galpha = -Re(y^H z), *gbeta = Im(y^H z) (device doubles, written),
+ *   ga[p] += sum over faces e of p of dL/dc_e * dc_e/da_p (device, M
+ *   doubles, ACCUMULATED), dL/dc_e = -Re(y^H dK/dc_e z).
+ * z is the forward solution (device, M complex).  The dependence of abar
+ * on a is ignored (P does not change the exact solution).  Any of gf,
+ * galpha, gbeta, ga may be NULL.  Synchronises `s` when info != NULL. */
+csl_status minres_adjoint(csl_problem p, const double *z, const double *gz,
+                          double *gf, double *galpha, double *gbeta,
+                          double *ga, const csl_solve_opts *opts,
+                          csl_solve_info *info, hipStream_t s);
+
+typedef struct csl_batch_opts {
+    double tol;
+    int maxit;
+    int check_true_residual;
+    int timeout_ms;
+    int grid_size;          /* workgroups of the persistent launch; 0 = auto   */
+    int use_graph;          /* 1: replay a captured hipGraph per solve          */
+    int reserved[3];
+} csl_batch_opts;
+
+/* Group `count` problems (any grids, shifts and precisions) into one
+ * persistent launch: every workgroup takes tiles from whichever system has
+ * work ready, so systems of uneven size share the device.  The problems
+ * must outlive the batch and must not be solved separately while a batch
+ * solve is queued.  opts may be NULL. */
+csl_status batch_create(const csl_problem *problems, int count,
+                        const csl_batch_opts *opts, csl_batch *out);
+
+/* Solve every system of the batch: f[j], z[j] are device pointers for
+ * system j (host arrays of `count` pointers).  One (graph) launch.  If
+ * infos != NULL (host array of `count`), synchronises `s`, fills the infos
+ * and returns CSL_OK only if every system converged (else the first
+ * non-OK status). */
+csl_status batch_solve(csl_batch b, const double *const *f, double *const *z,
+                       csl_solve_info *infos, hipStream_t s);
+
+csl_status batch_destroy(csl_batch b);
+
+/* Thread-local message describing the last non-OK status of this thread. */
+const char *csl_last_error(void);
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int csl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CSL_H */

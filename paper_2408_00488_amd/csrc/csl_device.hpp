@@ -1,0 +1,359 @@
+// Device building blocks for gfx950: complex helpers, LDS-staged sine
+// transforms (DST-I through a radix-4/2 Stockham FFT of the odd extension),
+// the variable-coefficient stencil, and the phase tiles of the MINRES
+// iteration.  Everything here runs inside workgroups of NT threads.
+#pragma once
+#include "csl_common.hpp"
+
+namespace csl {
+
+template <typename R>
+struct alignas(2 * sizeof(R)) Cx {
+  R x, y;
+};
+
+template <typename R>
+__device__ __forceinline__ Cx<R> cadd(Cx<R> a, Cx<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename R>
+__device__ __forceinline__ Cx<R> csub(Cx<R> a, Cx<R> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename R>
+__device__ __forceinline__ Cx<R> cmul(Cx<R> a, Cx<R> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+// Twiddle tables exp(-2 pi i m / TWN), m < TWN, filled by the host runtime.
+__device__ double2 g_tw64[TWN];
+__device__ float2 g_tw32[TWN];
+
+template <typename R> __device__ __forceinline__ const Cx<R> *twiddles();
+template <> __device__ __forceinline__ const Cx<double> *twiddles<double>() {
+  return reinterpret_cast<const Cx<double> *>(g_tw64);
+}
+template <> __device__ __forceinline__ const Cx<float> *twiddles<float>() {
+  return reinterpret_cast<const Cx<float> *>(g_tw32);
+}
+
+// Elements of the LDS line buffer per precision (64 KiB either way).
+template <typename R> struct MaxElts;
+template <> struct MaxElts<double> { static constexpr int value = 4096; };
+template <> struct MaxElts<float> { static constexpr int value = 8192; };
+
+// ---------------------------------------------------------------------------
+// In-LDS complex FFT of `nl` lines of length L = 2^lg stored back to back.
+// Stockham autosort: a radix-2 stage first when lg is odd, then radix-4
+// stages; each stage reads all of its inputs into registers, synchronises,
+// and writes the outputs in place.  Output is in natural order.
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ void fft_lines(Cx<R> *buf, int nl, int lg) {
+  constexpr int MAXE = MaxElts<R>::value;
+  const int tid = threadIdx.x;
+  const int L = 1 << lg;
+  const Cx<R> *tw = twiddles<R>();
+  int Ns = 1;
+  if (lg & 1) {
+    constexpr int U = MAXE / (2 * NT);
+    const int half = L >> 1;
+    const int total = nl * half;
+    Cx<R> a0[U], a1[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int b = tid + u * NT;
+      if (b < total) {
+        const int l = b >> (lg - 1), j = b & (half - 1);
+        a0[u] = buf[l * L + j];
+        a1[u] = buf[l * L + j + half];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int b = tid + u * NT;
+      if (b < total) {
+        const int l = b >> (lg - 1), j = b & (half - 1);
+        buf[l * L + 2 * j] = cadd(a0[u], a1[u]);
+        buf[l * L + 2 * j + 1] = csub(a0[u], a1[u]);
+      }
+    }
+    __syncthreads();
+    Ns = 2;
+  }
+  constexpr int U = MAXE / (4 * NT);
+  const int quarter = L >> 2;
+  const int total = nl * quarter;
+  for (; Ns < L; Ns <<= 2) {
+    Cx<R> a[U][4];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int b = tid + u * NT;
+      if (b < total) {
+        const int l = b >> (lg - 2), j = b & (quarter - 1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[u][q] = buf[l * L + j + q * quarter];
+      }
+    }
+    __syncthreads();
+    const int tstep = TWN / (4 * Ns);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int b = tid + u * NT;
+      if (b < total) {
+        const int l = b >> (lg - 2), j = b & (quarter - 1);
+        const int k = j & (Ns - 1);
+        Cx<R> x0 = a[u][0], x1 = a[u][1], x2 = a[u][2], x3 = a[u][3];
+        if (Ns > 1) {
+          x1 = cmul(x1, tw[k * tstep]);
+          x2 = cmul(x2, tw[2 * k * tstep]);
+          x3 = cmul(x3, tw[3 * k * tstep]);
+        }
+        const Cx<R> t0 = cadd(x0, x2), t1 = csub(x0, x2);
+        const Cx<R> t2 = cadd(x1, x3), t3 = csub(x1, x3);
+        const Cx<R> mt3 = {t3.y, -t3.x};  // -i * t3
+        const int base = l * L + ((j - k) << 2) + k;
+        buf[base] = cadd(t0, t2);
+        buf[base + Ns] = cadd(t1, mt3);
+        buf[base + 2 * Ns] = csub(t0, t2);
+        buf[base + 3 * Ns] = csub(t1, mt3);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// A tile of lines of one sine-transform pass.
+// Element r of line l lives at global index base + l*lstride + r*stride.
+// ---------------------------------------------------------------------------
+struct LineTile {
+  int ax;       // axis of the transform
+  int n;        // line length (interior points along ax)
+  int lg;       // log2 of the FFT length 2(n+1)
+  int nl;       // valid lines in this tile
+  int lp;       // lines per tile (power of two) of this pass
+  int lgl;      // log2(lp)
+  int base, stride, lstride;
+  int row0;     // contiguous-axis passes: first row
+  int outer;    // strided passes: index along the remaining axis (3-D)
+  int c0;       // strided passes: first index along the contiguous axis
+  uint32_t magic;  // ceil(2^32 / n), for e / n with e < 2^14
+};
+
+__device__ __forceinline__ int ilog2i(int v) { return 31 - __clz(v); }
+
+__device__ __forceinline__ LineTile line_tile(const SysDesc &S, int ax, int tile) {
+  LineTile t;
+  t.ax = ax;
+  t.n = S.n[ax];
+  t.lg = S.lg[ax];
+  t.lp = S.lpt[ax];
+  t.lgl = ilog2i(t.lp);
+  t.magic = (uint32_t)((0x100000000ull + (uint64_t)t.n - 1) / (uint64_t)t.n);
+  if (ax == S.d - 1) {
+    t.row0 = tile * t.lp;
+    t.nl = min(t.lp, S.rows - t.row0);
+    t.base = t.row0 * t.n;
+    t.stride = 1;
+    t.lstride = t.n;
+    t.outer = 0;
+    t.c0 = 0;
+  } else {
+    const int nlast = S.n[S.d - 1];
+    const int nblk = (nlast + t.lp - 1) / t.lp;
+    const int outer = tile / nblk;
+    const int blk = tile - outer * nblk;
+    t.c0 = blk * t.lp;
+    t.nl = min(t.lp, nlast - t.c0);
+    t.outer = outer;
+    const int o = (S.d == 3) ? (ax == 0 ? 1 : 0) : -1;
+    t.base = (o >= 0 ? outer * S.st[o] : 0) + t.c0;
+    t.stride = S.st[ax];
+    t.lstride = 1;
+    t.row0 = 0;
+  }
+  return t;
+}
+
+// Split a flat element counter into (line, position).  Contiguous-axis
+// tiles run positions fastest (coalesced rows); strided tiles run lines
+// fastest (coalesced across adjacent lines).  Returns false if invalid.
+__device__ __forceinline__ bool split_elem(const LineTile &t, int e, int &l, int &r) {
+  if (t.stride == 1) {
+    l = (int)__umulhi((uint32_t)e, t.magic);
+    r = e - l * t.n;
+    return l < t.nl;
+  }
+  r = e >> t.lgl;
+  l = e & (t.lp - 1);
+  return l < t.nl && r < t.n;
+}
+
+__device__ __forceinline__ int tile_elems(const LineTile &t) {
+  return t.stride == 1 ? t.nl * t.n : t.lp * t.n;
+}
+
+// Fill the LDS lines with the odd extension [0, x_1..x_n, 0, -x_n..-x_1].
+template <typename R, class Load>
+__device__ void lines_fill(Cx<R> *buf, const LineTile &t, Load &&load) {
+  const int tid = threadIdx.x;
+  const int L = 1 << t.lg, N = L >> 1;
+  const int total = tile_elems(t);
+  constexpr int U = 4;
+  for (int e0 = 0; e0 < total; e0 += NT * U) {
+    Cx<R> v[U];
+    int pos[U], rr[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * NT + tid;
+      pos[u] = -1;
+      int l, r;
+      if (e < total && split_elem(t, e, l, r)) {
+        v[u] = load(l, r, t.base + l * t.lstride + r * t.stride);
+        pos[u] = l * L;
+        rr[u] = r;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (pos[u] >= 0) {
+        buf[pos[u] + rr[u] + 1] = v[u];
+        buf[pos[u] + L - 1 - rr[u]] = Cx<R>{-v[u].x, -v[u].y};
+      }
+    }
+  }
+  for (int l = tid; l < t.nl; l += NT) {
+    buf[l * L] = Cx<R>{0, 0};
+    buf[l * L + N] = Cx<R>{0, 0};
+  }
+  __syncthreads();
+}
+
+// Orthonormal DST-I output k = r + 1 of a transformed line:
+// S_k = (i / sqrt(2N)) * Y_k.
+template <typename R>
+__device__ __forceinline__ Cx<R> dst_out(Cx<R> Y, R c) { return {-c * Y.y, c * Y.x}; }
+
+// Scale the transformed lines mode by mode and re-extend them in place for
+// the inverse transform (reads positions 1..N-1, writes N+1..2N-1 mirrors).
+template <typename R, class Scale>
+__device__ void lines_scale_extend(Cx<R> *buf, const LineTile &t, Scale &&scale) {
+  const int tid = threadIdx.x;
+  const int L = 1 << t.lg, N = L >> 1;
+  const R c = (R)1 / sqrt((R)L);
+  const int total = tile_elems(t);
+  for (int e = tid; e < total; e += NT) {
+    int l, r;
+    if (split_elem(t, e, l, r)) {
+      const int pos = l * L + r + 1;
+      Cx<R> v = dst_out(buf[pos], c);
+      const R s = scale(l, r);
+      v.x *= s;
+      v.y *= s;
+      buf[pos] = v;
+      buf[l * L + L - 1 - r] = Cx<R>{-v.x, -v.y};
+    }
+  }
+  for (int l = tid; l < t.nl; l += NT) {
+    buf[l * L] = Cx<R>{0, 0};
+    buf[l * L + N] = Cx<R>{0, 0};
+  }
+  __syncthreads();
+}
+
+template <typename R, class Store>
+__device__ void lines_store(const Cx<R> *buf, const LineTile &t, Store &&store) {
+  const int tid = threadIdx.x;
+  const int L = 1 << t.lg;
+  const R c = (R)1 / sqrt((R)L);
+  const int total = tile_elems(t);
+  for (int e = tid; e < total; e += NT) {
+    int l, r;
+    if (split_elem(t, e, l, r)) {
+      store(l, r, t.base + l * t.lstride + r * t.stride, dst_out(buf[l * L + r + 1], c));
+    }
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Stencil: (K u)_p with harmonic-mean face coefficients, boundary faces
+// carrying a_p, u = 0 outside the grid.
+// ---------------------------------------------------------------------------
+template <int D>
+__device__ __forceinline__ double2 stencil_K(const SysDesc &S, const double *__restrict__ a,
+                                             const double2 *__restrict__ u, int p,
+                                             const int (&idx)[3]) {
+  const double ap = a[p];
+  const double2 up = u[p];
+  double rx = 0.0, ry = 0.0;
+#pragma unroll
+  for (int ax = 0; ax < D; ++ax) {
+    const int st = S.st[ax];
+    double csum = 0.0, nx = 0.0, ny = 0.0;
+    if (idx[ax] > 0) {
+      const double aq = a[p - st];
+      const double c = 2.0 * ap * aq / (ap + aq);
+      const double2 q = u[p - st];
+      nx += c * q.x;
+      ny += c * q.y;
+      csum += c;
+    } else {
+      csum += ap;
+    }
+    if (idx[ax] < S.n[ax] - 1) {
+      const double aq = a[p + st];
+      const double c = 2.0 * ap * aq / (ap + aq);
+      const double2 q = u[p + st];
+      nx += c * q.x;
+      ny += c * q.y;
+      csum += c;
+    } else {
+      csum += ap;
+    }
+    rx += S.h2[ax] * (csum * up.x - nx);
+    ry += S.h2[ax] * (csum * up.y - ny);
+  }
+  return make_double2(rx, ry);
+}
+
+// Multi-index of element r of contiguous-axis row `row`.
+template <int D>
+__device__ __forceinline__ void row_index(const SysDesc &S, int row, int r, int (&idx)[3]) {
+  if (D == 2) {
+    idx[0] = row;
+    idx[1] = r;
+    idx[2] = 0;
+  } else {
+    const int i0 = row / S.n[1];
+    idx[0] = i0;
+    idx[1] = row - i0 * S.n[1];
+    idx[2] = r;
+  }
+}
+
+// Workgroup sum in a fixed order (bitwise reproducible).
+__device__ __forceinline__ double wg_sum(double v, double *red) {
+  const int tid = threadIdx.x;
+  red[tid] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// Coherent reads of control scalars written by other workgroups.
+__device__ __forceinline__ double ld_ctl(const double *p) {
+  const unsigned long long b = __hip_atomic_load(
+      reinterpret_cast<const unsigned long long *>(p), __ATOMIC_RELAXED,
+      __HIP_MEMORY_SCOPE_AGENT);
+  return __longlong_as_double((long long)b);
+}
+__device__ __forceinline__ int ld_ctl(const int *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace csl

@@ -1,0 +1,23 @@
+// Host-callable launch wrappers of the gfx950 kernels.
+#pragma once
+#include "csl_common.hpp"
+
+namespace csl {
+
+hipError_t upload_twiddles(const double2 *tw64, const float2 *tw32);
+hipError_t launch_init(const SysDesc *dsys, int nsys, Glob *G, hipStream_t s);
+hipError_t launch_solve(const SysDesc *dsys, const IOPtr *dio, IOPtr io0, int nsys,
+                        const SolveParams &P, Glob *G, int grid, size_t smem, hipStream_t s);
+hipError_t solve_occupancy(size_t smem, int *blocks_per_cu);
+hipError_t launch_apply_A(const SysDesc *dsys, int d, int M, const double2 *x, double2 *y,
+                          hipStream_t s);
+hipError_t launch_pinv_pass(const SysDesc *dsys, int d, int prec, int kind, int ntile, size_t smem,
+                            const double2 *x, double2 *y, hipStream_t s);
+hipError_t launch_adjoint(const SysDesc *dsys, int d, int M, const double2 *ytil,
+                          const double2 *z, double2 *gf, double *ga, double *part, int nblk,
+                          double *galpha, double *gbeta, hipStream_t s);
+hipError_t launch_conj(const double2 *x, double2 *y, int M, hipStream_t s);
+hipError_t launch_coef_stats(const SysDesc *dsys, int d, int M, double *part, int nblk,
+                             double *out, hipStream_t s);
+
+}  // namespace csl

@@ -1,0 +1,648 @@
+// Host runtime and C ABI of the absolute-value preconditioned MINRES solver
+// (arXiv:2408.00488): problem objects and their workspaces, tiling choices,
+// the stand-alone operators, single and batched persistent solves (the batch
+// optionally replayed from a captured hipGraph) and the adjoint.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "csl.h"
+#include "csl_common.hpp"
+#include "csl_kernels.hpp"
+
+using namespace csl;
+
+namespace {
+
+thread_local std::string g_err;
+
+csl_status fail(csl_status st, const std::string &msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIPCHK(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(e_ == hipErrorOutOfMemory ? CSL_ERR_OOM : CSL_ERR_HIP,               \
+                  std::string(#call) + ": " + hipGetErrorString(e_));                  \
+  } while (0)
+
+constexpr int kMaxDevices = 64;
+bool g_tw_ready[kMaxDevices] = {false};
+
+// exp(-2 pi i m / TWN) in FP64 from the host sin/cos, rounded for FP32.
+csl_status ensure_twiddles(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(CSL_ERR_ARG, "device index out of range");
+  if (g_tw_ready[dev]) return CSL_OK;
+  std::vector<double2> t64(TWN);
+  std::vector<float2> t32(TWN);
+  for (int m = 0; m < TWN; ++m) {
+    const double th = 2.0 * M_PI * (double)m / (double)TWN;
+    t64[m] = make_double2(std::cos(th), -std::sin(th));
+    t32[m] = make_float2((float)t64[m].x, (float)t64[m].y);
+  }
+  HIPCHK(upload_twiddles(t64.data(), t32.data()));
+  g_tw_ready[dev] = true;
+  return CSL_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int pow2floor(int v) {
+  int p = 1;
+  while (p * 2 <= v) p *= 2;
+  return p;
+}
+
+int ilog2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+}  // namespace
+
+struct csl_problem_s {
+  int device = 0;
+  int cus = 0;
+  double wall_khz = 0.0;
+  SysDesc h{};
+  SysDesc *d_desc = nullptr;
+  void *mem = nullptr;
+  Glob *glob = nullptr;
+  double *stats = nullptr;
+  double *stats_part = nullptr;
+  int stats_nblk = 0;
+  double2 *ytmp = nullptr;
+  double2 *gtmp = nullptr;
+  double *adj_part = nullptr;
+  int adj_nblk = 0;
+  double amin = 0, amax = 0;
+  size_t smem = 0;
+  int grid1 = 1;
+};
+
+struct csl_batch_s {
+  int device = 0;
+  int count = 0;
+  std::vector<csl_problem> probs;
+  SysDesc *d_desc = nullptr;
+  IOPtr *d_io = nullptr;
+  IOPtr *h_io = nullptr;       // pinned
+  DevInfo *d_info = nullptr;
+  Glob *glob = nullptr;
+  void *mem = nullptr;
+  size_t smem = 0;
+  int grid = 1;
+  SolveParams params{};
+  bool use_graph = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t copy_done = nullptr;
+  bool io_valid = false;
+};
+
+namespace {
+
+SolveParams make_params(double tol, int maxit, int check_true, int timeout_ms, double wall_khz) {
+  SolveParams P;
+  P.tol = tol > 0 ? tol : 1e-8;
+  P.maxit = maxit > 0 ? maxit : 1000;
+  P.check_true = check_true ? 1 : 0;
+  const int tms = timeout_ms > 0 ? timeout_ms : 60000;
+  P.timeout_ticks = (long long)(tms * wall_khz);
+  return P;
+}
+
+// Tiling of one system: lines per tile of each transform pass, rows per
+// tile of the pointwise passes, tile counts per phase kind, LDS bytes.
+void choose_tiles(SysDesc &h, size_t *smem_out) {
+  const int eltsz = h.prec ? 8 : 16;
+  const int maxe = h.prec ? 8192 : 4096;
+  const int target = h.prec ? 4096 : 2048;
+  const int nlast = h.n[h.d - 1];
+  size_t smem = 0;
+  for (int ax = 0; ax < 3; ++ax) {
+    if (ax >= h.d) {
+      h.lpt[ax] = 1;
+      continue;
+    }
+    const int L = 2 * (h.n[ax] + 1);
+    const int cap = std::max(1, maxe / L);
+    int want = std::max(1, target / L);
+    if (ax != h.d - 1) want = std::max(want, h.prec ? 8 : 4);  // 64-byte row segments
+    want = std::min(want, 64);
+    int lp = pow2floor(std::min(want, cap));
+    if (ax != h.d - 1) lp = std::min(lp, pow2floor(std::max(1, nlast)) * 2);
+    h.lpt[ax] = std::max(1, lp);
+    smem = std::max(smem, (size_t)h.lpt[ax] * L * eltsz);
+  }
+  h.rpt = std::max(1, 4096 / nlast);
+  for (int k = 0; k < K_NKINDS; ++k) h.ntile[k] = 0;
+  const int rows = h.rows;
+  h.ntile[K_RF] = h.ntile[K_RI] = (rows + h.lpt[h.d - 1] - 1) / h.lpt[h.d - 1];
+  if (h.d == 3) {
+    const int nb1 = (nlast + h.lpt[1] - 1) / h.lpt[1];
+    h.ntile[K_F1] = h.ntile[K_I1] = h.n[0] * nb1;
+    const int nb0 = (nlast + h.lpt[0] - 1) / h.lpt[0];
+    h.ntile[K_MID] = h.n[1] * nb0;
+  } else {
+    const int nb0 = (nlast + h.lpt[0] - 1) / h.lpt[0];
+    h.ntile[K_MID] = nb0;
+  }
+  h.ntile[K_PA] = h.ntile[K_PR] = (rows + h.rpt - 1) / h.rpt;
+  int mx = 0;
+  for (int k = 0; k < K_NKINDS; ++k) mx = std::max(mx, h.ntile[k]);
+  h.maxtile = mx;
+  *smem_out = smem;
+}
+
+csl_status info_from_device(const DevInfo &di, int glob_error, csl_solve_info *info) {
+  csl_solve_info r;
+  r.status = di.status;
+  r.iters = di.iters;
+  r.relres_est = di.relres_est;
+  r.relres_true = di.relres_true;
+  if (glob_error || di.status < 0) r.status = CSL_ERR_TIMEOUT;
+  if (info) *info = r;
+  return (csl_status)r.status;
+}
+
+void free_problem(csl_problem p) {
+  if (!p) return;
+  if (p->mem) (void)hipFree(p->mem);
+  delete p;
+}
+
+}  // namespace
+
+extern "C" {
+
+int csl_version(void) { return 100; }
+
+const char *csl_last_error(void) { return g_err.c_str(); }
+
+csl_status create_problem(const csl_grid *grid, const double *a_nodal, double alpha, double beta,
+                          const csl_problem_opts *opts, hipStream_t s, csl_problem *out) {
+  if (!out) return fail(CSL_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!grid || !a_nodal) return fail(CSL_ERR_ARG, "grid or coefficient is NULL");
+  if (grid->dim != 2 && grid->dim != 3) return fail(CSL_ERR_ARG, "dim must be 2 or 3");
+  if (!std::isfinite(alpha) || !std::isfinite(beta))
+    return fail(CSL_ERR_ARG, "shift must be finite");
+  csl_problem_opts o{};
+  o.abar_rule = CSL_ABAR_MEAN;
+  o.pinv_prec = CSL_PREC_FP64;
+  if (opts) o = *opts;
+  if (o.abar_rule < 0 || o.abar_rule > 2) return fail(CSL_ERR_ARG, "unknown abar rule");
+  if (o.pinv_prec != CSL_PREC_FP64 && o.pinv_prec != CSL_PREC_FP32)
+    return fail(CSL_ERR_ARG, "unknown preconditioner precision");
+  if (o.abar_rule == CSL_ABAR_GIVEN && !(o.abar > 0 && std::isfinite(o.abar)))
+    return fail(CSL_ERR_ARG, "given abar must be finite and positive");
+
+  SysDesc h{};
+  h.d = grid->dim;
+  long long M = 1;
+  for (int ax = 0; ax < 3; ++ax) {
+    if (ax < h.d) {
+      const int n = grid->n[ax];
+      if (n < 3 || n > TWN / 2 - 1 || ((n + 1) & n) != 0)
+        return fail(CSL_ERR_ARG, "n[" + std::to_string(ax) +
+                                     "] + 1 must be a power of two between 4 and 1024");
+      const double len = grid->length[ax] > 0 ? grid->length[ax] : 1.0;
+      if (!std::isfinite(len)) return fail(CSL_ERR_ARG, "length must be finite");
+      const double hh = len / (n + 1);
+      h.n[ax] = n;
+      h.h2[ax] = 1.0 / (hh * hh);
+      h.lg[ax] = ilog2(2 * (n + 1));
+      M *= n;
+    } else {
+      h.n[ax] = 1;
+      h.h2[ax] = 0.0;
+      h.lg[ax] = 0;
+    }
+  }
+  if (M > (1ll << 30)) return fail(CSL_ERR_ARG, "grid too large");
+  h.M = (int)M;
+  h.st[h.d - 1] = 1;
+  for (int ax = h.d - 2; ax >= 0; --ax) h.st[ax] = h.st[ax + 1] * h.n[ax + 1];
+  h.rows = h.M / h.n[h.d - 1];
+  h.prec = o.pinv_prec;
+  h.alpha = alpha;
+  h.beta = beta;
+
+  csl_problem p = new csl_problem_s();
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    delete p;
+    return fail(CSL_ERR_HIP, "hipGetDevice failed");
+  }
+  p->device = dev;
+  {
+    csl_status st = ensure_twiddles(dev);
+    if (st != CSL_OK) {
+      delete p;
+      return st;
+    }
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    delete p;
+    return fail(CSL_ERR_HIP, "hipGetDeviceProperties failed");
+  }
+  p->cus = prop.multiProcessorCount;
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+    khz = 100000;
+  p->wall_khz = (double)khz;
+
+  choose_tiles(h, &p->smem);
+  p->stats_nblk = std::min(1024, (h.M + NT - 1) / NT);
+  p->adj_nblk = std::min(1024, (h.M + NT - 1) / NT);
+
+  // one allocation for the coefficient copy, tables and workspaces
+  const size_t vec = align256(sizeof(double2) * (size_t)h.M);
+  const size_t tsz = align256((size_t)h.M * (h.prec ? 8 : 16));
+  const int nmu = h.n[0] + h.n[1] + h.n[2];
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o2 = off;
+    off += align256(bytes);
+    return o2;
+  };
+  const size_t o_a = take(sizeof(double) * h.M);
+  const size_t o_mu = take(sizeof(double) * nmu);
+  const size_t o_muf = take(sizeof(float) * nmu);
+  size_t o_v[6];
+  for (int i = 0; i < 6; ++i) o_v[i] = take(vec);
+  const size_t o_t = take(tsz);
+  const size_t o_part = take(sizeof(double) * std::max(1, h.maxtile));
+  const size_t o_ctl = take(sizeof(Ctl));
+  const size_t o_info = take(sizeof(DevInfo));
+  const size_t o_glob = take(sizeof(Glob));
+  const size_t o_desc = take(sizeof(SysDesc));
+  const size_t o_stats = take(sizeof(double) * 4);
+  const size_t o_spart = take(sizeof(double) * 4 * p->stats_nblk);
+  const size_t o_ytmp = take(vec);
+  const size_t o_gtmp = take(vec);
+  const size_t o_apart = take(sizeof(double) * 2 * p->adj_nblk);
+  hipError_t e = hipMalloc(&p->mem, off);
+  if (e != hipSuccess) {
+    delete p;
+    return fail(e == hipErrorOutOfMemory ? CSL_ERR_OOM : CSL_ERR_HIP,
+                std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  char *base = (char *)p->mem;
+  double *d_a = (double *)(base + o_a);
+  double *d_mu = (double *)(base + o_mu);
+  float *d_muf = (float *)(base + o_muf);
+  h.a = d_a;
+  h.V[0] = (double2 *)(base + o_v[0]);
+  h.V[1] = (double2 *)(base + o_v[1]);
+  h.Z[0] = (double2 *)(base + o_v[2]);
+  h.Z[1] = (double2 *)(base + o_v[3]);
+  h.W[0] = (double2 *)(base + o_v[4]);
+  h.W[1] = (double2 *)(base + o_v[5]);
+  h.T = base + o_t;
+  h.part = (double *)(base + o_part);
+  h.ctl = (Ctl *)(base + o_ctl);
+  h.info = (DevInfo *)(base + o_info);
+  p->glob = (Glob *)(base + o_glob);
+  p->d_desc = (SysDesc *)(base + o_desc);
+  p->stats = (double *)(base + o_stats);
+  p->stats_part = (double *)(base + o_spart);
+  p->ytmp = (double2 *)(base + o_ytmp);
+  p->gtmp = (double2 *)(base + o_gtmp);
+  p->adj_part = (double *)(base + o_apart);
+
+  // per-axis eigenvalues of L: (4/h^2) sin^2(k pi / (2(n+1)))
+  std::vector<double> mu(nmu);
+  std::vector<float> muf(nmu);
+  int mo = 0;
+  for (int ax = 0; ax < 3; ++ax) {
+    h.mu[ax] = d_mu + mo;
+    h.mu_f[ax] = d_muf + mo;
+    const int n = h.n[ax];
+    for (int k = 1; k <= n; ++k) {
+      const double sv = std::sin((double)k * M_PI / (2.0 * (n + 1)));
+      mu[mo + k - 1] = ax < h.d ? 4.0 * h.h2[ax] * sv * sv : 0.0;
+      muf[mo + k - 1] = (float)mu[mo + k - 1];
+    }
+    mo += n;
+  }
+  double st4[4];
+#define PCHK(call)                                                                   \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess) {                                                          \
+      free_problem(p);                                                               \
+      return fail(CSL_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));  \
+    }                                                                                \
+  } while (0)
+  PCHK(hipMemcpyAsync(d_a, a_nodal, sizeof(double) * h.M, hipMemcpyDeviceToDevice, s));
+  PCHK(hipMemcpyAsync(d_mu, mu.data(), sizeof(double) * nmu, hipMemcpyHostToDevice, s));
+  PCHK(hipMemcpyAsync(d_muf, muf.data(), sizeof(float) * nmu, hipMemcpyHostToDevice, s));
+  PCHK(hipMemcpyAsync(p->d_desc, &h, sizeof(SysDesc), hipMemcpyHostToDevice, s));
+  PCHK(launch_coef_stats(p->d_desc, h.d, h.M, p->stats_part, p->stats_nblk, p->stats, s));
+  PCHK(hipMemcpyAsync(st4, p->stats, sizeof(st4), hipMemcpyDeviceToHost, s));
+  PCHK(hipStreamSynchronize(s));
+  if (st4[3] != 0.0) {
+    free_problem(p);
+    return fail(CSL_ERR_ARG, "coefficient samples must be finite and positive");
+  }
+  p->amin = st4[1];
+  p->amax = st4[2];
+  double abar = 0.0;
+  if (o.abar_rule == CSL_ABAR_MEAN) abar = st4[0] / (double)h.M;
+  else if (o.abar_rule == CSL_ABAR_GEOMEAN) abar = std::sqrt(st4[1] * st4[2]);
+  else abar = o.abar;
+  h.abar = abar;
+  h.abar_f = (float)abar;
+  h.alpha_f = (float)alpha;
+  h.beta_f = (float)beta;
+  // P is singular only if beta = 0 and abar * mu_sum + alpha = 0 for some mode
+  if (beta == 0.0) {
+    double mn = INFINITY, mxv = 0.0;
+    const int n0 = h.n[0], n1 = h.n[1], n2 = h.d == 3 ? h.n[2] : 1;
+    const double *m0 = mu.data(), *m1 = mu.data() + h.n[0], *m2 = mu.data() + h.n[0] + h.n[1];
+    for (int i = 0; i < n0; ++i)
+      for (int j = 0; j < n1; ++j)
+        for (int k = 0; k < n2; ++k) {
+          const double lam = m0[i] + m1[j] + (h.d == 3 ? m2[k] : 0.0);
+          const double v = std::fabs(abar * lam + alpha);
+          mn = std::min(mn, v);
+          mxv = std::max(mxv, v);
+        }
+    if (mn <= 1e-300 || mn <= 1e-14 * mxv) {
+      free_problem(p);
+      return fail(CSL_ERR_SINGULAR, "preconditioner is singular: beta = 0 and "
+                                    "abar*mu + alpha = 0 for some mode");
+    }
+  }
+  p->h = h;
+  PCHK(hipMemcpyAsync(p->d_desc, &p->h, sizeof(SysDesc), hipMemcpyHostToDevice, s));
+  PCHK(hipStreamSynchronize(s));
+  int bpc = 0;
+  PCHK(solve_occupancy(p->smem, &bpc));
+  const int cap = std::max(1, bpc) * p->cus;
+  p->grid1 = std::max(1, std::min(h.maxtile, cap));
+#undef PCHK
+  *out = p;
+  return CSL_OK;
+}
+
+csl_status destroy_problem(csl_problem p) {
+  if (!p) return fail(CSL_ERR_ARG, "problem is NULL");
+  free_problem(p);
+  return CSL_OK;
+}
+
+csl_status problem_info(csl_problem p, double *abar, double *a_min, double *a_max) {
+  if (!p) return fail(CSL_ERR_ARG, "problem is NULL");
+  if (abar) *abar = p->h.abar;
+  if (a_min) *a_min = p->amin;
+  if (a_max) *a_max = p->amax;
+  return CSL_OK;
+}
+
+csl_status apply_A(csl_problem p, const double *x, double *y, hipStream_t s) {
+  if (!p || !x || !y) return fail(CSL_ERR_ARG, "NULL argument");
+  if (x == y) return fail(CSL_ERR_ARG, "apply_A: x and y must not alias");
+  HIPCHK(launch_apply_A(p->d_desc, p->h.d, p->h.M, (const double2 *)x, (double2 *)y, s));
+  return CSL_OK;
+}
+
+csl_status apply_Pinv(csl_problem p, const double *x, double *y, hipStream_t s) {
+  if (!p || !x || !y) return fail(CSL_ERR_ARG, "NULL argument");
+  const SysDesc &h = p->h;
+  const double2 *xi = (const double2 *)x;
+  double2 *yo = (double2 *)y;
+  std::vector<int> kinds;
+  kinds.push_back(K_RF);
+  if (h.d == 3) kinds.push_back(K_F1);
+  kinds.push_back(K_MID);
+  if (h.d == 3) kinds.push_back(K_I1);
+  kinds.push_back(K_RI);
+  for (int k : kinds)
+    HIPCHK(launch_pinv_pass(p->d_desc, h.d, h.prec, k, h.ntile[k], p->smem, xi, yo, s));
+  return CSL_OK;
+}
+
+static csl_status run_single(csl_problem p, const double2 *f, double2 *x, const SolveParams &P,
+                             hipStream_t s) {
+  HIPCHK(launch_init(p->d_desc, 1, p->glob, s));
+  IOPtr io0{f, x};
+  HIPCHK(launch_solve(p->d_desc, nullptr, io0, 1, P, p->glob, p->grid1, p->smem, s));
+  return CSL_OK;
+}
+
+static csl_status fetch_single_info(csl_problem p, csl_solve_info *info, hipStream_t s) {
+  DevInfo di;
+  Glob g;
+  HIPCHK(hipMemcpyAsync(&di, p->h.info, sizeof(di), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&g, p->glob, sizeof(g), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const csl_status st = info_from_device(di, g.error, info);
+  if (st != CSL_OK) {
+    static const char *names[] = {"ok", "bad argument", "singular", "not converged",
+                                  "breakdown", "non-finite", "hip", "oom", "timeout"};
+    g_err = std::string("solve ended with status: ") + (st >= 0 && st <= 8 ? names[st] : "?");
+  }
+  return st;
+}
+
+csl_status minres_solve(csl_problem p, const double *f, double *z, const csl_solve_opts *opts,
+                        csl_solve_info *info, hipStream_t s) {
+  if (!p || !f || !z) return fail(CSL_ERR_ARG, "NULL argument");
+  if (f == z) return fail(CSL_ERR_ARG, "minres_solve: f and z must not alias");
+  csl_solve_opts o{};
+  if (opts) o = *opts;
+  if (o.maxit > 16000000) return fail(CSL_ERR_ARG, "maxit too large");
+  if (opts && !(std::isfinite(o.tol))) return fail(CSL_ERR_ARG, "tol must be finite");
+  const SolveParams P = make_params(o.tol, o.maxit, o.check_true_residual, o.timeout_ms, p->wall_khz);
+  csl_status st = run_single(p, (const double2 *)f, (double2 *)z, P, s);
+  if (st != CSL_OK) return st;
+  if (!info) return CSL_OK;
+  return fetch_single_info(p, info, s);
+}
+
+csl_status minres_adjoint(csl_problem p, const double *z, const double *gz, double *gf,
+                          double *galpha, double *gbeta, double *ga, const csl_solve_opts *opts,
+                          csl_solve_info *info, hipStream_t s) {
+  if (!p || !z || !gz) return fail(CSL_ERR_ARG, "NULL argument");
+  csl_solve_opts o{};
+  if (opts) o = *opts;
+  const SolveParams P = make_params(o.tol, o.maxit, o.check_true_residual, o.timeout_ms, p->wall_khz);
+  const int M = p->h.M;
+  // y = (K + conj(lambda) I)^{-1} G  <=>  A (block) u = conj(G) with u = y;
+  // the solve stores conj(u) = conj(y) in ytmp.
+  HIPCHK(launch_conj((const double2 *)gz, p->gtmp, M, s));
+  csl_status st = run_single(p, p->gtmp, p->ytmp, P, s);
+  if (st != CSL_OK) return st;
+  HIPCHK(launch_adjoint(p->d_desc, p->h.d, M, p->ytmp, (const double2 *)z, (double2 *)gf, ga,
+                        p->adj_part, p->adj_nblk, galpha, gbeta, s));
+  if (!info) return CSL_OK;
+  return fetch_single_info(p, info, s);
+}
+
+csl_status batch_create(const csl_problem *problems, int count, const csl_batch_opts *opts,
+                        csl_batch *out) {
+  if (!out) return fail(CSL_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!problems || count <= 0) return fail(CSL_ERR_ARG, "empty batch");
+  csl_batch_opts o{};
+  o.use_graph = 1;
+  if (opts) o = *opts;
+  for (int i = 0; i < count; ++i) {
+    if (!problems[i]) return fail(CSL_ERR_ARG, "NULL problem in batch");
+    for (int j = 0; j < i; ++j)
+      if (problems[j] == problems[i]) return fail(CSL_ERR_ARG, "problem listed twice in batch");
+    if (problems[i]->device != problems[0]->device)
+      return fail(CSL_ERR_ARG, "batch problems must live on one device");
+  }
+  csl_batch b = new csl_batch_s();
+  b->device = problems[0]->device;
+  b->count = count;
+  b->probs.assign(problems, problems + count);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o2 = off;
+    off += align256(bytes);
+    return o2;
+  };
+  const size_t o_desc = take(sizeof(SysDesc) * count);
+  const size_t o_io = take(sizeof(IOPtr) * count);
+  const size_t o_info = take(sizeof(DevInfo) * count);
+  const size_t o_glob = take(sizeof(Glob));
+  hipError_t e = hipMalloc(&b->mem, off);
+  if (e != hipSuccess) {
+    delete b;
+    return fail(CSL_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  char *base = (char *)b->mem;
+  b->d_desc = (SysDesc *)(base + o_desc);
+  b->d_io = (IOPtr *)(base + o_io);
+  b->d_info = (DevInfo *)(base + o_info);
+  b->glob = (Glob *)(base + o_glob);
+  std::vector<SysDesc> descs(count);
+  size_t smem = 0;
+  long long total_tiles = 0;
+  for (int i = 0; i < count; ++i) {
+    descs[i] = problems[i]->h;
+    descs[i].info = b->d_info + i;
+    smem = std::max(smem, problems[i]->smem);
+    total_tiles += problems[i]->h.maxtile;
+  }
+  b->smem = smem;
+  auto cleanup = [&](const std::string &msg) {
+    if (b->h_io) (void)hipHostFree(b->h_io);
+    if (b->copy_done) (void)hipEventDestroy(b->copy_done);
+    (void)hipFree(b->mem);
+    delete b;
+    return fail(CSL_ERR_HIP, msg);
+  };
+  if (hipMemcpy(b->d_desc, descs.data(), sizeof(SysDesc) * count, hipMemcpyHostToDevice) !=
+      hipSuccess)
+    return cleanup("hipMemcpy of batch descriptors failed");
+  if (hipHostMalloc((void **)&b->h_io, sizeof(IOPtr) * count, hipHostMallocDefault) != hipSuccess)
+    return cleanup("hipHostMalloc failed");
+  if (hipEventCreateWithFlags(&b->copy_done, hipEventDisableTiming) != hipSuccess)
+    return cleanup("hipEventCreate failed");
+  int bpc = 0;
+  if (solve_occupancy(smem, &bpc) != hipSuccess) return cleanup("occupancy query failed");
+  const int cap = std::max(1, bpc) * problems[0]->cus;
+  b->grid = o.grid_size > 0 ? o.grid_size : (int)std::min<long long>(cap, total_tiles);
+  b->grid = std::max(1, b->grid);
+  b->params = make_params(o.tol, o.maxit, o.check_true_residual, o.timeout_ms,
+                          problems[0]->wall_khz);
+  b->use_graph = o.use_graph != 0;
+  if (b->use_graph) {
+    hipStream_t cs;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+      return cleanup("hipStreamCreate failed");
+    bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+      ok = launch_init(b->d_desc, count, b->glob, cs) == hipSuccess;
+      IOPtr none{nullptr, nullptr};
+      ok = ok && launch_solve(b->d_desc, b->d_io, none, count, b->params, b->glob, b->grid, smem,
+                              cs) == hipSuccess;
+      hipGraph_t g = nullptr;
+      const bool ended = hipStreamEndCapture(cs, &g) == hipSuccess;
+      ok = ok && ended && g;
+      if (ok) ok = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) == hipSuccess;
+      b->graph = g;
+    }
+    (void)hipStreamDestroy(cs);
+    if (!ok) {
+      if (b->exec) (void)hipGraphExecDestroy(b->exec);
+      if (b->graph) (void)hipGraphDestroy(b->graph);
+      return cleanup("hipGraph capture of the batched solve failed");
+    }
+  }
+  *out = b;
+  return CSL_OK;
+}
+
+csl_status batch_solve(csl_batch b, const double *const *f, double *const *z,
+                       csl_solve_info *infos, hipStream_t s) {
+  if (!b || !f || !z) return fail(CSL_ERR_ARG, "NULL argument");
+  bool same = b->io_valid;
+  for (int i = 0; i < b->count; ++i) {
+    if (!f[i] || !z[i]) return fail(CSL_ERR_ARG, "NULL vector in batch");
+    if ((const void *)f[i] == (const void *)z[i])
+      return fail(CSL_ERR_ARG, "batch_solve: f and z must not alias");
+    if (same && (b->h_io[i].f != (const double2 *)f[i] || b->h_io[i].x != (double2 *)z[i]))
+      same = false;
+  }
+  if (!same) {
+    HIPCHK(hipEventSynchronize(b->copy_done));
+    for (int i = 0; i < b->count; ++i) {
+      b->h_io[i].f = (const double2 *)f[i];
+      b->h_io[i].x = (double2 *)z[i];
+    }
+    HIPCHK(hipMemcpyAsync(b->d_io, b->h_io, sizeof(IOPtr) * b->count, hipMemcpyHostToDevice, s));
+    HIPCHK(hipEventRecord(b->copy_done, s));
+    b->io_valid = true;
+  }
+  if (b->use_graph) {
+    HIPCHK(hipGraphLaunch(b->exec, s));
+  } else {
+    HIPCHK(launch_init(b->d_desc, b->count, b->glob, s));
+    IOPtr none{nullptr, nullptr};
+    HIPCHK(launch_solve(b->d_desc, b->d_io, none, b->count, b->params, b->glob, b->grid, b->smem,
+                        s));
+  }
+  if (!infos) return CSL_OK;
+  std::vector<DevInfo> di(b->count);
+  Glob g;
+  HIPCHK(hipMemcpyAsync(di.data(), b->d_info, sizeof(DevInfo) * b->count, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&g, b->glob, sizeof(g), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  csl_status first = CSL_OK;
+  for (int i = 0; i < b->count; ++i) {
+    const csl_status st = info_from_device(di[i], g.error, &infos[i]);
+    if (st != CSL_OK && first == CSL_OK) first = st;
+  }
+  if (first != CSL_OK) g_err = "batch: at least one system did not converge";
+  return first;
+}
+
+csl_status batch_destroy(csl_batch b) {
+  if (!b) return fail(CSL_ERR_ARG, "batch is NULL");
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->copy_done) (void)hipEventDestroy(b->copy_done);
+  if (b->h_io) (void)hipHostFree(b->h_io);
+  if (b->mem) (void)hipFree(b->mem);
+  delete b;
+  return CSL_OK;
+}
+
+}  // extern "C"

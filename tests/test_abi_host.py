@@ -1,0 +1,83 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every entry point declared in include/csl.h, and rejects bad arguments
+before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2408_00488_amd import build as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "csl.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB):
+        B.build()
+    from paper_2408_00488_amd import load_library
+    return load_library()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?(?:csl_status|int|char)\s*\*?\s*(\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ["create_problem", "destroy_problem", "apply_A", "apply_Pinv", "minres_solve",
+              "minres_adjoint", "batch_create", "batch_solve", "batch_destroy",
+              "csl_last_error", "csl_version", "problem_info"]:
+        assert n in names, n
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+    assert lib.csl_version() >= 100
+
+
+def _grid(dim, n, length=1.0):
+    from paper_2408_00488_amd import _Grid
+    g = _Grid()
+    g.dim = dim
+    for k in range(3):
+        g.n[k] = n[k] if k < len(n) else 0
+        g.length[k] = length
+    return g
+
+
+@pytest.mark.parametrize("dim,n,msg", [(4, (7, 7), "dim"), (2, (8, 7), "power of two"),
+                                       (2, (7, 2047), "power of two"), (3, (7, 7, 1), "power of two")])
+def test_create_problem_rejects_bad_grid(lib, dim, n, msg):
+    h = ctypes.c_void_p()
+    g = _grid(dim, n)
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
+    st = lib.create_problem(ctypes.byref(g), fake, 1.0, 1.0, None, None, ctypes.byref(h))
+    assert st == 1
+    assert msg in lib.csl_last_error().decode()
+    assert not h.value
+
+
+def test_create_problem_rejects_null_and_nonfinite(lib):
+    h = ctypes.c_void_p()
+    g = _grid(2, (7, 7))
+    assert lib.create_problem(ctypes.byref(g), None, 1.0, 1.0, None, None, ctypes.byref(h)) == 1
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.create_problem(ctypes.byref(g), fake, float("nan"), 1.0, None, None,
+                              ctypes.byref(h)) == 1
+    assert "finite" in lib.csl_last_error().decode()
+
+
+def test_null_handles_rejected(lib):
+    assert lib.apply_A(None, None, None, None) == 1
+    assert lib.apply_Pinv(None, None, None, None) == 1
+    assert lib.minres_solve(None, None, None, None, None, None) == 1
+    assert lib.destroy_problem(None) == 1
+    assert lib.batch_destroy(None) == 1
+    assert lib.batch_create(None, 0, None, ctypes.byref(ctypes.c_void_p())) == 1
