@@ -92,7 +92,11 @@ typedef struct csl_problem_opts {
     int abar_rule;          /* CSL_ABAR_*                                       */
     int pinv_prec;          /* CSL_PREC_*                                       */
     double abar;            /* used when abar_rule == CSL_ABAR_GIVEN            */
-    int reserved[4];
+    int tile_elems;         /* target LDS elements per sine-transform tile of
+                               the contiguous axis (0 = default: 2048 FP64,
+                               4096 FP32); larger tiles mean fewer phase
+                               hand-offs, smaller ones more parallelism       */
+    int reserved[3];
 } csl_problem_opts;
 
 typedef struct csl_solve_opts {
@@ -171,7 +175,9 @@ typedef struct csl_batch_opts {
     int timeout_ms;
     int grid_size;          /* workgroups of the persistent launch; 0 = auto   */
     int use_graph;          /* 1: replay a captured hipGraph per solve          */
-    int reserved[3];
+    int reserved[3];        /* reserved[0]: grid points per scheduling tile
+                               (0 = 16384); larger tiles mean fewer
+                               cross-workgroup hand-offs                    */
 } csl_batch_opts;
 
 /* Group `count` problems (any grids, shifts and precisions) into one

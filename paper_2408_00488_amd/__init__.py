@@ -46,7 +46,8 @@ class _Grid(ctypes.Structure):
 
 class _ProblemOpts(ctypes.Structure):
     _fields_ = [("abar_rule", ctypes.c_int), ("pinv_prec", ctypes.c_int),
-                ("abar", ctypes.c_double), ("reserved", ctypes.c_int * 4)]
+                ("abar", ctypes.c_double), ("tile_elems", ctypes.c_int),
+                ("reserved", ctypes.c_int * 3)]
 
 
 class _SolveOpts(ctypes.Structure):
@@ -144,7 +145,7 @@ class Problem:
 
     def __init__(self, a, alpha: float, beta: float, lengths=None,
                  abar_rule: str = "mean", abar: float | None = None,
-                 pinv_fp32: bool = False):
+                 pinv_fp32: bool = False, tile_elems: int = 0):
         torch = _torch()
         L = load_library()
         if not (isinstance(a, torch.Tensor) and a.is_cuda and a.dtype == torch.float64):
@@ -166,6 +167,7 @@ class Problem:
         o.abar_rule = _ABAR[abar_rule]
         o.pinv_prec = 1 if pinv_fp32 else 0
         o.abar = float(abar) if abar is not None else 0.0
+        o.tile_elems = int(tile_elems)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             _check(L.create_problem(ctypes.byref(g), _ptr(self.a), self.alpha, self.beta,
@@ -289,7 +291,7 @@ class Batch:
     """Several problems solved by one persistent launch (optionally a graph)."""
 
     def __init__(self, problems, tol=1e-8, maxit=1000, check_true=True, timeout_ms=0,
-                 grid_size=0, use_graph=True):
+                 grid_size=0, use_graph=True, tile_points=0):
         self.problems = list(problems)
         arr = (ctypes.c_void_p * len(self.problems))(*[p.handle for p in self.problems])
         o = _BatchOpts()
@@ -299,6 +301,7 @@ class Batch:
         o.timeout_ms = int(timeout_ms)
         o.grid_size = int(grid_size)
         o.use_graph = 1 if use_graph else 0
+        o.reserved[0] = int(tile_points)
         h = ctypes.c_void_p()
         _check(load_library().batch_create(arr, len(self.problems), ctypes.byref(o),
                                            ctypes.byref(h)))

@@ -10,18 +10,22 @@ constexpr int NT = 256;        // threads per workgroup (4 wave64)
 constexpr int TWN = 2048;      // twiddle table length = longest FFT
 constexpr int MAX_LG = 11;     // log2(TWN)
 
-// Phase kinds of one MINRES iteration (the order of a 3-D iteration is
-// RF, F1, MID, I1, RI, PA [, PR]; a 2-D one skips F1 and I1).
+// Phase kinds of one MINRES iteration.  The Lanczos vectors are kept
+// transformed along the contiguous axis (W_c v, W_c the orthonormal sine
+// transform of that axis, which is its own inverse); inner products are
+// unchanged by it.  A 2-D iteration j is X, Y, Z; a 3-D one X, Y1, Y, Y1I, Z.
 enum Kind : int {
-  K_RF = 0,   // sine transform along the contiguous axis; source = new
-              // Lanczos vector (stencil + three-term recurrence) or f
-  K_F1 = 1,   // 3-D: forward sine transform along axis 1
-  K_MID = 2,  // axis 0: forward transform, per-mode scaling, inverse
-  K_I1 = 3,   // 3-D: inverse transform along axis 1
-  K_RI = 4,   // inverse transform along the contiguous axis -> z, <z, v>
-  K_PA = 5,   // w/x update of the previous step + delta = <z, A z>
-  K_PR = 6,   // true residual ||f - A x||^2
-  K_NKINDS = 7,
+  K_X = 0,    // contiguous-axis rows: q = A zhat_j (stencil), delta_j partial,
+              // forward transform of q -> Tq (FP64).  Iteration 0: W_c f -> Tv_1
+  K_Y1 = 1,   // 3-D axis 1 columns: recurrence Tv_{j+1} = Tq - (delta/gamma) Tv_j
+              // - (gamma/gamma_old) Tv_{j-1}, forward transform -> T
+  K_Y = 2,    // axis 0 columns: forward transform, per-mode factor, inverse.
+              // 2-D: also the recurrence on input and <T, Tv_{j+1}> on output
+  K_Y1I = 3,  // 3-D axis 1 columns: inverse transform, <T, Tv_{j+1}> partial
+  K_Z = 4,    // contiguous-axis rows: inverse transform -> zhat_{j+1}; update
+              // w_{j+1} and x_j of step j
+  K_PR = 5,   // rows: true residual ||f - A x||^2 partial
+  K_NKINDS = 6,
   K_DONE = 15
 };
 
@@ -38,6 +42,7 @@ struct alignas(64) Ctl {
   unsigned long long word;   // ticket word (atomic)
   unsigned int done;         // tiles of the current phase completed (atomic)
   int finishing;             // -1, or the status to report after a final PR
+  int after_z;               // 0: next iteration, 1: residual check, 2: final
   // Lanczos / Givens scalars (FP64, written only by phase epilogues)
   double gamma, gamma_old;   // gamma_j, gamma_{j-1}
   double c, c_old, s, s_old; // rotations c_j, c_{j-1}, s_j, s_{j-1}
@@ -66,27 +71,30 @@ struct SysDesc {
   int M;          // points
   int rows;       // M / n[d-1]: lines along the contiguous axis
   int prec;       // 0 = FP64 preconditioner, 1 = FP32
-  int lpt[3];     // lines per tile of the sine-transform pass along each axis
-  int rpt;        // rows per tile of the pointwise passes
-  int ntile[K_NKINDS];
+  int lpt_x;      // rows per tile of the FP64 contiguous-axis pass (K_X)
+  int lpt_z;      // rows per tile of the preconditioner-precision row pass
+  int lpt_s[2];   // lines per tile of the strided passes along axes 0, 1
+  int rpt;        // rows per tile of the residual pass
+  int fst[3][3];  // strides of the face-coefficient array of each axis
+  int nchunk[K_NKINDS];  // LDS-sized chunks of each phase kind
+  int cpt[K_NKINDS];     // chunks per tile (one scheduling unit)
+  int ntile[K_NKINDS];   // ceil(nchunk / cpt)
   int maxtile;
   double h2[3];   // 1 / h_k^2
   double alpha, beta, abar;
   float alpha_f, beta_f, abar_f;
   const double *a;         // nodal coefficient
+  const double *F[3];      // face coefficients / h_k^2 of each axis
   const double *mu[3];     // per-axis eigenvalues of L, FP64
   const float *mu_f[3];    // FP32 copies
-  double2 *V[2];           // Lanczos vectors v (by parity of the index)
-  double2 *Z[2];           // preconditioned vectors z
-  double2 *W[2];           // search directions w
-  void *T;                 // sine-transform intermediate (double2 or float2)
+  double2 *Tq;             // W_c (A zhat_j)
+  double2 *Tv[2];          // W_c v_m, by parity of m
+  void *T;                 // preconditioner intermediate (double2 or float2)
+  double2 *Z[2];           // zhat_m = P^{-1} v_m / gamma_m, by parity of m
+  double2 *W[2];           // search directions w_m, by parity of m
   double *part;            // per-tile partial sums
   Ctl *ctl;
   DevInfo *info;
-  // solve parameters
-  double tol;
-  int maxit;
-  int check_true;
 };
 
 // Right-hand side and output of one system for one solve.

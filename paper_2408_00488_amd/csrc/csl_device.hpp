@@ -33,10 +33,10 @@ template <> __device__ __forceinline__ const Cx<float> *twiddles<float>() {
   return reinterpret_cast<const Cx<float> *>(g_tw32);
 }
 
-// Elements of the LDS line buffer per precision (64 KiB either way).
-template <typename R> struct MaxElts;
-template <> struct MaxElts<double> { static constexpr int value = 4096; };
-template <> struct MaxElts<float> { static constexpr int value = 8192; };
+// Elements of the LDS line buffer for an LDS budget of LDSB bytes.
+template <typename R, int LDSB> struct MaxElts {
+  static constexpr int value = LDSB / (int)sizeof(Cx<R>);
+};
 
 // ---------------------------------------------------------------------------
 // In-LDS complex FFT of `nl` lines of length L = 2^lg stored back to back.
@@ -44,9 +44,9 @@ template <> struct MaxElts<float> { static constexpr int value = 8192; };
 // stages; each stage reads all of its inputs into registers, synchronises,
 // and writes the outputs in place.  Output is in natural order.
 // ---------------------------------------------------------------------------
-template <typename R>
+template <typename R, int LDSB>
 __device__ void fft_lines(Cx<R> *buf, int nl, int lg) {
-  constexpr int MAXE = MaxElts<R>::value;
+  constexpr int MAXE = MaxElts<R, LDSB>::value;
   const int tid = threadIdx.x;
   const int L = 1 << lg;
   const Cx<R> *tw = twiddles<R>();
@@ -102,9 +102,12 @@ __device__ void fft_lines(Cx<R> *buf, int nl, int lg) {
         const int k = j & (Ns - 1);
         Cx<R> x0 = a[u][0], x1 = a[u][1], x2 = a[u][2], x3 = a[u][3];
         if (Ns > 1) {
-          x1 = cmul(x1, tw[k * tstep]);
-          x2 = cmul(x2, tw[2 * k * tstep]);
-          x3 = cmul(x3, tw[3 * k * tstep]);
+          const Cx<R> w1 = tw[k * tstep];
+          const Cx<R> w2 = cmul(w1, w1);
+          const Cx<R> w3 = cmul(w2, w1);
+          x1 = cmul(x1, w1);
+          x2 = cmul(x2, w2);
+          x3 = cmul(x3, w3);
         }
         const Cx<R> t0 = cadd(x0, x2), t1 = csub(x0, x2);
         const Cx<R> t2 = cadd(x1, x3), t3 = csub(x1, x3);
@@ -140,12 +143,12 @@ struct LineTile {
 
 __device__ __forceinline__ int ilog2i(int v) { return 31 - __clz(v); }
 
-__device__ __forceinline__ LineTile line_tile(const SysDesc &S, int ax, int tile) {
+__device__ __forceinline__ LineTile line_tile(const SysDesc &S, int ax, int lp, int tile) {
   LineTile t;
   t.ax = ax;
   t.n = S.n[ax];
   t.lg = S.lg[ax];
-  t.lp = S.lpt[ax];
+  t.lp = lp;
   t.lgl = ilog2i(t.lp);
   t.magic = (uint32_t)((0x100000000ull + (uint64_t)t.n - 1) / (uint64_t)t.n);
   if (ax == S.d - 1) {
@@ -192,12 +195,11 @@ __device__ __forceinline__ int tile_elems(const LineTile &t) {
 }
 
 // Fill the LDS lines with the odd extension [0, x_1..x_n, 0, -x_n..-x_1].
-template <typename R, class Load>
+template <typename R, int U = 4, class Load>
 __device__ void lines_fill(Cx<R> *buf, const LineTile &t, Load &&load) {
   const int tid = threadIdx.x;
   const int L = 1 << t.lg, N = L >> 1;
   const int total = tile_elems(t);
-  constexpr int U = 4;
   for (int e0 = 0; e0 < total; e0 += NT * U) {
     Cx<R> v[U];
     int pos[U], rr[U];
@@ -234,18 +236,22 @@ __device__ __forceinline__ Cx<R> dst_out(Cx<R> Y, R c) { return {-c * Y.y, c * Y
 
 // Scale the transformed lines mode by mode and re-extend them in place for
 // the inverse transform (reads positions 1..N-1, writes N+1..2N-1 mirrors).
+// Returns this thread's share of sum_k s_k |U_k|^2 over the tile, U the
+// transform coefficients before scaling.
 template <typename R, class Scale>
-__device__ void lines_scale_extend(Cx<R> *buf, const LineTile &t, Scale &&scale) {
+__device__ double lines_scale_extend(Cx<R> *buf, const LineTile &t, Scale &&scale) {
   const int tid = threadIdx.x;
   const int L = 1 << t.lg, N = L >> 1;
   const R c = (R)1 / sqrt((R)L);
   const int total = tile_elems(t);
+  double acc = 0.0;
   for (int e = tid; e < total; e += NT) {
     int l, r;
     if (split_elem(t, e, l, r)) {
       const int pos = l * L + r + 1;
       Cx<R> v = dst_out(buf[pos], c);
       const R s = scale(l, r);
+      acc += (double)s * ((double)v.x * (double)v.x + (double)v.y * (double)v.y);
       v.x *= s;
       v.y *= s;
       buf[pos] = v;
@@ -257,6 +263,7 @@ __device__ void lines_scale_extend(Cx<R> *buf, const LineTile &t, Scale &&scale)
     buf[l * L + N] = Cx<R>{0, 0};
   }
   __syncthreads();
+  return acc;
 }
 
 template <typename R, class Store>
@@ -274,45 +281,124 @@ __device__ void lines_store(const Cx<R> *buf, const LineTile &t, Store &&store) 
   __syncthreads();
 }
 
+// Two-step variants: every global load of U elements (pre) is issued before
+// any of them is consumed (make / post), so U elements' loads are in flight
+// together.
+template <typename R, int U, class Pre, class Make>
+__device__ void lines_fill2(Cx<R> *buf, const LineTile &t, Pre &&pre, Make &&make) {
+  using PT = decltype(pre(0, 0, 0));
+  const int tid = threadIdx.x;
+  const int L = 1 << t.lg, N = L >> 1;
+  const int total = tile_elems(t);
+  for (int e0 = 0; e0 < total; e0 += NT * U) {
+    PT pv[U];
+    int ll[U], rr[U], pp[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * NT + tid;
+      ll[u] = -1;
+      int l, r;
+      if (e < total && split_elem(t, e, l, r)) {
+        ll[u] = l;
+        rr[u] = r;
+        pp[u] = t.base + l * t.lstride + r * t.stride;
+        pv[u] = pre(l, r, pp[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (ll[u] >= 0) {
+        const Cx<R> v = make(ll[u], rr[u], pp[u], pv[u]);
+        buf[ll[u] * L + rr[u] + 1] = v;
+        buf[ll[u] * L + L - 1 - rr[u]] = Cx<R>{-v.x, -v.y};
+      }
+    }
+  }
+  for (int l = tid; l < t.nl; l += NT) {
+    buf[l * L] = Cx<R>{0, 0};
+    buf[l * L + N] = Cx<R>{0, 0};
+  }
+  __syncthreads();
+}
+
+template <typename R, int U, class Pre, class Post>
+__device__ void lines_store2(const Cx<R> *buf, const LineTile &t, Pre &&pre, Post &&post) {
+  using PT = decltype(pre(0));
+  const int tid = threadIdx.x;
+  const int L = 1 << t.lg;
+  const R c = (R)1 / sqrt((R)L);
+  const int total = tile_elems(t);
+  for (int e0 = 0; e0 < total; e0 += NT * U) {
+    PT pv[U];
+    Cx<R> vv[U];
+    int pp[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * NT + tid;
+      pp[u] = -1;
+      int l, r;
+      if (e < total && split_elem(t, e, l, r)) {
+        pp[u] = t.base + l * t.lstride + r * t.stride;
+        pv[u] = pre(pp[u]);
+        vv[u] = dst_out(buf[l * L + r + 1], c);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (pp[u] >= 0) post(pp[u], vv[u], pv[u]);
+    }
+  }
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
-// Stencil: (K u)_p with harmonic-mean face coefficients, boundary faces
-// carrying a_p, u = 0 outside the grid.
+// Stencil: (K u)_p = sum over the 2d faces e of p of c_e (u_p - u_nbr(e)) / h^2
+// with u = 0 outside the grid.  F[ax] holds c_e / h_ax^2 for every face of
+// axis ax (harmonic means of neighbouring nodal samples inside, the adjacent
+// sample on the boundary), in an array with n_ax + 1 entries along ax.
 // ---------------------------------------------------------------------------
 template <int D>
-__device__ __forceinline__ double2 stencil_K(const SysDesc &S, const double *__restrict__ a,
-                                             const double2 *__restrict__ u, int p,
-                                             const int (&idx)[3]) {
-  const double ap = a[p];
-  const double2 up = u[p];
-  double rx = 0.0, ry = 0.0;
+struct StencilIn {
+  double2 c;          // u_p
+  double2 b[D], a[D]; // neighbours below / above along each axis (0 outside)
+  double fb[D], fa[D];
+};
+
+template <int D>
+__device__ __forceinline__ StencilIn<D> stencil_load(const SysDesc &S,
+                                                     const double2 *__restrict__ u, int p,
+                                                     const int (&idx)[3]) {
+  StencilIn<D> in;
+  in.c = u[p];
 #pragma unroll
   for (int ax = 0; ax < D; ++ax) {
     const int st = S.st[ax];
-    double csum = 0.0, nx = 0.0, ny = 0.0;
-    if (idx[ax] > 0) {
-      const double aq = a[p - st];
-      const double c = 2.0 * ap * aq / (ap + aq);
-      const double2 q = u[p - st];
-      nx += c * q.x;
-      ny += c * q.y;
-      csum += c;
-    } else {
-      csum += ap;
-    }
-    if (idx[ax] < S.n[ax] - 1) {
-      const double aq = a[p + st];
-      const double c = 2.0 * ap * aq / (ap + aq);
-      const double2 q = u[p + st];
-      nx += c * q.x;
-      ny += c * q.y;
-      csum += c;
-    } else {
-      csum += ap;
-    }
-    rx += S.h2[ax] * (csum * up.x - nx);
-    ry += S.h2[ax] * (csum * up.y - ny);
+    int fi = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) fi += idx[k] * S.fst[ax][k];
+    in.fb[ax] = S.F[ax][fi];
+    in.fa[ax] = S.F[ax][fi + S.fst[ax][ax]];
+    in.b[ax] = idx[ax] > 0 ? u[p - st] : make_double2(0.0, 0.0);
+    in.a[ax] = idx[ax] < S.n[ax] - 1 ? u[p + st] : make_double2(0.0, 0.0);
+  }
+  return in;
+}
+
+template <int D>
+__device__ __forceinline__ double2 stencil_apply(const StencilIn<D> &in) {
+  double rx = 0.0, ry = 0.0;
+#pragma unroll
+  for (int ax = 0; ax < D; ++ax) {
+    rx += in.fb[ax] * (in.c.x - in.b[ax].x) + in.fa[ax] * (in.c.x - in.a[ax].x);
+    ry += in.fb[ax] * (in.c.y - in.b[ax].y) + in.fa[ax] * (in.c.y - in.a[ax].y);
   }
   return make_double2(rx, ry);
+}
+
+template <int D>
+__device__ __forceinline__ double2 stencil_K(const SysDesc &S, const double2 *__restrict__ u,
+                                             int p, const int (&idx)[3]) {
+  return stencil_apply<D>(stencil_load<D>(S, u, p, idx));
 }
 
 // Multi-index of element r of contiguous-axis row `row`.
@@ -330,17 +416,17 @@ __device__ __forceinline__ void row_index(const SysDesc &S, int row, int r, int 
   }
 }
 
-// Workgroup sum in a fixed order (bitwise reproducible).
+// Workgroup sum in a fixed order (bitwise reproducible): butterfly
+// reduction inside each wave, then the NT/64 wave sums in order.
 __device__ __forceinline__ double wg_sum(double v, double *red) {
   const int tid = threadIdx.x;
-  red[tid] = v;
-  __syncthreads();
 #pragma unroll
-  for (int s = NT / 2; s > 0; s >>= 1) {
-    if (tid < s) red[tid] += red[tid + s];
-    __syncthreads();
-  }
-  const double r = red[0];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  double r = red[0];
+#pragma unroll
+  for (int w = 1; w < NT / 64; ++w) r += red[w];
   __syncthreads();
   return r;
 }

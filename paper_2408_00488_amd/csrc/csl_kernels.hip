@@ -15,79 +15,288 @@ __device__ __forceinline__ Cx<R> to_cx(double2 v) {
 }
 
 // ---------------------------------------------------------------------------
-// One tile of a sine-transform pass.
-//   MINRES mode (STANDALONE = false):
-//     K_RF  iter 0: source f (also ||f||^2 partial, zero the output x)
-//     K_RF  iter j: source v_{j+1} = A zhat_j - (delta_j/gamma_j) v_j
-//                   - (gamma_j/gamma_{j-1}) v_{j-1}, written to V[(j+1)&1]
-//     K_F1, K_MID, K_I1: T -> T
-//     K_RI  iter j: T -> z_{j+1} in Z[(j+1)&1] and the partial <z_{j+1}, v_{j+1}>
-//   Stand-alone P^{-1} (STANDALONE = true): first pass reads x, last writes y.
-// The transform of every pass is the orthonormal DST-I (its own inverse);
-// K_MID applies forward transform, per-mode factor, inverse transform.
+// K_X, rows of the contiguous axis, always FP64 (it transforms Lanczos
+// vectors, not preconditioner data).
+//   iter 0: Tv_1 = W_c f; partial ||f||^2; zero the output x.
+//   iter j: q = A zhat_j = conj(K zhat_j + conj(lambda) zhat_j) (complex
+//           storage of the block product), partial delta_j = <zhat_j, q>,
+//           Tq = W_c q.
 // ---------------------------------------------------------------------------
-template <typename R, int D, bool STANDALONE>
-__device__ void tile_line(const SysDesc &S, const IOPtr &io, int kind, int iter, int tile,
-                          char *smem, double *red) {
-  Cx<R> *buf = reinterpret_cast<Cx<R> *>(smem);
-  const int ax = (kind == K_RF || kind == K_RI) ? D - 1 : (kind == K_MID ? 0 : 1);
-  const LineTile t = line_tile(S, ax, tile);
-  Cx<R> *T = reinterpret_cast<Cx<R> *>(S.T);
+template <int D, int LDSB>
+__device__ void tile_X(const SysDesc &S, const IOPtr &io, int iter, int tile, char *smem,
+                       double *red) {
+  Cx<double> *buf = reinterpret_cast<Cx<double> *>(smem);
   double acc = 0.0;
+  const int c1 = min(S.nchunk[K_X], (tile + 1) * S.cpt[K_X]);
+  for (int chunk = tile * S.cpt[K_X]; chunk < c1; ++chunk) {
+    const LineTile t = line_tile(S, D - 1, S.lpt_x, chunk);
+    Cx<double> *out;
+    if (iter == 0) {
+      const double2 *__restrict__ f = io.f;
+      double2 *__restrict__ X = io.x;
+      lines_fill<double>(buf, t, [&](int, int, int p) {
+        const double2 v = f[p];
+        acc += v.x * v.x + v.y * v.y;
+        X[p] = make_double2(0.0, 0.0);
+        return Cx<double>{v.x, v.y};
+      });
+      out = reinterpret_cast<Cx<double> *>(S.Tv[1]);
+    } else {
+      const double2 *__restrict__ zj = S.Z[iter & 1];
+      const double al = S.alpha, be = S.beta;
+      lines_fill2<double, 2>(
+          buf, t,
+          [&](int l, int r, int p) {
+            int idx[3];
+            row_index<D>(S, t.row0 + l, r, idx);
+            return stencil_load<D>(S, zj, p, idx);
+          },
+          [&](int, int, int, const StencilIn<D> &in) {
+            const double2 kz = stencil_apply<D>(in);
+            const double2 zz = in.c;
+            const double qx = kz.x + al * zz.x + be * zz.y;
+            const double qy = -(kz.y + al * zz.y - be * zz.x);
+            acc += zz.x * qx + zz.y * qy;
+            return Cx<double>{qx, qy};
+          });
+      out = reinterpret_cast<Cx<double> *>(S.Tq);
+    }
+    fft_lines<double, LDSB>(buf, t.nl, t.lg);
+    lines_store<double>(buf, t, [&](int, int, int p, Cx<double> v) { out[p] = v; });
+  }
+  const double s = wg_sum(acc, red);
+  if (threadIdx.x == 0) S.part[tile] = s;
+}
 
-  // ---------------- fill
-  if (kind == K_RF && STANDALONE) {
-    const double2 *__restrict__ x = io.f;
-    lines_fill<R>(buf, t, [&](int, int, int p) { return to_cx<R>(x[p]); });
-  } else if (kind == K_RF && iter == 0) {
-    const double2 *__restrict__ f = io.f;
-    double2 *__restrict__ X = io.x;
-    lines_fill<R>(buf, t, [&](int, int, int p) {
-      const double2 v = f[p];
-      acc += v.x * v.x + v.y * v.y;
-      X[p] = make_double2(0.0, 0.0);
-      return to_cx<R>(v);
-    });
-  } else if (kind == K_RF) {
-    const int j = iter;
-    const Ctl *C = S.ctl;
-    const double g = ld_ctl(&C->gamma), go = ld_ctl(&C->gamma_old);
-    const double dl = ld_ctl(&C->delta);
-    const double ig = 1.0 / g, cd = dl / g, cg = g / go;
-    const double al = S.alpha, be = S.beta;
-    const double2 *__restrict__ zj = S.Z[j & 1];
-    const double2 *__restrict__ vj = (j == 1) ? io.f : S.V[j & 1];
-    const double2 *__restrict__ vjm1 = (j == 2) ? io.f : S.V[(j - 1) & 1];
-    double2 *vout = S.V[(j + 1) & 1];
-    const bool has_vm1 = j >= 2;
-    const double *__restrict__ a = S.a;
-    lines_fill<R>(buf, t, [&](int l, int r, int p) {
-      int idx[3];
-      row_index<D>(S, t.row0 + l, r, idx);
-      const double2 kz = stencil_K<D>(S, a, zj, p, idx);
-      const double2 zz = zj[p];
-      const double zx = zz.x * ig, zy = zz.y * ig;
-      const double kx = kz.x * ig, ky = kz.y * ig;
-      // q = A zhat in complex storage = conj(K zhat + conj(lambda) zhat)
-      const double qx = kx + al * zx + be * zy;
-      const double qy = -(ky + al * zy - be * zx);
-      const double2 v1 = vj[p];
-      double vx = qx - cd * v1.x, vy = qy - cd * v1.y;
-      if (has_vm1) {
-        const double2 v0 = vjm1[p];
-        vx -= cg * v0.x;
-        vy -= cg * v0.y;
-      }
-      vout[p] = make_double2(vx, vy);
-      return Cx<R>{(R)vx, (R)vy};
-    });
+// ---------------------------------------------------------------------------
+// Strided passes (columns), preconditioner precision R.
+//   First strided pass (2-D K_Y, 3-D K_Y1): input is the new Lanczos vector
+//     Tv_{j+1} = Tq - (delta_j/gamma_j) Tv_j - (gamma_j/gamma_{j-1}) Tv_{j-1}
+//     (FP64, stored), or Tv_1 at iteration 0.
+//   K_Y: forward transform along axis 0, per-mode factor, inverse transform.
+//   Last strided pass (2-D K_Y, 3-D K_Y1I): output T' and the partial of
+//     gamma_{j+1}^2 = <z_{j+1}, v_{j+1}> = <T', Tv_{j+1}> (W_c orthogonal).
+// ---------------------------------------------------------------------------
+template <typename R, int D, int LDSB>
+__device__ void tile_Y(const SysDesc &S, int kind, int iter, int tile, char *smem, double *red) {
+  Cx<R> *buf = reinterpret_cast<Cx<R> *>(smem);
+  const int ax = (kind == K_Y) ? 0 : 1;
+  Cx<R> *T = reinterpret_cast<Cx<R> *>(S.T);
+  const bool first = (kind == K_Y1) || (D == 2);
+  const int j = iter;
+  double gacc = 0.0;
+  const int c1 = min(S.nchunk[kind], (tile + 1) * S.cpt[kind]);
+  for (int chunk = tile * S.cpt[kind]; chunk < c1; ++chunk) {
+  const LineTile t = line_tile(S, ax, S.lpt_s[ax], chunk);
+  if (first) {
+    if (j == 0) {
+      const double2 *__restrict__ v1 = S.Tv[1];
+      lines_fill<R>(buf, t, [&](int, int, int p) { return to_cx<R>(v1[p]); });
+    } else {
+      const Ctl *C = S.ctl;
+      const double g = ld_ctl(&C->gamma), go = ld_ctl(&C->gamma_old);
+      const double dl = ld_ctl(&C->delta);
+      const double cd = dl / g, cg = g / go;
+      const double2 *__restrict__ tq = S.Tq;
+      const double2 *__restrict__ vj = S.Tv[j & 1];
+      double2 *__restrict__ vout = S.Tv[(j + 1) & 1];   // holds Tv_{j-1}
+      const bool has_vm1 = j >= 2;
+      struct In3 {
+        double2 q, v1, v0;
+      };
+      lines_fill2<R, 4>(
+          buf, t,
+          [&](int, int, int p) {
+            In3 in;
+            in.q = tq[p];
+            in.v1 = vj[p];
+            in.v0 = has_vm1 ? vout[p] : make_double2(0.0, 0.0);
+            return in;
+          },
+          [&](int, int, int p, const In3 &in) {
+            const double vx = in.q.x - cd * in.v1.x - cg * in.v0.x;
+            const double vy = in.q.y - cd * in.v1.y - cg * in.v0.y;
+            vout[p] = make_double2(vx, vy);
+            return Cx<R>{(R)vx, (R)vy};
+          });
+    }
   } else {
     lines_fill<R>(buf, t, [&](int, int, int p) { return T[p]; });
   }
+  fft_lines<R, LDSB>(buf, t.nl, t.lg);
+  if (kind == K_Y) {
+    const R ab = (sizeof(R) == 8) ? (R)S.abar : (R)S.abar_f;
+    const R al = (sizeof(R) == 8) ? (R)S.alpha : (R)S.alpha_f;
+    const R be = (sizeof(R) == 8) ? (R)S.beta : (R)S.beta_f;
+    const R *mu0;
+    const R *mu1;
+    const R *mu2;
+    if constexpr (sizeof(R) == 8) {
+      mu0 = reinterpret_cast<const R *>(S.mu[0]);
+      mu1 = reinterpret_cast<const R *>(S.mu[1]);
+      mu2 = reinterpret_cast<const R *>(S.mu[2]);
+    } else {
+      mu0 = reinterpret_cast<const R *>(S.mu_f[0]);
+      mu1 = reinterpret_cast<const R *>(S.mu_f[1]);
+      mu2 = reinterpret_cast<const R *>(S.mu_f[2]);
+    }
+    // gamma_{j+1}^2 = <P^{-1} v, v> = sum_k s_k |(W v)_k|^2: here W v is the
+    // fully transformed Lanczos vector, so its partial comes from this pass.
+    gacc += lines_scale_extend<R>(buf, t, [&](int l, int r) -> R {
+      R lam;
+      if (D == 2) {
+        lam = mu0[r] + mu1[t.c0 + l];
+      } else {
+        lam = (mu0[r] + mu1[t.outer]) + mu2[t.c0 + l];
+      }
+      const R sh = ab * lam + al;
+      return (R)1 / sqrt(sh * sh + be * be);
+    });
+    fft_lines<R, LDSB>(buf, t.nl, t.lg);
+  }
+  lines_store<R>(buf, t, [&](int, int, int p, Cx<R> v) { T[p] = v; });
+  }
+  if (kind == K_Y) {
+    const double sg = wg_sum(gacc, red);
+    if (threadIdx.x == 0) S.part[tile] = sg;
+  }
+}
 
-  fft_lines<R>(buf, t.nl, t.lg);
+// ---------------------------------------------------------------------------
+// K_Z, rows of the contiguous axis, precision R: z_{j+1} = W_c T',
+// zhat_{j+1} = z_{j+1} / gamma_{j+1}; then the update of step j (j >= 1):
+//   w_{j+1} = (zhat_j - e3 w_{j-1} - e2 w_j) / e1,  x_j = x_{j-1} + ceta w_{j+1}
+// with x held as its conjugate (the user's z).
+// ---------------------------------------------------------------------------
+template <typename R, int D, int LDSB>
+__device__ void tile_Z(const SysDesc &S, const IOPtr &io, int iter, int tile, char *smem) {
+  Cx<R> *buf = reinterpret_cast<Cx<R> *>(smem);
+  const int c1 = min(S.nchunk[K_Z], (tile + 1) * S.cpt[K_Z]);
+  for (int chunk = tile * S.cpt[K_Z]; chunk < c1; ++chunk) {
+  const LineTile t = line_tile(S, D - 1, S.lpt_z, chunk);
+  const Cx<R> *T = reinterpret_cast<const Cx<R> *>(S.T);
+  const int j = iter;
+  const Ctl *C = S.ctl;
+  const double g = ld_ctl(&C->gamma);
+  const bool store_z = (g != 0.0);
+  const double ig = store_z ? 1.0 / g : 0.0;
+  double2 *__restrict__ znew = S.Z[(j + 1) & 1];
+  lines_fill<R, 8>(buf, t, [&](int, int, int p) { return T[p]; });
+  fft_lines<R, LDSB>(buf, t.nl, t.lg);
+  if (j == 0) {
+    lines_store<R>(buf, t, [&](int, int, int p, Cx<R> v) {
+      znew[p] = make_double2((double)v.x * ig, (double)v.y * ig);
+    });
+    continue;
+  }
+  const double e1 = ld_ctl(&C->e1), e2 = ld_ctl(&C->e2), e3 = ld_ctl(&C->e3);
+  const double ceta = ld_ctl(&C->ceta);
+  const double2 *__restrict__ zj = S.Z[j & 1];
+  double2 *__restrict__ wnew = S.W[(j + 1) & 1];   // holds w_{j-1} before the update
+  const double2 *__restrict__ wj = S.W[j & 1];
+  double2 *__restrict__ X = io.x;
+  const bool use_wm1 = j > 2, use_wj = j > 1, use_x = j > 1;
+  struct In4 {
+    double2 z, w0, w1, x;
+  };
+  lines_store2<R, 4>(
+      buf, t,
+      [&](int p) {
+        In4 in;
+        in.z = zj[p];
+        in.w0 = use_wm1 ? wnew[p] : make_double2(0.0, 0.0);
+        in.w1 = use_wj ? wj[p] : make_double2(0.0, 0.0);
+        in.x = use_x ? X[p] : make_double2(0.0, 0.0);
+        return in;
+      },
+      [&](int p, Cx<R> v, const In4 &in) {
+        if (store_z) znew[p] = make_double2((double)v.x * ig, (double)v.y * ig);
+        const double wx = (in.z.x - e3 * in.w0.x - e2 * in.w1.x) / e1;
+        const double wy = (in.z.y - e3 * in.w0.y - e2 * in.w1.y) / e1;
+        wnew[p] = make_double2(wx, wy);
+        X[p] = make_double2(in.x.x + ceta * wx, in.x.y - ceta * wy);
+      });
+  }
+}
 
-  if (kind == K_MID) {
+// True residual partial ||f - (K + lambda I) z||^2 with z the user output.
+template <int D>
+__device__ void tile_PR(const SysDesc &S, const IOPtr &io, int tile, double *red) {
+  const int nlast = S.n[D - 1];
+  const int r0 = tile * S.cpt[K_PR] * S.rpt;
+  const int r1 = min(S.rows, r0 + S.cpt[K_PR] * S.rpt);
+  const int p0 = r0 * nlast, p1 = r1 * nlast;
+  const double2 *__restrict__ X = io.x;
+  const double2 *__restrict__ f = io.f;
+  const double al = S.alpha, be = S.beta;
+  double acc = 0.0;
+  for (int p = p0 + (int)threadIdx.x; p < p1; p += NT) {
+    const int row = p / nlast;
+    int idx[3];
+    row_index<D>(S, row, p - row * nlast, idx);
+    const double2 kx = stencil_K<D>(S, X, p, idx);
+    const double2 xv = X[p];
+    const double ux = kx.x + al * xv.x - be * xv.y;
+    const double uy = kx.y + al * xv.y + be * xv.x;
+    const double2 fv = f[p];
+    const double rx = fv.x - ux, ry = fv.y - uy;
+    acc += rx * rx + ry * ry;
+  }
+  const double s = wg_sum(acc, red);
+  if (threadIdx.x == 0) S.part[tile] = s;
+}
+
+template <int LDSB>
+__device__ void process_tile(const SysDesc &S, const IOPtr &io, int kind, int iter, int tile,
+                             char *smem, double *red) {
+  const bool d3 = (S.d == 3);
+  switch (kind) {
+    case K_X:
+      if (d3) tile_X<3, LDSB>(S, io, iter, tile, smem, red);
+      else tile_X<2, LDSB>(S, io, iter, tile, smem, red);
+      break;
+    case K_Z:
+      if (S.prec) {
+        if (d3) tile_Z<float, 3, LDSB>(S, io, iter, tile, smem);
+        else tile_Z<float, 2, LDSB>(S, io, iter, tile, smem);
+      } else {
+        if (d3) tile_Z<double, 3, LDSB>(S, io, iter, tile, smem);
+        else tile_Z<double, 2, LDSB>(S, io, iter, tile, smem);
+      }
+      break;
+    case K_PR:
+      if (d3) tile_PR<3>(S, io, tile, red);
+      else tile_PR<2>(S, io, tile, red);
+      break;
+    default:
+      if (S.prec) {
+        if (d3) tile_Y<float, 3, LDSB>(S, kind, iter, tile, smem, red);
+        else tile_Y<float, 2, LDSB>(S, kind, iter, tile, smem, red);
+      } else {
+        if (d3) tile_Y<double, 3, LDSB>(S, kind, iter, tile, smem, red);
+        else tile_Y<double, 2, LDSB>(S, kind, iter, tile, smem, red);
+      }
+      break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Stand-alone P^{-1}: rows forward (x -> T), strided passes, rows inverse
+// (T -> y), all in the preconditioner precision R.
+// ---------------------------------------------------------------------------
+template <typename R, int D, int LDSB>
+__device__ void tile_pinv(const SysDesc &S, int pass, const double2 *x, double2 *y, int tile,
+                          char *smem) {
+  Cx<R> *buf = reinterpret_cast<Cx<R> *>(smem);
+  Cx<R> *T = reinterpret_cast<Cx<R> *>(S.T);
+  // pass: 0 rows forward, 1 axis-1 forward, 2 axis-0 mid, 3 axis-1 inverse, 4 rows inverse
+  const int ax = (pass == 0 || pass == 4) ? D - 1 : (pass == 2 ? 0 : 1);
+  const int lp = (ax == D - 1) ? S.lpt_z : S.lpt_s[ax];
+  const LineTile t = line_tile(S, ax, lp, tile);
+  if (pass == 0) lines_fill<R>(buf, t, [&](int, int, int p) { return to_cx<R>(x[p]); });
+  else lines_fill<R>(buf, t, [&](int, int, int p) { return T[p]; });
+  fft_lines<R, LDSB>(buf, t.nl, t.lg);
+  if (pass == 2) {
     const R ab = (sizeof(R) == 8) ? (R)S.abar : (R)S.abar_f;
     const R al = (sizeof(R) == 8) ? (R)S.alpha : (R)S.alpha_f;
     const R be = (sizeof(R) == 8) ? (R)S.beta : (R)S.beta_f;
@@ -113,143 +322,14 @@ __device__ void tile_line(const SysDesc &S, const IOPtr &io, int kind, int iter,
       const R sh = ab * lam + al;
       return (R)1 / sqrt(sh * sh + be * be);
     });
-    fft_lines<R>(buf, t.nl, t.lg);
+    fft_lines<R, LDSB>(buf, t.nl, t.lg);
   }
-
-  // ---------------- store
-  if (kind == K_RI && STANDALONE) {
-    double2 *__restrict__ y = io.x;
+  if (pass == 4) {
     lines_store<R>(buf, t, [&](int, int, int p, Cx<R> v) {
       y[p] = make_double2((double)v.x, (double)v.y);
     });
-  } else if (kind == K_RI) {
-    const int j = iter;
-    double2 *__restrict__ zout = S.Z[(j + 1) & 1];
-    const double2 *__restrict__ partner = (j == 0) ? io.f : S.V[(j + 1) & 1];
-    lines_store<R>(buf, t, [&](int, int, int p, Cx<R> v) {
-      const double2 z = make_double2((double)v.x, (double)v.y);
-      zout[p] = z;
-      const double2 w = partner[p];
-      acc += z.x * w.x + z.y * w.y;
-    });
   } else {
     lines_store<R>(buf, t, [&](int, int, int p, Cx<R> v) { T[p] = v; });
-  }
-  if (!STANDALONE && (kind == K_RI || (kind == K_RF && iter == 0))) {
-    const double s = wg_sum(acc, red);
-    if (threadIdx.x == 0) S.part[tile] = s;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Pointwise phase PA of iteration j: apply the pending update of step j-1
-//   w_j = (zhat_{j-1} - e3 w_{j-2} - e2 w_{j-1}) / e1,  x_{j-1} = x_{j-2} + ceta w_j
-// (x held as its conjugate, the user's z), and the partial of
-// delta_j = <zhat_j, A zhat_j>.
-// ---------------------------------------------------------------------------
-template <int D>
-__device__ void tile_PA(const SysDesc &S, const IOPtr &io, int j, int tile, double *red) {
-  const Ctl *C = S.ctl;
-  const int upd = ld_ctl(&C->has_update);
-  const double g = ld_ctl(&C->gamma), go = ld_ctl(&C->gamma_old);
-  const double e1 = ld_ctl(&C->e1), e2 = ld_ctl(&C->e2), e3 = ld_ctl(&C->e3);
-  const double ceta = ld_ctl(&C->ceta);
-  const int nlast = S.n[D - 1];
-  const int r0 = tile * S.rpt;
-  const int r1 = min(S.rows, r0 + S.rpt);
-  const int p0 = r0 * nlast, p1 = r1 * nlast;
-  const double2 *__restrict__ zj = S.Z[j & 1];
-  const double2 *__restrict__ zjm1 = S.Z[(j - 1) & 1];
-  double2 *wnew = S.W[j & 1];
-  const double2 *__restrict__ wjm1 = S.W[(j - 1) & 1];
-  double2 *__restrict__ X = io.x;
-  const bool use_wm2 = j > 3, use_wm1 = j > 2, use_x = j > 2;
-  const bool do_delta = (g != 0.0);
-  const double igo = 1.0 / go;
-  const double ig = do_delta ? 1.0 / g : 0.0;
-  const double al = S.alpha, be = S.beta;
-  const double *__restrict__ a = S.a;
-  double acc = 0.0;
-  for (int p = p0 + (int)threadIdx.x; p < p1; p += NT) {
-    if (upd) {
-      const double2 zz = zjm1[p];
-      double wx = zz.x * igo, wy = zz.y * igo;
-      if (use_wm2) {
-        const double2 w0 = wnew[p];
-        wx -= e3 * w0.x;
-        wy -= e3 * w0.y;
-      }
-      if (use_wm1) {
-        const double2 w1 = wjm1[p];
-        wx -= e2 * w1.x;
-        wy -= e2 * w1.y;
-      }
-      wx /= e1;
-      wy /= e1;
-      wnew[p] = make_double2(wx, wy);
-      double2 xv = use_x ? X[p] : make_double2(0.0, 0.0);
-      xv.x += ceta * wx;
-      xv.y -= ceta * wy;
-      X[p] = xv;
-    }
-    if (do_delta) {
-      const int row = p / nlast;
-      int idx[3];
-      row_index<D>(S, row, p - row * nlast, idx);
-      const double2 kz = stencil_K<D>(S, a, zj, p, idx);
-      const double2 zz = zj[p];
-      const double zx = zz.x * ig, zy = zz.y * ig;
-      const double kx = kz.x * ig, ky = kz.y * ig;
-      const double qx = kx + al * zx + be * zy;
-      const double qy = -(ky + al * zy - be * zx);
-      acc += zx * qx + zy * qy;
-    }
-  }
-  const double s = wg_sum(acc, red);
-  if (threadIdx.x == 0) S.part[tile] = s;
-}
-
-// True residual partial ||f - (K + lambda I) z||^2 with z the user output.
-template <int D>
-__device__ void tile_PR(const SysDesc &S, const IOPtr &io, int tile, double *red) {
-  const int nlast = S.n[D - 1];
-  const int r0 = tile * S.rpt;
-  const int r1 = min(S.rows, r0 + S.rpt);
-  const int p0 = r0 * nlast, p1 = r1 * nlast;
-  const double2 *__restrict__ X = io.x;
-  const double2 *__restrict__ f = io.f;
-  const double al = S.alpha, be = S.beta;
-  double acc = 0.0;
-  for (int p = p0 + (int)threadIdx.x; p < p1; p += NT) {
-    const int row = p / nlast;
-    int idx[3];
-    row_index<D>(S, row, p - row * nlast, idx);
-    const double2 kx = stencil_K<D>(S, S.a, X, p, idx);
-    const double2 xv = X[p];
-    const double ux = kx.x + al * xv.x - be * xv.y;
-    const double uy = kx.y + al * xv.y + be * xv.x;
-    const double2 fv = f[p];
-    const double rx = fv.x - ux, ry = fv.y - uy;
-    acc += rx * rx + ry * ry;
-  }
-  const double s = wg_sum(acc, red);
-  if (threadIdx.x == 0) S.part[tile] = s;
-}
-
-__device__ void process_tile(const SysDesc &S, const IOPtr &io, int kind, int iter, int tile,
-                             char *smem, double *red) {
-  if (kind == K_PA) {
-    if (S.d == 3) tile_PA<3>(S, io, iter, tile, red);
-    else tile_PA<2>(S, io, iter, tile, red);
-  } else if (kind == K_PR) {
-    if (S.d == 3) tile_PR<3>(S, io, tile, red);
-    else tile_PR<2>(S, io, tile, red);
-  } else if (S.prec) {
-    if (S.d == 3) tile_line<float, 3, false>(S, io, kind, iter, tile, smem, red);
-    else tile_line<float, 2, false>(S, io, kind, iter, tile, smem, red);
-  } else {
-    if (S.d == 3) tile_line<double, 3, false>(S, io, kind, iter, tile, smem, red);
-    else tile_line<double, 2, false>(S, io, kind, iter, tile, smem, red);
   }
 }
 
@@ -282,139 +362,132 @@ enum { ST_OK = 0, ST_NOT_CONVERGED = 3, ST_BREAKDOWN = 4, ST_NONFINITE = 5 };
 __device__ void epilogue(const SysDesc &S, const SolveParams &P, int kind, int iter, Glob *G,
                          double *red) {
   const int nt = S.ntile[kind];
+  const bool last_strided = (kind == K_Y);   // carries the gamma^2 partials
+  const bool need_sum = (kind == K_X) || (kind == K_PR) || last_strided;
   double a = 0.0;
-  const bool need_sum = (kind == K_RI || kind == K_PA || kind == K_PR || (kind == K_RF && iter == 0));
   if (need_sum) {
     for (int i = threadIdx.x; i < nt; i += NT) a += S.part[i];
   }
   const double sum = need_sum ? wg_sum(a, red) : 0.0;
   if (threadIdx.x != 0) return;
   Ctl *C = S.ctl;
-  const int first_mid = (S.d == 3) ? K_F1 : K_MID;
   const double nan = __longlong_as_double(0x7ff8000000000000ll);
-  switch (kind) {
-    case K_RF:
-      if (iter == 0) {
-        const double bn = sqrt(sum);
-        C->bnorm = bn;
-        if (!isfinite(bn)) {
-          S.info->relres_est = nan;
-          finish(S, G, iter, ST_NONFINITE, 0, nan);
-        } else if (bn == 0.0) {
-          S.info->relres_est = 0.0;
-          finish(S, G, iter, ST_OK, 0, 0.0);
-        } else {
-          publish(C, iter, first_mid);
-        }
-      } else {
-        publish(C, iter, first_mid);
-      }
-      break;
-    case K_F1:
-      publish(C, iter, K_MID);
-      break;
-    case K_MID:
-      publish(C, iter, S.d == 3 ? K_I1 : K_RI);
-      break;
-    case K_I1:
-      publish(C, iter, K_RI);
-      break;
-    case K_RI: {
-      const double g2 = sum;
-      const int done_iters = iter > 0 ? iter - 1 : 0;
-      if (!isfinite(g2)) {
+  const int first_strided = (S.d == 3) ? K_Y1 : K_Y;
+  if (kind == K_X) {
+    if (iter == 0) {
+      const double bn = sqrt(sum);
+      C->bnorm = bn;
+      if (!isfinite(bn)) {
         S.info->relres_est = nan;
-        finish(S, G, iter, ST_NONFINITE, done_iters, nan);
-        break;
-      }
-      if (iter == 0) {
-        if (g2 <= 0.0) {
-          S.info->relres_est = nan;
-          finish(S, G, iter, ST_BREAKDOWN, 0, nan);
-          break;
-        }
-        const double g = sqrt(g2);
-        C->gamma = g;
-        C->gamma_old = 1.0;
-        C->eta = g;
-        C->eta0 = g;
-        C->c = 1.0;
-        C->c_old = 1.0;
-        C->s = 0.0;
-        C->s_old = 0.0;
-        C->has_update = 0;
-        publish(C, 1, K_PA);
+        finish(S, G, iter, ST_NONFINITE, 0, nan);
+      } else if (bn == 0.0) {
+        S.info->relres_est = 0.0;
+        finish(S, G, iter, ST_OK, 0, 0.0);
       } else {
-        if (g2 < 0.0) {
-          finish(S, G, iter, ST_BREAKDOWN, done_iters, nan);
-          break;
-        }
-        const double gn = sqrt(g2);
-        const double dl = C->delta, g = C->gamma;
-        const double c = C->c, co = C->c_old, s = C->s, so = C->s_old, eta = C->eta;
-        const double e0 = c * dl - co * s * g;
-        const double e1 = hypot(e0, gn);
-        const double e2 = s * dl + co * c * g;
-        const double e3 = so * g;
-        const double cn = e0 / e1, sn = gn / e1;
-        C->e1 = e1;
-        C->e2 = e2;
-        C->e3 = e3;
-        C->ceta = cn * eta;
-        C->eta = -sn * eta;
-        C->has_update = 1;
-        C->c_old = c;
-        C->c = cn;
-        C->s_old = s;
-        C->s = sn;
-        C->gamma_old = g;
-        C->gamma = gn;
-        publish(C, iter + 1, K_PA);
+        publish(C, 0, first_strided);
       }
-      break;
-    }
-    case K_PA: {
+    } else if (!isfinite(sum)) {
+      finish(S, G, iter, ST_NONFINITE, iter - 1, nan);
+    } else {
       C->delta = sum;
-      if (!C->has_update) {
-        publish(C, iter, K_RF);
-        break;
-      }
-      const int k = iter - 1;
-      const double est = fabs(C->eta) / C->eta0;
-      S.info->relres_est = est;
-      const bool lucky = (C->gamma == 0.0);
-      if (!lucky && !isfinite(sum)) {
-        finish(S, G, iter, ST_NONFINITE, k, nan);
-      } else if (lucky) {
-        C->finishing = ST_OK;
-        publish(C, iter, K_PR);
-      } else if (est <= P.tol) {
-        C->finishing = P.check_true ? -1 : ST_OK;
-        publish(C, iter, K_PR);
-      } else if (k >= P.maxit) {
-        C->finishing = ST_NOT_CONVERGED;
-        publish(C, iter, K_PR);
-      } else {
-        publish(C, iter, K_RF);
-      }
-      break;
+      publish(C, iter, first_strided);
     }
-    case K_PR: {
-      const int k = iter - 1;
-      const double rt = sqrt(sum) / C->bnorm;
-      if (C->finishing >= 0) {
-        finish(S, G, iter, C->finishing, k, rt);
-      } else if (rt <= P.tol) {
-        finish(S, G, iter, ST_OK, k, rt);
-      } else if (k >= P.maxit) {
-        finish(S, G, iter, ST_NOT_CONVERGED, k, rt);
-      } else {
-        publish(C, iter, K_RF);
-      }
-      break;
+    return;
+  }
+  if (kind == K_Y1) {
+    publish(C, iter, K_Y);
+    return;
+  }
+  if (kind == K_Y1I) {
+    publish(C, iter, K_Z);
+    return;
+  }
+  if (last_strided) {
+    const double g2 = sum;
+    if (!isfinite(g2)) {
+      S.info->relres_est = nan;
+      finish(S, G, iter, ST_NONFINITE, iter > 0 ? iter - 1 : 0, nan);
+      return;
     }
-    default:
-      break;
+    if (iter == 0) {
+      if (g2 <= 0.0) {
+        S.info->relres_est = nan;
+        finish(S, G, iter, ST_BREAKDOWN, 0, nan);
+        return;
+      }
+      const double g = sqrt(g2);
+      C->gamma = g;
+      C->gamma_old = 1.0;
+      C->eta = g;
+      C->eta0 = g;
+      C->c = 1.0;
+      C->c_old = 1.0;
+      C->s = 0.0;
+      C->s_old = 0.0;
+      C->after_z = 0;
+      publish(C, 0, S.d == 3 ? K_Y1I : K_Z);
+      return;
+    }
+    if (g2 < 0.0) {
+      finish(S, G, iter, ST_BREAKDOWN, iter - 1, nan);
+      return;
+    }
+    // Givens rotations of column j of the Lanczos tridiagonal (step j)
+    const double gn = sqrt(g2);
+    const double dl = C->delta, g = C->gamma;
+    const double c = C->c, co = C->c_old, s = C->s, so = C->s_old, eta = C->eta;
+    const double e0 = c * dl - co * s * g;
+    const double e1 = hypot(e0, gn);
+    const double e2 = s * dl + co * c * g;
+    const double e3 = so * g;
+    const double cn = e0 / e1, sn = gn / e1;
+    C->e1 = e1;
+    C->e2 = e2;
+    C->e3 = e3;
+    C->ceta = cn * eta;
+    C->eta = -sn * eta;
+    C->c_old = c;
+    C->c = cn;
+    C->s_old = s;
+    C->s = sn;
+    C->gamma_old = g;
+    C->gamma = gn;
+    // decide what follows the update of x_j (phase K_Z)
+    const double est = fabs(C->eta) / C->eta0;
+    S.info->relres_est = est;
+    if (gn == 0.0) {
+      C->after_z = 2;
+      C->finishing = ST_OK;
+    } else if (est <= P.tol) {
+      C->after_z = P.check_true ? 1 : 2;
+      C->finishing = P.check_true ? -1 : ST_OK;
+    } else if (iter >= P.maxit) {
+      C->after_z = 2;
+      C->finishing = ST_NOT_CONVERGED;
+    } else {
+      C->after_z = 0;
+    }
+    publish(C, iter, S.d == 3 ? K_Y1I : K_Z);
+    return;
+  }
+  if (kind == K_Z) {
+    if (iter == 0 || C->after_z == 0) publish(C, iter + 1, K_X);
+    else publish(C, iter, K_PR);
+    return;
+  }
+  if (kind == K_PR) {
+    const int k = iter;
+    const double rt = sqrt(sum) / C->bnorm;
+    if (C->finishing >= 0) {
+      finish(S, G, iter, C->finishing, k, rt);
+    } else if (rt <= P.tol) {
+      finish(S, G, iter, ST_OK, k, rt);
+    } else if (k >= P.maxit) {
+      finish(S, G, iter, ST_NOT_CONVERGED, k, rt);
+    } else {
+      publish(C, iter + 1, K_X);
+    }
+    return;
   }
 }
 
@@ -425,71 +498,94 @@ __device__ void epilogue(const SysDesc &S, const SolveParams &P, int kind, int i
 // so progress does not depend on which workgroups are resident.  Idle
 // workgroups exit when every system is done or the time limit passes.
 // ---------------------------------------------------------------------------
+template <int LDSB>
 __global__ __launch_bounds__(NT) void solve_kernel(const SysDesc *__restrict__ sys,
                                                    const IOPtr *__restrict__ io, IOPtr io0,
                                                    int nsys, SolveParams P, Glob *G) {
   extern __shared__ __align__(16) char smem[];
-  __shared__ double red[NT];
+  __shared__ double red[NT / 64];
   __shared__ int sh_s, sh_tile, sh_kind, sh_iter, sh_last;
   const int tid = threadIdx.x;
   int cur = blockIdx.x % nsys;
   const long long t0 = wall_clock64();
   for (;;) {
-    if (tid == 0) {
+    if (tid < 64) {
+      // Wave 0 looks at up to 64 systems per round trip: each lane loads one
+      // ticket word, a ballot lists the systems with a tile ready, and lanes
+      // try to claim one in order, starting from the last system served.
+      const int lane = tid;
       int found = -1;
       if (__hip_atomic_load(&G->active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= 0 ||
           __hip_atomic_load(&G->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
         found = -2;
       } else {
-        for (int k = 0; k < nsys && found == -1; ++k) {
-          int s = cur + k;
-          if (s >= nsys) s -= nsys;
-          Ctl *C = sys[s].ctl;
-          const uint64_t w = __hip_atomic_load(&C->word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          const int kd = word_kind(w);
-          if (kd >= K_NKINDS || word_next(w) >= (uint32_t)sys[s].ntile[kd]) continue;
-          const uint64_t w2 = __hip_atomic_fetch_add(&C->word, 1ull, __ATOMIC_ACQUIRE,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
-          const int kd2 = word_kind(w2);
-          if (kd2 < K_NKINDS && word_next(w2) < (uint32_t)sys[s].ntile[kd2]) {
-            found = s;
-            sh_tile = (int)word_next(w2);
-            sh_kind = kd2;
-            sh_iter = word_iter(w2);
-            cur = s;
+        for (int base = 0; base < nsys && found == -1; base += 64) {
+          const int k = base + lane;
+          int sl = cur + k;
+          while (sl >= nsys) sl -= nsys;
+          bool avail = false;
+          if (k < nsys) {
+            const uint64_t w = __hip_atomic_load(&sys[sl].ctl->word, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+            const int kd = word_kind(w);
+            avail = kd < K_NKINDS && word_next(w) < (uint32_t)sys[sl].ntile[kd];
+          }
+          unsigned long long mask = __ballot(avail);
+          while (mask != 0ull && found == -1) {
+            const int ln = __ffsll((long long)mask) - 1;
+            mask &= mask - 1ull;
+            int got = 0;
+            if (lane == ln) {
+              const uint64_t w2 = __hip_atomic_fetch_add(&sys[sl].ctl->word, 1ull,
+                                                         __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+              const int kd2 = word_kind(w2);
+              if (kd2 < K_NKINDS && word_next(w2) < (uint32_t)sys[sl].ntile[kd2]) {
+                got = 1;
+                sh_tile = (int)word_next(w2);
+                sh_kind = kd2;
+                sh_iter = word_iter(w2);
+                // make the previous phase's results visible to this workgroup
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+              }
+            }
+            got = __shfl(got, ln, 64);
+            if (got) found = __shfl(sl, ln, 64);
           }
         }
         if (found == -1) {
           __builtin_amdgcn_s_sleep(2);
           if (wall_clock64() - t0 > P.timeout_ticks) {
-            __hip_atomic_fetch_or(&G->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (lane == 0)
+              __hip_atomic_fetch_or(&G->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             found = -2;
           }
+        } else if (found >= 0) {
+          cur = found;
         }
       }
-      sh_s = found;
+      if (lane == 0) sh_s = found;
     }
     __syncthreads();
     const int s = sh_s;
     if (s == -2) break;
     if (s >= 0) {
       const int kind = sh_kind, iter = sh_iter, tile = sh_tile;
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       const SysDesc &S = sys[s];
       const IOPtr iop = io ? io[s] : io0;
-      process_tile(S, iop, kind, iter, tile, smem, red);
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      process_tile<LDSB>(S, iop, kind, iter, tile, smem, red);
+      // every wave's stores are complete at the barrier; one agent-scope
+      // release then publishes them with the completion count
       __syncthreads();
       if (tid == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         const unsigned old = __hip_atomic_fetch_add(&S.ctl->done, 1u, __ATOMIC_ACQ_REL,
                                                      __HIP_MEMORY_SCOPE_AGENT);
-        sh_last = (old + 1 == (unsigned)S.ntile[kind]);
+        const int last = (old + 1 == (unsigned)S.ntile[kind]);
+        if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        sh_last = last;
       }
       __syncthreads();
-      if (sh_last) {
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        epilogue(S, P, kind, iter, G, red);
-      }
+      if (sh_last) epilogue(S, P, kind, iter, G, red);
     }
     __syncthreads();
   }
@@ -498,10 +594,10 @@ __global__ __launch_bounds__(NT) void solve_kernel(const SysDesc *__restrict__ s
 __global__ void init_kernel(const SysDesc *__restrict__ sys, int nsys, Glob *G) {
   for (int s = threadIdx.x; s < nsys; s += blockDim.x) {
     Ctl *C = sys[s].ctl;
-    C->word = make_word(0, K_RF);
+    C->word = make_word(0, K_X);
     C->done = 0;
     C->finishing = -1;
-    C->has_update = 0;
+    C->after_z = 0;
     DevInfo *I = sys[s].info;
     I->status = -1;
     I->iters = 0;
@@ -527,7 +623,7 @@ __global__ __launch_bounds__(NT) void apply_A_kernel(const SysDesc *__restrict__
     const int row = p / nlast;
     int idx[3];
     row_index<D>(S, row, p - row * nlast, idx);
-    const double2 kx = stencil_K<D>(S, S.a, x, p, idx);
+    const double2 kx = stencil_K<D>(S, x, p, idx);
     const double2 xv = x[p];
     // y = (K + lambda I) conj(x) = conj(K x + conj(lambda) x)
     const double ux = kx.x + S.alpha * xv.x + S.beta * xv.y;
@@ -536,13 +632,45 @@ __global__ __launch_bounds__(NT) void apply_A_kernel(const SysDesc *__restrict__
   }
 }
 
-template <typename R, int D>
-__global__ __launch_bounds__(NT) void pinv_pass_kernel(const SysDesc *__restrict__ sys, int kind,
+template <typename R, int D, int LDSB>
+__global__ __launch_bounds__(NT) void pinv_pass_kernel(const SysDesc *__restrict__ sys, int pass,
                                                        const double2 *x, double2 *y) {
   extern __shared__ __align__(16) char smem[];
-  __shared__ double red[NT];
-  IOPtr io{x, y};
-  tile_line<R, D, true>(*sys, io, kind, 0, blockIdx.x, smem, red);
+  tile_pinv<R, D, LDSB>(*sys, pass, x, y, blockIdx.x, smem);
+}
+
+// Face coefficients of axis ax divided by h_ax^2: harmonic mean of the two
+// neighbouring nodal samples inside, the adjacent sample on the boundary.
+template <int D>
+__global__ __launch_bounds__(NT) void faces_kernel(const SysDesc *__restrict__ sys, int ax,
+                                                   double *__restrict__ F) {
+  const SysDesc &S = *sys;
+  const double *__restrict__ a = S.a;
+  int fn[3];
+  for (int k = 0; k < 3; ++k) fn[k] = (k < D) ? S.n[k] + (k == ax ? 1 : 0) : 1;
+  const int total = fn[0] * fn[1] * (D == 3 ? fn[2] : 1);
+  for (int e = blockIdx.x * NT + threadIdx.x; e < total; e += gridDim.x * NT) {
+    int idx[3];
+    int rem = e;
+    for (int k = D - 1; k >= 0; --k) {
+      idx[k] = rem % fn[k];
+      rem /= fn[k];
+    }
+    // nodes below (i_ax - 1) and above (i_ax) the face
+    int pa = 0;
+    for (int k = 0; k < D; ++k) pa += (k == ax ? min(idx[k], S.n[ax] - 1) : idx[k]) * S.st[k];
+    double c;
+    if (idx[ax] == 0) {
+      c = a[pa];
+    } else if (idx[ax] == S.n[ax]) {
+      c = a[pa];
+    } else {
+      const double lo = a[pa - S.st[ax]];
+      const double hi = a[pa];
+      c = 2.0 * lo * hi / (lo + hi);
+    }
+    F[e] = c * S.h2[ax];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -745,12 +873,17 @@ hipError_t launch_init(const SysDesc *dsys, int nsys, Glob *G, hipStream_t s) {
 
 hipError_t launch_solve(const SysDesc *dsys, const IOPtr *dio, IOPtr io0, int nsys,
                         const SolveParams &P, Glob *G, int grid, size_t smem, hipStream_t s) {
-  hipLaunchKernelGGL(solve_kernel, dim3(grid), dim3(NT), smem, s, dsys, dio, io0, nsys, P, G);
+  if (smem <= 32768)
+    hipLaunchKernelGGL(solve_kernel<32768>, dim3(grid), dim3(NT), smem, s, dsys, dio, io0, nsys, P, G);
+  else
+    hipLaunchKernelGGL(solve_kernel<65536>, dim3(grid), dim3(NT), smem, s, dsys, dio, io0, nsys, P, G);
   return hipGetLastError();
 }
 
 hipError_t solve_occupancy(size_t smem, int *blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, solve_kernel, NT, smem);
+  if (smem <= 32768)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, solve_kernel<32768>, NT, smem);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, solve_kernel<65536>, NT, smem);
 }
 
 hipError_t launch_apply_A(const SysDesc *dsys, int d, int M, const double2 *x, double2 *y,
@@ -761,19 +894,33 @@ hipError_t launch_apply_A(const SysDesc *dsys, int d, int M, const double2 *x, d
   return hipGetLastError();
 }
 
-hipError_t launch_pinv_pass(const SysDesc *dsys, int d, int prec, int kind, int ntile, size_t smem,
-                            const double2 *x, double2 *y, hipStream_t s) {
+template <int LDSB>
+static void pinv_launch(const SysDesc *dsys, int d, int prec, int pass, int ntile, size_t smem,
+                        const double2 *x, double2 *y, hipStream_t s) {
   if (prec) {
     if (d == 3)
-      hipLaunchKernelGGL((pinv_pass_kernel<float, 3>), dim3(ntile), dim3(NT), smem, s, dsys, kind, x, y);
+      hipLaunchKernelGGL((pinv_pass_kernel<float, 3, LDSB>), dim3(ntile), dim3(NT), smem, s, dsys, pass, x, y);
     else
-      hipLaunchKernelGGL((pinv_pass_kernel<float, 2>), dim3(ntile), dim3(NT), smem, s, dsys, kind, x, y);
+      hipLaunchKernelGGL((pinv_pass_kernel<float, 2, LDSB>), dim3(ntile), dim3(NT), smem, s, dsys, pass, x, y);
   } else {
     if (d == 3)
-      hipLaunchKernelGGL((pinv_pass_kernel<double, 3>), dim3(ntile), dim3(NT), smem, s, dsys, kind, x, y);
+      hipLaunchKernelGGL((pinv_pass_kernel<double, 3, LDSB>), dim3(ntile), dim3(NT), smem, s, dsys, pass, x, y);
     else
-      hipLaunchKernelGGL((pinv_pass_kernel<double, 2>), dim3(ntile), dim3(NT), smem, s, dsys, kind, x, y);
+      hipLaunchKernelGGL((pinv_pass_kernel<double, 2, LDSB>), dim3(ntile), dim3(NT), smem, s, dsys, pass, x, y);
   }
+}
+
+hipError_t launch_pinv_pass(const SysDesc *dsys, int d, int prec, int pass, int ntile, size_t smem,
+                            const double2 *x, double2 *y, hipStream_t s) {
+  if (smem <= 32768) pinv_launch<32768>(dsys, d, prec, pass, ntile, smem, x, y, s);
+  else pinv_launch<65536>(dsys, d, prec, pass, ntile, smem, x, y, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_faces(const SysDesc *dsys, int d, int ax, int nfaces, double *F, hipStream_t s) {
+  const int grid = (nfaces + NT - 1) / NT < 4096 ? (nfaces + NT - 1) / NT : 4096;
+  if (d == 3) hipLaunchKernelGGL(faces_kernel<3>, dim3(grid), dim3(NT), 0, s, dsys, ax, F);
+  else hipLaunchKernelGGL(faces_kernel<2>, dim3(grid), dim3(NT), 0, s, dsys, ax, F);
   return hipGetLastError();
 }
 

@@ -11,8 +11,9 @@ hipError_t launch_solve(const SysDesc *dsys, const IOPtr *dio, IOPtr io0, int ns
 hipError_t solve_occupancy(size_t smem, int *blocks_per_cu);
 hipError_t launch_apply_A(const SysDesc *dsys, int d, int M, const double2 *x, double2 *y,
                           hipStream_t s);
-hipError_t launch_pinv_pass(const SysDesc *dsys, int d, int prec, int kind, int ntile, size_t smem,
+hipError_t launch_pinv_pass(const SysDesc *dsys, int d, int prec, int pass, int ntile, size_t smem,
                             const double2 *x, double2 *y, hipStream_t s);
+hipError_t launch_faces(const SysDesc *dsys, int d, int ax, int nfaces, double *F, hipStream_t s);
 hipError_t launch_adjoint(const SysDesc *dsys, int d, int M, const double2 *ytil,
                           const double2 *z, double2 *gf, double *ga, double *part, int nblk,
                           double *galpha, double *gbeta, hipStream_t s);

@@ -121,47 +121,90 @@ SolveParams make_params(double tol, int maxit, int check_true, int timeout_ms, d
   return P;
 }
 
-// Tiling of one system: lines per tile of each transform pass, rows per
-// tile of the pointwise passes, tile counts per phase kind, LDS bytes.
-void choose_tiles(SysDesc &h, size_t *smem_out) {
-  const int eltsz = h.prec ? 8 : 16;
-  const int maxe = h.prec ? 8192 : 4096;
-  const int target = h.prec ? 4096 : 2048;
-  const int nlast = h.n[h.d - 1];
-  size_t smem = 0;
-  for (int ax = 0; ax < 3; ++ax) {
-    if (ax >= h.d) {
-      h.lpt[ax] = 1;
+// Tiling of one system: rows per tile of the FP64 row pass (K_X), of the
+// preconditioner-precision row pass (K_Z), lines per tile of the strided
+// passes, rows per tile of the residual pass; tile counts per phase kind and
+// the LDS bytes a workgroup needs.
+void choose_tiles(SysDesc &h, int tile_elems, size_t *smem_out) {
+  // LDS budget per workgroup: 32 KiB unless a line of 2048 (n = 1023) needs 64
+  int Lmax = 0;
+  for (int ax = 0; ax < h.d; ++ax) Lmax = std::max(Lmax, 2 * (h.n[ax] + 1));
+  const int ldsb = Lmax > 1024 ? 65536 : 32768;
+  const int eltR = h.prec ? 8 : 16;
+  const int maxeR = ldsb / eltR;
+  const int maxe64 = ldsb / 16;
+  const int tgt64 = tile_elems > 0 ? std::min(tile_elems, maxe64) : maxe64;
+  const int tgtR = tile_elems > 0 ? std::min(tile_elems, maxeR) : maxeR;
+  const int dl = h.d - 1;
+  const int nlast = h.n[dl];
+  const int Ll = 2 * (nlast + 1);
+  auto rows_lp = [&](int tgt, int maxe) {
+    const int cap = std::max(1, std::min(64, maxe / Ll));
+    return pow2floor(std::max(1, std::min(tgt / Ll, cap)));
+  };
+  h.lpt_x = rows_lp(tgt64, maxe64);
+  h.lpt_z = rows_lp(tgtR, maxeR);
+  size_t smem = std::max((size_t)h.lpt_x * Ll * 16, (size_t)h.lpt_z * Ll * eltR);
+  for (int ax = 0; ax < 2; ++ax) {
+    if (ax >= dl) {
+      h.lpt_s[ax] = 1;
       continue;
     }
     const int L = 2 * (h.n[ax] + 1);
-    const int cap = std::max(1, maxe / L);
-    int want = std::max(1, target / L);
-    if (ax != h.d - 1) want = std::max(want, h.prec ? 8 : 4);  // 64-byte row segments
-    want = std::min(want, 64);
+    const int cap = std::max(1, std::min(64, maxeR / L));
+    int want = std::max(4, tgtR / L);
     int lp = pow2floor(std::min(want, cap));
-    if (ax != h.d - 1) lp = std::min(lp, pow2floor(std::max(1, nlast)) * 2);
-    h.lpt[ax] = std::max(1, lp);
-    smem = std::max(smem, (size_t)h.lpt[ax] * L * eltsz);
+    lp = std::min(lp, pow2floor(std::max(1, nlast)) * 2);
+    h.lpt_s[ax] = std::max(1, lp);
+    smem = std::max(smem, (size_t)h.lpt_s[ax] * L * eltR);
   }
-  h.rpt = std::max(1, 4096 / nlast);
-  for (int k = 0; k < K_NKINDS; ++k) h.ntile[k] = 0;
+  h.rpt = std::max(1, tgt64 / nlast);
+  for (int k = 0; k < K_NKINDS; ++k) {
+    h.nchunk[k] = 0;
+    h.cpt[k] = 1;
+  }
   const int rows = h.rows;
-  h.ntile[K_RF] = h.ntile[K_RI] = (rows + h.lpt[h.d - 1] - 1) / h.lpt[h.d - 1];
+  h.nchunk[K_X] = (rows + h.lpt_x - 1) / h.lpt_x;
+  h.nchunk[K_Z] = (rows + h.lpt_z - 1) / h.lpt_z;
   if (h.d == 3) {
-    const int nb1 = (nlast + h.lpt[1] - 1) / h.lpt[1];
-    h.ntile[K_F1] = h.ntile[K_I1] = h.n[0] * nb1;
-    const int nb0 = (nlast + h.lpt[0] - 1) / h.lpt[0];
-    h.ntile[K_MID] = h.n[1] * nb0;
+    const int nb1 = (nlast + h.lpt_s[1] - 1) / h.lpt_s[1];
+    h.nchunk[K_Y1] = h.nchunk[K_Y1I] = h.n[0] * nb1;
+    const int nb0 = (nlast + h.lpt_s[0] - 1) / h.lpt_s[0];
+    h.nchunk[K_Y] = h.n[1] * nb0;
   } else {
-    const int nb0 = (nlast + h.lpt[0] - 1) / h.lpt[0];
-    h.ntile[K_MID] = nb0;
+    h.nchunk[K_Y] = (nlast + h.lpt_s[0] - 1) / h.lpt_s[0];
   }
-  h.ntile[K_PA] = h.ntile[K_PR] = (rows + h.rpt - 1) / h.rpt;
+  h.nchunk[K_PR] = (rows + h.rpt - 1) / h.rpt;
+  for (int k = 0; k < K_NKINDS; ++k) h.ntile[k] = h.nchunk[k];
   int mx = 0;
   for (int k = 0; k < K_NKINDS; ++k) mx = std::max(mx, h.ntile[k]);
   h.maxtile = mx;
-  *smem_out = smem;
+  *smem_out = smem <= 32768 ? smem : 65536;
+}
+
+// Group chunks into tiles of about `points` grid points each (1 chunk per
+// tile when points <= 0): fewer, larger tiles mean fewer cross-workgroup
+// hand-offs (each one an L2 write-back and invalidate) per phase.
+void set_tile_points(SysDesc &h, int points) {
+  const int nlast = h.n[h.d - 1];
+  int cpts[K_NKINDS];
+  for (int k = 0; k < K_NKINDS; ++k) cpts[k] = 1;
+  if (points > 0) {
+    auto per = [&](int chunk_points) { return std::max(1, points / std::max(1, chunk_points)); };
+    cpts[K_X] = per(h.lpt_x * nlast);
+    cpts[K_Z] = per(h.lpt_z * nlast);
+    cpts[K_Y] = per(h.lpt_s[0] * h.n[0]);
+    if (h.d == 3) cpts[K_Y1] = cpts[K_Y1I] = per(h.lpt_s[1] * h.n[1]);
+    cpts[K_PR] = per(h.rpt * nlast);
+  }
+  int mx = 0;
+  for (int k = 0; k < K_NKINDS; ++k) {
+    h.cpt[k] = cpts[k];
+    h.ntile[k] = h.nchunk[k] > 0 ? (h.nchunk[k] + cpts[k] - 1) / cpts[k] : 0;
+    mx = std::max(mx, h.ntile[k]);
+  }
+  h.maxtile = std::max(h.maxtile, 0);
+  (void)mx;
 }
 
 csl_status info_from_device(const DevInfo &di, int glob_error, csl_solve_info *info) {
@@ -263,7 +306,11 @@ csl_status create_problem(const csl_grid *grid, const double *a_nodal, double al
     khz = 100000;
   p->wall_khz = (double)khz;
 
-  choose_tiles(h, &p->smem);
+  if (o.tile_elems < 0) {
+    delete p;
+    return fail(CSL_ERR_ARG, "tile_elems must be >= 0");
+  }
+  choose_tiles(h, o.tile_elems, &p->smem);
   p->stats_nblk = std::min(1024, (h.M + NT - 1) / NT);
   p->adj_nblk = std::min(1024, (h.M + NT - 1) / NT);
 
@@ -271,6 +318,14 @@ csl_status create_problem(const csl_grid *grid, const double *a_nodal, double al
   const size_t vec = align256(sizeof(double2) * (size_t)h.M);
   const size_t tsz = align256((size_t)h.M * (h.prec ? 8 : 16));
   const int nmu = h.n[0] + h.n[1] + h.n[2];
+  int nfaces[3] = {0, 0, 0};
+  for (int ax = 0; ax < h.d; ++ax) {
+    int fn[3];
+    for (int k = 0; k < 3; ++k) fn[k] = k < h.d ? h.n[k] + (k == ax ? 1 : 0) : 1;
+    nfaces[ax] = fn[0] * fn[1] * fn[2];
+    h.fst[ax][h.d - 1] = 1;
+    for (int k = h.d - 2; k >= 0; --k) h.fst[ax][k] = h.fst[ax][k + 1] * fn[k + 1];
+  }
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o2 = off;
@@ -278,10 +333,12 @@ csl_status create_problem(const csl_grid *grid, const double *a_nodal, double al
     return o2;
   };
   const size_t o_a = take(sizeof(double) * h.M);
+  size_t o_f[3] = {0, 0, 0};
+  for (int ax = 0; ax < h.d; ++ax) o_f[ax] = take(sizeof(double) * nfaces[ax]);
   const size_t o_mu = take(sizeof(double) * nmu);
   const size_t o_muf = take(sizeof(float) * nmu);
-  size_t o_v[6];
-  for (int i = 0; i < 6; ++i) o_v[i] = take(vec);
+  size_t o_v[7];
+  for (int i = 0; i < 7; ++i) o_v[i] = take(vec);
   const size_t o_t = take(tsz);
   const size_t o_part = take(sizeof(double) * std::max(1, h.maxtile));
   const size_t o_ctl = take(sizeof(Ctl));
@@ -304,12 +361,14 @@ csl_status create_problem(const csl_grid *grid, const double *a_nodal, double al
   double *d_mu = (double *)(base + o_mu);
   float *d_muf = (float *)(base + o_muf);
   h.a = d_a;
-  h.V[0] = (double2 *)(base + o_v[0]);
-  h.V[1] = (double2 *)(base + o_v[1]);
-  h.Z[0] = (double2 *)(base + o_v[2]);
-  h.Z[1] = (double2 *)(base + o_v[3]);
-  h.W[0] = (double2 *)(base + o_v[4]);
-  h.W[1] = (double2 *)(base + o_v[5]);
+  for (int ax = 0; ax < 3; ++ax) h.F[ax] = ax < h.d ? (const double *)(base + o_f[ax]) : nullptr;
+  h.Tq = (double2 *)(base + o_v[0]);
+  h.Tv[0] = (double2 *)(base + o_v[1]);
+  h.Tv[1] = (double2 *)(base + o_v[2]);
+  h.Z[0] = (double2 *)(base + o_v[3]);
+  h.Z[1] = (double2 *)(base + o_v[4]);
+  h.W[0] = (double2 *)(base + o_v[5]);
+  h.W[1] = (double2 *)(base + o_v[6]);
   h.T = base + o_t;
   h.part = (double *)(base + o_part);
   h.ctl = (Ctl *)(base + o_ctl);
@@ -351,6 +410,8 @@ csl_status create_problem(const csl_grid *grid, const double *a_nodal, double al
   PCHK(hipMemcpyAsync(d_muf, muf.data(), sizeof(float) * nmu, hipMemcpyHostToDevice, s));
   PCHK(hipMemcpyAsync(p->d_desc, &h, sizeof(SysDesc), hipMemcpyHostToDevice, s));
   PCHK(launch_coef_stats(p->d_desc, h.d, h.M, p->stats_part, p->stats_nblk, p->stats, s));
+  for (int ax = 0; ax < h.d; ++ax)
+    PCHK(launch_faces(p->d_desc, h.d, ax, nfaces[ax], (double *)h.F[ax], s));
   PCHK(hipMemcpyAsync(st4, p->stats, sizeof(st4), hipMemcpyDeviceToHost, s));
   PCHK(hipStreamSynchronize(s));
   if (st4[3] != 0.0) {
@@ -424,14 +485,17 @@ csl_status apply_Pinv(csl_problem p, const double *x, double *y, hipStream_t s) 
   const SysDesc &h = p->h;
   const double2 *xi = (const double2 *)x;
   double2 *yo = (double2 *)y;
-  std::vector<int> kinds;
-  kinds.push_back(K_RF);
-  if (h.d == 3) kinds.push_back(K_F1);
-  kinds.push_back(K_MID);
-  if (h.d == 3) kinds.push_back(K_I1);
-  kinds.push_back(K_RI);
-  for (int k : kinds)
-    HIPCHK(launch_pinv_pass(p->d_desc, h.d, h.prec, k, h.ntile[k], p->smem, xi, yo, s));
+  // passes: 0 rows forward, 1 axis-1 forward, 2 axis 0 with scaling,
+  // 3 axis-1 inverse, 4 rows inverse
+  std::vector<std::pair<int, int>> passes;
+  const int nrow = (h.rows + h.lpt_z - 1) / h.lpt_z;
+  passes.push_back({0, nrow});
+  if (h.d == 3) passes.push_back({1, h.ntile[K_Y1]});
+  passes.push_back({2, h.ntile[K_Y]});
+  if (h.d == 3) passes.push_back({3, h.ntile[K_Y1I]});
+  passes.push_back({4, nrow});
+  for (auto &pp : passes)
+    HIPCHK(launch_pinv_pass(p->d_desc, h.d, h.prec, pp.first, pp.second, p->smem, xi, yo, s));
   return CSL_OK;
 }
 
@@ -534,11 +598,15 @@ csl_status batch_create(const csl_problem *problems, int count, const csl_batch_
   std::vector<SysDesc> descs(count);
   size_t smem = 0;
   long long total_tiles = 0;
+  const int tile_points = o.reserved[0] > 0 ? o.reserved[0] : 16384;
   for (int i = 0; i < count; ++i) {
     descs[i] = problems[i]->h;
     descs[i].info = b->d_info + i;
+    set_tile_points(descs[i], tile_points);
     smem = std::max(smem, problems[i]->smem);
-    total_tiles += problems[i]->h.maxtile;
+    int mt = 0;
+    for (int k = 0; k < K_NKINDS; ++k) mt = std::max(mt, descs[i].ntile[k]);
+    total_tiles += mt;
   }
   b->smem = smem;
   auto cleanup = [&](const std::string &msg) {
