@@ -52,10 +52,62 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--plain-reps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=8,
+    ap.add_argument("--cpu-sample", type=int, default=40,
                     help="systems of the batch timed with the CPU oracle")
     ap.add_argument("--count", type=int, default=64)
+    ap.add_argument("--batch-only", action="store_true",
+                    help="time only the batched solve (for profiler runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run device-to-device copies of 1 GiB, the reference for the "
+                         "HBM byte counters")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """Three device copies of 1 GiB (1 GiB read + 1 GiB written each): the
+    reference that scales the FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+    n = (1 << 30) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30, "copies": 3}))
+
+
+KERNEL_SOURCES = ["paper_2408_00488_amd/csrc/csl_kernels.hip",
+                  "paper_2408_00488_amd/csrc/csl_device.hpp",
+                  "paper_2408_00488_amd/csrc/csl_common.hpp"]
+TRAFFIC_FILE = "profiles/solve_kernel_batch64_hbm_traffic.txt"
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the kernel source as it is now (else None)."""
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(workload, systems_idx, gpu_solutions):
@@ -88,6 +140,9 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU available"}))
         sys.exit(1)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     import paper_2408_00488_amd as C
     from paper_2408_00488_amd import workloads as WL
     C.load_library()
@@ -125,6 +180,10 @@ def main():
     value = len(w.systems) * args.steps / wall
     zs, infos = batch.solve(F, Z)
     iters = [i["iters"] for i in infos]
+    if args.batch_only:
+        log(f"batched: {ms_per_step:.2f} ms per solve of {len(w.systems)} systems, "
+            f"{value:.0f} solves/s, iterations {sum(iters)}")
+        return
     relres = [i["relres_true"] for i in infos]
     statuses = [i["status"] for i in infos]
     Zcpu = [z.cpu().numpy() for z in Z]
@@ -186,7 +245,7 @@ def main():
                                "one hipGraph replay",
                    "systems": len(w.systems), "points": points},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": measured_traffic(),
                      "kernel": "solve_kernel", "avg_launch_ms": avg_launch_s * 1e3,
                      "alg_bytes_per_launch": alg_bytes},
         "cpu_baseline": cpu,

@@ -176,7 +176,7 @@ typedef struct csl_batch_opts {
     int grid_size;          /* workgroups of the persistent launch; 0 = auto   */
     int use_graph;          /* 1: replay a captured hipGraph per solve          */
     int reserved[3];        /* reserved[0]: grid points per scheduling tile
-                               (0 = 16384); larger tiles mean fewer
+                               (0 = 8192); larger tiles mean fewer
                                cross-workgroup hand-offs                    */
 } csl_batch_opts;
 

@@ -44,12 +44,26 @@ template <typename R, int LDSB> struct MaxElts {
 // stages; each stage reads all of its inputs into registers, synchronises,
 // and writes the outputs in place.  Output is in natural order.
 // ---------------------------------------------------------------------------
+// LDS bytes reserved after the line buffer for the twiddles of one length.
+constexpr int TW_LDS_BYTES = 8192;
+
+// Stage exp(-2 pi i m / L), m < L/4, into LDS: every radix-4 stage of a
+// length-L Stockham FFT uses w1 = exp(-2 pi i k / (4 Ns)), k < Ns, which is
+// entry k L / (4 Ns) < L/4 of that table.
+template <typename R>
+__device__ void load_twiddles(Cx<R> *twl, int lg) {
+  const Cx<R> *tw = twiddles<R>();
+  const int q = (1 << lg) >> 2;
+  const int step = TWN >> lg;
+  for (int m = threadIdx.x; m < q; m += NT) twl[m] = tw[m * step];
+  __syncthreads();
+}
+
 template <typename R, int LDSB>
-__device__ void fft_lines(Cx<R> *buf, int nl, int lg) {
+__device__ void fft_lines(Cx<R> *buf, int nl, int lg, const Cx<R> *twl) {
   constexpr int MAXE = MaxElts<R, LDSB>::value;
   const int tid = threadIdx.x;
   const int L = 1 << lg;
-  const Cx<R> *tw = twiddles<R>();
   int Ns = 1;
   if (lg & 1) {
     constexpr int U = MAXE / (2 * NT);
@@ -93,7 +107,7 @@ __device__ void fft_lines(Cx<R> *buf, int nl, int lg) {
       }
     }
     __syncthreads();
-    const int tstep = TWN / (4 * Ns);
+    const int tstep = L / (4 * Ns);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int b = tid + u * NT;
@@ -102,7 +116,7 @@ __device__ void fft_lines(Cx<R> *buf, int nl, int lg) {
         const int k = j & (Ns - 1);
         Cx<R> x0 = a[u][0], x1 = a[u][1], x2 = a[u][2], x3 = a[u][3];
         if (Ns > 1) {
-          const Cx<R> w1 = tw[k * tstep];
+          const Cx<R> w1 = twl[k * tstep];
           const Cx<R> w2 = cmul(w1, w1);
           const Cx<R> w3 = cmul(w2, w1);
           x1 = cmul(x1, w1);

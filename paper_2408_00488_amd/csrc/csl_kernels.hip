@@ -26,6 +26,8 @@ template <int D, int LDSB>
 __device__ void tile_X(const SysDesc &S, const IOPtr &io, int iter, int tile, char *smem,
                        double *red) {
   Cx<double> *buf = reinterpret_cast<Cx<double> *>(smem);
+  Cx<double> *twl = reinterpret_cast<Cx<double> *>(smem + LDSB);
+  load_twiddles<double>(twl, S.lg[D - 1]);
   double acc = 0.0;
   const int c1 = min(S.nchunk[K_X], (tile + 1) * S.cpt[K_X]);
   for (int chunk = tile * S.cpt[K_X]; chunk < c1; ++chunk) {
@@ -61,7 +63,7 @@ __device__ void tile_X(const SysDesc &S, const IOPtr &io, int iter, int tile, ch
           });
       out = reinterpret_cast<Cx<double> *>(S.Tq);
     }
-    fft_lines<double, LDSB>(buf, t.nl, t.lg);
+    fft_lines<double, LDSB>(buf, t.nl, t.lg, twl);
     lines_store<double>(buf, t, [&](int, int, int p, Cx<double> v) { out[p] = v; });
   }
   const double s = wg_sum(acc, red);
@@ -81,6 +83,8 @@ template <typename R, int D, int LDSB>
 __device__ void tile_Y(const SysDesc &S, int kind, int iter, int tile, char *smem, double *red) {
   Cx<R> *buf = reinterpret_cast<Cx<R> *>(smem);
   const int ax = (kind == K_Y) ? 0 : 1;
+  Cx<R> *twl = reinterpret_cast<Cx<R> *>(smem + LDSB);
+  load_twiddles<R>(twl, S.lg[ax]);
   Cx<R> *T = reinterpret_cast<Cx<R> *>(S.T);
   const bool first = (kind == K_Y1) || (D == 2);
   const int j = iter;
@@ -123,7 +127,7 @@ __device__ void tile_Y(const SysDesc &S, int kind, int iter, int tile, char *sme
   } else {
     lines_fill<R>(buf, t, [&](int, int, int p) { return T[p]; });
   }
-  fft_lines<R, LDSB>(buf, t.nl, t.lg);
+  fft_lines<R, LDSB>(buf, t.nl, t.lg, twl);
   if (kind == K_Y) {
     const R ab = (sizeof(R) == 8) ? (R)S.abar : (R)S.abar_f;
     const R al = (sizeof(R) == 8) ? (R)S.alpha : (R)S.alpha_f;
@@ -152,7 +156,7 @@ __device__ void tile_Y(const SysDesc &S, int kind, int iter, int tile, char *sme
       const R sh = ab * lam + al;
       return (R)1 / sqrt(sh * sh + be * be);
     });
-    fft_lines<R, LDSB>(buf, t.nl, t.lg);
+    fft_lines<R, LDSB>(buf, t.nl, t.lg, twl);
   }
   lines_store<R>(buf, t, [&](int, int, int p, Cx<R> v) { T[p] = v; });
   }
@@ -171,6 +175,8 @@ __device__ void tile_Y(const SysDesc &S, int kind, int iter, int tile, char *sme
 template <typename R, int D, int LDSB>
 __device__ void tile_Z(const SysDesc &S, const IOPtr &io, int iter, int tile, char *smem) {
   Cx<R> *buf = reinterpret_cast<Cx<R> *>(smem);
+  Cx<R> *twl = reinterpret_cast<Cx<R> *>(smem + LDSB);
+  load_twiddles<R>(twl, S.lg[D - 1]);
   const int c1 = min(S.nchunk[K_Z], (tile + 1) * S.cpt[K_Z]);
   for (int chunk = tile * S.cpt[K_Z]; chunk < c1; ++chunk) {
   const LineTile t = line_tile(S, D - 1, S.lpt_z, chunk);
@@ -182,7 +188,7 @@ __device__ void tile_Z(const SysDesc &S, const IOPtr &io, int iter, int tile, ch
   const double ig = store_z ? 1.0 / g : 0.0;
   double2 *__restrict__ znew = S.Z[(j + 1) & 1];
   lines_fill<R, 8>(buf, t, [&](int, int, int p) { return T[p]; });
-  fft_lines<R, LDSB>(buf, t.nl, t.lg);
+  fft_lines<R, LDSB>(buf, t.nl, t.lg, twl);
   if (j == 0) {
     lines_store<R>(buf, t, [&](int, int, int p, Cx<R> v) {
       znew[p] = make_double2((double)v.x * ig, (double)v.y * ig);
@@ -191,6 +197,7 @@ __device__ void tile_Z(const SysDesc &S, const IOPtr &io, int iter, int tile, ch
   }
   const double e1 = ld_ctl(&C->e1), e2 = ld_ctl(&C->e2), e3 = ld_ctl(&C->e3);
   const double ceta = ld_ctl(&C->ceta);
+  const double ie1 = 1.0 / e1;
   const double2 *__restrict__ zj = S.Z[j & 1];
   double2 *__restrict__ wnew = S.W[(j + 1) & 1];   // holds w_{j-1} before the update
   const double2 *__restrict__ wj = S.W[j & 1];
@@ -211,8 +218,8 @@ __device__ void tile_Z(const SysDesc &S, const IOPtr &io, int iter, int tile, ch
       },
       [&](int p, Cx<R> v, const In4 &in) {
         if (store_z) znew[p] = make_double2((double)v.x * ig, (double)v.y * ig);
-        const double wx = (in.z.x - e3 * in.w0.x - e2 * in.w1.x) / e1;
-        const double wy = (in.z.y - e3 * in.w0.y - e2 * in.w1.y) / e1;
+        const double wx = (in.z.x - e3 * in.w0.x - e2 * in.w1.x) * ie1;
+        const double wy = (in.z.y - e3 * in.w0.y - e2 * in.w1.y) * ie1;
         wnew[p] = make_double2(wx, wy);
         X[p] = make_double2(in.x.x + ceta * wx, in.x.y - ceta * wy);
       });
@@ -293,9 +300,11 @@ __device__ void tile_pinv(const SysDesc &S, int pass, const double2 *x, double2 
   const int ax = (pass == 0 || pass == 4) ? D - 1 : (pass == 2 ? 0 : 1);
   const int lp = (ax == D - 1) ? S.lpt_z : S.lpt_s[ax];
   const LineTile t = line_tile(S, ax, lp, tile);
+  Cx<R> *twl = reinterpret_cast<Cx<R> *>(smem + LDSB);
+  load_twiddles<R>(twl, t.lg);
   if (pass == 0) lines_fill<R>(buf, t, [&](int, int, int p) { return to_cx<R>(x[p]); });
   else lines_fill<R>(buf, t, [&](int, int, int p) { return T[p]; });
-  fft_lines<R, LDSB>(buf, t.nl, t.lg);
+  fft_lines<R, LDSB>(buf, t.nl, t.lg, twl);
   if (pass == 2) {
     const R ab = (sizeof(R) == 8) ? (R)S.abar : (R)S.abar_f;
     const R al = (sizeof(R) == 8) ? (R)S.alpha : (R)S.alpha_f;
@@ -322,7 +331,7 @@ __device__ void tile_pinv(const SysDesc &S, int pass, const double2 *x, double2 
       const R sh = ab * lam + al;
       return (R)1 / sqrt(sh * sh + be * be);
     });
-    fft_lines<R, LDSB>(buf, t.nl, t.lg);
+    fft_lines<R, LDSB>(buf, t.nl, t.lg, twl);
   }
   if (pass == 4) {
     lines_store<R>(buf, t, [&](int, int, int p, Cx<R> v) {
@@ -508,6 +517,7 @@ __global__ __launch_bounds__(NT) void solve_kernel(const SysDesc *__restrict__ s
   const int tid = threadIdx.x;
   int cur = blockIdx.x % nsys;
   const long long t0 = wall_clock64();
+  int backoff = 0;
   for (;;) {
     if (tid < 64) {
       // Wave 0 looks at up to 64 systems per round trip: each lane loads one
@@ -515,52 +525,55 @@ __global__ __launch_bounds__(NT) void solve_kernel(const SysDesc *__restrict__ s
       // try to claim one in order, starting from the last system served.
       const int lane = tid;
       int found = -1;
-      if (__hip_atomic_load(&G->active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= 0 ||
-          __hip_atomic_load(&G->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-        found = -2;
-      } else {
-        for (int base = 0; base < nsys && found == -1; base += 64) {
-          const int k = base + lane;
-          int sl = cur + k;
-          while (sl >= nsys) sl -= nsys;
-          bool avail = false;
-          if (k < nsys) {
-            const uint64_t w = __hip_atomic_load(&sys[sl].ctl->word, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
-            const int kd = word_kind(w);
-            avail = kd < K_NKINDS && word_next(w) < (uint32_t)sys[sl].ntile[kd];
-          }
-          unsigned long long mask = __ballot(avail);
-          while (mask != 0ull && found == -1) {
-            const int ln = __ffsll((long long)mask) - 1;
-            mask &= mask - 1ull;
-            int got = 0;
-            if (lane == ln) {
-              const uint64_t w2 = __hip_atomic_fetch_add(&sys[sl].ctl->word, 1ull,
-                                                         __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-              const int kd2 = word_kind(w2);
-              if (kd2 < K_NKINDS && word_next(w2) < (uint32_t)sys[sl].ntile[kd2]) {
-                got = 1;
-                sh_tile = (int)word_next(w2);
-                sh_kind = kd2;
-                sh_iter = word_iter(w2);
-                // make the previous phase's results visible to this workgroup
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-              }
-            }
-            got = __shfl(got, ln, 64);
-            if (got) found = __shfl(sl, ln, 64);
-          }
+      for (int base = 0; base < nsys && found == -1; base += 64) {
+        const int k = base + lane;
+        int sl = cur + k;
+        while (sl >= nsys) sl -= nsys;
+        bool avail = false;
+        if (k < nsys) {
+          const uint64_t w = __hip_atomic_load(&sys[sl].ctl->word, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+          const int kd = word_kind(w);
+          avail = kd < K_NKINDS && word_next(w) < (uint32_t)sys[sl].ntile[kd];
         }
-        if (found == -1) {
-          __builtin_amdgcn_s_sleep(2);
-          if (wall_clock64() - t0 > P.timeout_ticks) {
-            if (lane == 0)
-              __hip_atomic_fetch_or(&G->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            found = -2;
+        unsigned long long mask = __ballot(avail);
+        while (mask != 0ull && found == -1) {
+          const int ln = __ffsll((long long)mask) - 1;
+          mask &= mask - 1ull;
+          int got = 0;
+          if (lane == ln) {
+            const uint64_t w2 = __hip_atomic_fetch_add(&sys[sl].ctl->word, 1ull,
+                                                       __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            const int kd2 = word_kind(w2);
+            if (kd2 < K_NKINDS && word_next(w2) < (uint32_t)sys[sl].ntile[kd2]) {
+              got = 1;
+              sh_tile = (int)word_next(w2);
+              sh_kind = kd2;
+              sh_iter = word_iter(w2);
+              // make the previous phase's results visible to this workgroup
+              __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
           }
-        } else if (found >= 0) {
-          cur = found;
+          got = __shfl(got, ln, 64);
+          if (got) found = __shfl(sl, ln, 64);
+        }
+      }
+      if (found >= 0) {
+        cur = found;
+        backoff = 0;
+      } else {
+        // nothing ready: stop when every system is done or on error / time
+        // limit, else back off (up to ~4 us) before looking again
+        if (__hip_atomic_load(&G->active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= 0 ||
+            __hip_atomic_load(&G->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+          found = -2;
+        } else if (wall_clock64() - t0 > P.timeout_ticks) {
+          if (lane == 0)
+            __hip_atomic_fetch_or(&G->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          found = -2;
+        } else {
+          backoff = backoff < 16 ? backoff + 1 : 16;
+          for (int i = 0; i < backoff; ++i) __builtin_amdgcn_s_sleep(8);
         }
       }
       if (lane == 0) sh_s = found;
@@ -874,16 +887,20 @@ hipError_t launch_init(const SysDesc *dsys, int nsys, Glob *G, hipStream_t s) {
 hipError_t launch_solve(const SysDesc *dsys, const IOPtr *dio, IOPtr io0, int nsys,
                         const SolveParams &P, Glob *G, int grid, size_t smem, hipStream_t s) {
   if (smem <= 32768)
-    hipLaunchKernelGGL(solve_kernel<32768>, dim3(grid), dim3(NT), smem, s, dsys, dio, io0, nsys, P, G);
+    hipLaunchKernelGGL(solve_kernel<32768>, dim3(grid), dim3(NT), 32768 + TW_LDS_BYTES, s, dsys, dio,
+                       io0, nsys, P, G);
   else
-    hipLaunchKernelGGL(solve_kernel<65536>, dim3(grid), dim3(NT), smem, s, dsys, dio, io0, nsys, P, G);
+    hipLaunchKernelGGL(solve_kernel<65536>, dim3(grid), dim3(NT), 65536 + TW_LDS_BYTES, s, dsys, dio,
+                       io0, nsys, P, G);
   return hipGetLastError();
 }
 
 hipError_t solve_occupancy(size_t smem, int *blocks_per_cu) {
   if (smem <= 32768)
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, solve_kernel<32768>, NT, smem);
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, solve_kernel<65536>, NT, smem);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, solve_kernel<32768>, NT,
+                                                        32768 + TW_LDS_BYTES);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, solve_kernel<65536>, NT,
+                                                      65536 + TW_LDS_BYTES);
 }
 
 hipError_t launch_apply_A(const SysDesc *dsys, int d, int M, const double2 *x, double2 *y,
@@ -912,8 +929,8 @@ static void pinv_launch(const SysDesc *dsys, int d, int prec, int pass, int ntil
 
 hipError_t launch_pinv_pass(const SysDesc *dsys, int d, int prec, int pass, int ntile, size_t smem,
                             const double2 *x, double2 *y, hipStream_t s) {
-  if (smem <= 32768) pinv_launch<32768>(dsys, d, prec, pass, ntile, smem, x, y, s);
-  else pinv_launch<65536>(dsys, d, prec, pass, ntile, smem, x, y, s);
+  if (smem <= 32768) pinv_launch<32768>(dsys, d, prec, pass, ntile, 32768 + TW_LDS_BYTES, x, y, s);
+  else pinv_launch<65536>(dsys, d, prec, pass, ntile, 65536 + TW_LDS_BYTES, x, y, s);
   return hipGetLastError();
 }
 

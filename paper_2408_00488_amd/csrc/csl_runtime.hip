@@ -598,7 +598,7 @@ csl_status batch_create(const csl_problem *problems, int count, const csl_batch_
   std::vector<SysDesc> descs(count);
   size_t smem = 0;
   long long total_tiles = 0;
-  const int tile_points = o.reserved[0] > 0 ? o.reserved[0] : 16384;
+  const int tile_points = o.reserved[0] > 0 ? o.reserved[0] : 8192;
   for (int i = 0; i < count; ++i) {
     descs[i] = problems[i]->h;
     descs[i].info = b->d_info + i;
@@ -626,7 +626,10 @@ csl_status batch_create(const csl_problem *problems, int count, const csl_batch_
   int bpc = 0;
   if (solve_occupancy(smem, &bpc) != hipSuccess) return cleanup("occupancy query failed");
   const int cap = std::max(1, bpc) * problems[0]->cus;
-  b->grid = o.grid_size > 0 ? o.grid_size : (int)std::min<long long>(cap, total_tiles);
+  // tiles are claimed dynamically, so a full-occupancy grid keeps every CU
+  // busy whatever the mix of systems
+  b->grid = o.grid_size > 0 ? o.grid_size : cap;
+  (void)total_tiles;
   b->grid = std::max(1, b->grid);
   b->params = make_params(o.tol, o.maxit, o.check_true_residual, o.timeout_ms,
                           problems[0]->wall_khz);
