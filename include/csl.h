@@ -88,6 +88,19 @@ enum {
                                inner products, norms and rotations stay FP64   */
 };
 
+/* How the orthonormal DST-I along an axis is computed (the W of
+ * P^{-1} = W diag(s) W, Section 3).  Both give the same transform up to
+ * rounding. */
+enum {
+    CSL_DST_AUTO = 0,       /* per axis, the faster of FFT and GEMM, timed on
+                               this device the first time a grid shape and
+                               precision is seen in the process            */
+    CSL_DST_FFT = 1,        /* FFT of the odd extension, staged in LDS      */
+    CSL_DST_GEMM = 2        /* product with the dense n x n sine matrix on
+                               the matrix cores, for axes with
+                               15 <= n <= 127; FFT on the other axes        */
+};
+
 typedef struct csl_problem_opts {
     int abar_rule;          /* CSL_ABAR_*                                       */
     int pinv_prec;          /* CSL_PREC_*                                       */
@@ -96,7 +109,8 @@ typedef struct csl_problem_opts {
                                the contiguous axis (0 = default: 2048 FP64,
                                4096 FP32); larger tiles mean fewer phase
                                hand-offs, smaller ones more parallelism       */
-    int reserved[3];
+    int dst_engine;         /* CSL_DST_*                                        */
+    int reserved[2];
 } csl_problem_opts;
 
 typedef struct csl_solve_opts {
@@ -131,6 +145,10 @@ csl_status destroy_problem(csl_problem p);
  * (Lemma 3).  Any pointer may be NULL. */
 csl_status problem_info(csl_problem p, double *abar, double *a_min,
                         double *a_max);
+
+/* Sine-transform engine in use along each axis (CSL_DST_FFT or
+ * CSL_DST_GEMM; entries past the grid's dimension are CSL_DST_FFT). */
+csl_status problem_dst_engines(csl_problem p, int engines[3]);
 
 /* y = A x for the block matrix of Eq. (2); in complex storage
  * y = (K + lambda I) conj(x).  x, y: device, M complex; must not alias. */

@@ -47,7 +47,7 @@ class _Grid(ctypes.Structure):
 class _ProblemOpts(ctypes.Structure):
     _fields_ = [("abar_rule", ctypes.c_int), ("pinv_prec", ctypes.c_int),
                 ("abar", ctypes.c_double), ("tile_elems", ctypes.c_int),
-                ("reserved", ctypes.c_int * 3)]
+                ("dst_engine", ctypes.c_int), ("reserved", ctypes.c_int * 2)]
 
 
 class _SolveOpts(ctypes.Structure):
@@ -90,6 +90,7 @@ def load_library():
                                  ctypes.POINTER(_ProblemOpts), vp, ctypes.POINTER(vp)]
     L.destroy_problem.argtypes = [vp]
     L.problem_info.argtypes = [vp, dp, dp, dp]
+    L.problem_dst_engines.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
     L.apply_A.argtypes = [vp, vp, vp, vp]
     L.apply_Pinv.argtypes = [vp, vp, vp, vp]
     L.minres_solve.argtypes = [vp, vp, vp, ctypes.POINTER(_SolveOpts),
@@ -103,7 +104,8 @@ def load_library():
     L.batch_destroy.argtypes = [vp]
     L.csl_last_error.restype = ctypes.c_char_p
     L.csl_version.restype = ctypes.c_int
-    for fn in ("create_problem", "destroy_problem", "problem_info", "apply_A", "apply_Pinv",
+    for fn in ("create_problem", "destroy_problem", "problem_info", "problem_dst_engines",
+               "apply_A", "apply_Pinv",
                "minres_solve", "minres_adjoint", "batch_create", "batch_solve",
                "batch_destroy"):
         getattr(L, fn).restype = ctypes.c_int
@@ -137,6 +139,8 @@ def _info_dict(i: _SolveInfo) -> dict:
 
 
 _ABAR = {"mean": 0, "geomean": 1, "given": 2}
+_DST = {"auto": 0, "fft": 1, "gemm": 2}
+_DST_NAMES = {1: "fft", 2: "gemm"}
 
 
 class Problem:
@@ -145,7 +149,7 @@ class Problem:
 
     def __init__(self, a, alpha: float, beta: float, lengths=None,
                  abar_rule: str = "mean", abar: float | None = None,
-                 pinv_fp32: bool = False, tile_elems: int = 0):
+                 pinv_fp32: bool = False, tile_elems: int = 0, dst: str = "auto"):
         torch = _torch()
         L = load_library()
         if not (isinstance(a, torch.Tensor) and a.is_cuda and a.dtype == torch.float64):
@@ -168,6 +172,7 @@ class Problem:
         o.pinv_prec = 1 if pinv_fp32 else 0
         o.abar = float(abar) if abar is not None else 0.0
         o.tile_elems = int(tile_elems)
+        o.dst_engine = _DST[dst]
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             _check(L.create_problem(ctypes.byref(g), _ptr(self.a), self.alpha, self.beta,
@@ -176,6 +181,10 @@ class Problem:
         ab, mn, mx = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         _check(L.problem_info(h, ctypes.byref(ab), ctypes.byref(mn), ctypes.byref(mx)))
         self.abar, self.a_min, self.a_max = ab.value, mn.value, mx.value
+        eng = (ctypes.c_int * 3)()
+        _check(L.problem_dst_engines(h, eng))
+        #: sine-transform engine per axis: "fft" or "gemm"
+        self.dst_engines = tuple(_DST_NAMES[eng[k]] for k in range(g.dim))
 
     @property
     def handle(self):

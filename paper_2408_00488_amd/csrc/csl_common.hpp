@@ -85,6 +85,9 @@ struct SysDesc {
   float alpha_f, beta_f, abar_f;
   const double *a;         // nodal coefficient
   const double *F[3];      // face coefficients / h_k^2 of each axis
+  int gemm[3];             // 1: sine transforms along this axis by MFMA matrix product
+  const double *Wm[3];     // padded orthonormal DST-I matrix per axis (FP64), if gemm
+  const float *Wmf[3];     // FP32 copy
   const double *mu[3];     // per-axis eigenvalues of L, FP64
   const float *mu_f[3];    // FP32 copies
   double2 *Tq;             // W_c (A zhat_j)

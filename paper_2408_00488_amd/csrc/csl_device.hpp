@@ -415,6 +415,252 @@ __device__ __forceinline__ double2 stencil_K(const SysDesc &S, const double2 *__
   return stencil_apply<D>(stencil_load<D>(S, u, p, idx));
 }
 
+
+// ---------------------------------------------------------------------------
+// Dense sine-matrix transform on MFMA (lines of n <= 127 points).
+// A chunk of lp complex lines is the real matrix X (np x 2 lp, np = n
+// rounded up to 16; column 2l = Re of line l, 2l+1 = Im) stored in LDS as
+// complex lines of np entries (rows n..np-1 zero).  Y = W X with W the
+// padded orthonormal DST-I matrix (np x np, symmetric, in global memory),
+// on 16x16x4 MFMA tiles: lane l feeds A[l%16][l/16] and B[l/16][l%16];
+// the accumulator row of register r is 4r + l/16 (FP64) or 4(l/16) + r
+// (FP32), its column l%16.
+// ---------------------------------------------------------------------------
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+
+template <typename R> struct Mfma;
+template <> struct Mfma<double> {
+  typedef mfma_d4 acc;
+  static __device__ __forceinline__ acc step(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int r, int lane) { return 4 * r + (lane >> 4); }
+};
+template <> struct Mfma<float> {
+  typedef mfma_f4 acc;
+  static __device__ __forceinline__ acc step(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int r, int lane) { return 4 * (lane >> 4) + r; }
+};
+
+// Y = W X for a chunk of lp lines of padded length np (X, Y in LDS).  The
+// real and imaginary parts of a line are two columns of X; each wave owns
+// 16 x 16 output blocks and streams the K dimension in steps of 4, taking
+// W from the cache hierarchy and X from LDS, so that only a handful of
+// registers are live beside the accumulator.
+template <typename R>
+__device__ void gemm_lines(const Cx<R> *X, Cx<R> *Y, int np, int lp, const R *__restrict__ W) {
+  constexpr int KU = 4;   // K steps in flight
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nrb = np >> 4;
+  const int ncb = (2 * lp + 15) >> 4;
+  const int kq = np >> 2;   // multiple of KU since np is a multiple of 16
+  const R *Xr = reinterpret_cast<const R *>(X);
+  R *Yr = reinterpret_cast<R *>(Y);
+  const int kl = lane >> 4;
+  for (int blk = wave; blk < nrb * ncb; blk += NT / 64) {
+    const int rb = blk / ncb, cb = blk - rb * ncb;
+    const int m = rb * 16 + (lane & 15);
+    const int col = cb * 16 + (lane & 15);
+    const bool valid = col < 2 * lp;
+    const int line = valid ? (col >> 1) : 0, part = col & 1;
+    const R *wrow = W + m * np + kl;
+    const R *xcol = Xr + (line * np + kl) * 2 + part;
+    typename Mfma<R>::acc c = {0, 0, 0, 0};
+    for (int kk = 0; kk < kq; kk += KU) {
+      R a[KU], b[KU];
+#pragma unroll
+      for (int u = 0; u < KU; ++u) {
+        a[u] = wrow[(kk + u) * 4];
+        b[u] = valid ? xcol[(kk + u) * 8] : (R)0;
+      }
+#pragma unroll
+      for (int u = 0; u < KU; ++u) c = Mfma<R>::step(a[u], b[u], c);
+    }
+    if (valid) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        Yr[(line * np + rb * 16 + Mfma<R>::row(r, lane)) * 2 + part] = c[r];
+    }
+  }
+  __syncthreads();
+}
+
+// Transform engines: the same tile code drives the LDS FFT (FftEng) or the
+// MFMA sine-matrix product (GemmEng).
+template <typename R, int LDSB> struct FftEng {
+  template <int U, class Load>
+  static __device__ __forceinline__ void fill(Cx<R> *buf, const LineTile &t, Load &&load) {
+    lines_fill<R, U>(buf, t, load);
+  }
+  template <int U, class Pre, class Make>
+  static __device__ __forceinline__ void fill2(Cx<R> *buf, const LineTile &t, Pre &&pre,
+                                               Make &&make) {
+    lines_fill2<R, U>(buf, t, pre, make);
+  }
+  static __device__ __forceinline__ Cx<R> *transform(Cx<R> *buf, const LineTile &t,
+                                                     const Cx<R> *twl, const R *) {
+    fft_lines<R, LDSB>(buf, t.nl, t.lg, twl);
+    return buf;
+  }
+  template <class Scale>
+  static __device__ __forceinline__ double scale_transform(Cx<R> *buf, const LineTile &t,
+                                                           const Cx<R> *twl, const R *,
+                                                           Scale &&sc, Cx<R> **out) {
+    const double acc = lines_scale_extend<R>(buf, t, sc);
+    fft_lines<R, LDSB>(buf, t.nl, t.lg, twl);
+    *out = buf;
+    return acc;
+  }
+  template <class Store>
+  static __device__ __forceinline__ void store(const Cx<R> *out, const LineTile &t, Store &&st) {
+    lines_store<R>(out, t, st);
+  }
+  template <int U, class Pre, class Post>
+  static __device__ __forceinline__ void store2(const Cx<R> *out, const LineTile &t, Pre &&pre,
+                                                Post &&post) {
+    lines_store2<R, U>(out, t, pre, post);
+  }
+};
+
+__device__ __forceinline__ int gemm_np(int n) { return (n + 15) & ~15; }
+
+template <typename R, int LDSB> struct GemmEng {
+  template <int U, class Load>
+  static __device__ __forceinline__ void fill(Cx<R> *buf, const LineTile &t, Load &&load) {
+    const int np = gemm_np(t.n);
+    const int total = tile_elems(t);
+    const int tid = threadIdx.x;
+    for (int e0 = 0; e0 < total; e0 += NT * U) {
+      Cx<R> v[U];
+      int pos[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * NT + tid;
+        pos[u] = -1;
+        int l, r;
+        if (e < total && split_elem(t, e, l, r)) {
+          v[u] = load(l, r, t.base + l * t.lstride + r * t.stride);
+          pos[u] = l * np + r;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (pos[u] >= 0) buf[pos[u]] = v[u];
+    }
+    pad(buf, t, np);
+  }
+  template <int U, class Pre, class Make>
+  static __device__ __forceinline__ void fill2(Cx<R> *buf, const LineTile &t, Pre &&pre,
+                                               Make &&make) {
+    using PT = decltype(pre(0, 0, 0));
+    const int np = gemm_np(t.n);
+    const int total = tile_elems(t);
+    const int tid = threadIdx.x;
+    for (int e0 = 0; e0 < total; e0 += NT * U) {
+      PT pv[U];
+      int ll[U], rr[U], pp[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * NT + tid;
+        ll[u] = -1;
+        int l, r;
+        if (e < total && split_elem(t, e, l, r)) {
+          ll[u] = l;
+          rr[u] = r;
+          pp[u] = t.base + l * t.lstride + r * t.stride;
+          pv[u] = pre(l, r, pp[u]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (ll[u] >= 0) buf[ll[u] * np + rr[u]] = make(ll[u], rr[u], pp[u], pv[u]);
+    }
+    pad(buf, t, np);
+  }
+  // zero the padding rows and the unused lines of the chunk
+  static __device__ __forceinline__ void pad(Cx<R> *buf, const LineTile &t, int np) {
+    const int padr = np - t.n;
+    for (int e = threadIdx.x; e < t.lp * np; e += NT) {
+      const int l = e / np, r = e - l * np;
+      if (l >= t.nl || r >= t.n) buf[e] = Cx<R>{0, 0};
+    }
+    (void)padr;
+    __syncthreads();
+  }
+  static __device__ __forceinline__ Cx<R> *transform(Cx<R> *buf, const LineTile &t,
+                                                     const Cx<R> *, const R *W) {
+    const int np = gemm_np(t.n);
+    Cx<R> *Y = buf + t.lp * np;
+    gemm_lines<R>(buf, Y, np, t.lp, W);
+    return Y;
+  }
+  template <class Scale>
+  static __device__ __forceinline__ double scale_transform(Cx<R> *buf, const LineTile &t,
+                                                           const Cx<R> *, const R *W, Scale &&sc,
+                                                           Cx<R> **out) {
+    const int np = gemm_np(t.n);
+    Cx<R> *Y = buf + t.lp * np;
+    double acc = 0.0;
+    const int total = tile_elems(t);
+    for (int e = threadIdx.x; e < total; e += NT) {
+      int l, r;
+      if (split_elem(t, e, l, r)) {
+        Cx<R> v = Y[l * np + r];
+        const R s = sc(l, r);
+        acc += (double)s * ((double)v.x * (double)v.x + (double)v.y * (double)v.y);
+        v.x *= s;
+        v.y *= s;
+        Y[l * np + r] = v;
+      }
+    }
+    __syncthreads();
+    gemm_lines<R>(Y, buf, np, t.lp, W);
+    *out = buf;
+    return acc;
+  }
+  template <class Store>
+  static __device__ __forceinline__ void store(const Cx<R> *out, const LineTile &t, Store &&st) {
+    const int np = gemm_np(t.n);
+    const int total = tile_elems(t);
+    for (int e = threadIdx.x; e < total; e += NT) {
+      int l, r;
+      if (split_elem(t, e, l, r)) st(l, r, t.base + l * t.lstride + r * t.stride, out[l * np + r]);
+    }
+    __syncthreads();
+  }
+  template <int U, class Pre, class Post>
+  static __device__ __forceinline__ void store2(const Cx<R> *out, const LineTile &t, Pre &&pre,
+                                                Post &&post) {
+    using PT = decltype(pre(0));
+    const int np = gemm_np(t.n);
+    const int total = tile_elems(t);
+    const int tid = threadIdx.x;
+    for (int e0 = 0; e0 < total; e0 += NT * U) {
+      PT pv[U];
+      Cx<R> vv[U];
+      int pp[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * NT + tid;
+        pp[u] = -1;
+        int l, r;
+        if (e < total && split_elem(t, e, l, r)) {
+          pp[u] = t.base + l * t.lstride + r * t.stride;
+          pv[u] = pre(pp[u]);
+          vv[u] = out[l * np + r];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (pp[u] >= 0) post(pp[u], vv[u], pv[u]);
+    }
+    __syncthreads();
+  }
+};
+
 // Multi-index of element r of contiguous-axis row `row`.
 template <int D>
 __device__ __forceinline__ void row_index(const SysDesc &S, int row, int r, int (&idx)[3]) {

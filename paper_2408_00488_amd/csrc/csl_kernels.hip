@@ -22,9 +22,10 @@ __device__ __forceinline__ Cx<R> to_cx(double2 v) {
 //           storage of the block product), partial delta_j = <zhat_j, q>,
 //           Tq = W_c q.
 // ---------------------------------------------------------------------------
-template <int D, int LDSB>
+template <int D, int LDSB, class E>
 __device__ void tile_X(const SysDesc &S, const IOPtr &io, int iter, int tile, char *smem,
                        double *red) {
+  const double *Wm = S.Wm[D - 1];
   Cx<double> *buf = reinterpret_cast<Cx<double> *>(smem);
   Cx<double> *twl = reinterpret_cast<Cx<double> *>(smem + LDSB);
   load_twiddles<double>(twl, S.lg[D - 1]);
@@ -36,7 +37,7 @@ __device__ void tile_X(const SysDesc &S, const IOPtr &io, int iter, int tile, ch
     if (iter == 0) {
       const double2 *__restrict__ f = io.f;
       double2 *__restrict__ X = io.x;
-      lines_fill<double>(buf, t, [&](int, int, int p) {
+      E::template fill<4>(buf, t, [&](int, int, int p) {
         const double2 v = f[p];
         acc += v.x * v.x + v.y * v.y;
         X[p] = make_double2(0.0, 0.0);
@@ -46,7 +47,7 @@ __device__ void tile_X(const SysDesc &S, const IOPtr &io, int iter, int tile, ch
     } else {
       const double2 *__restrict__ zj = S.Z[iter & 1];
       const double al = S.alpha, be = S.beta;
-      lines_fill2<double, 2>(
+      E::template fill2<2>(
           buf, t,
           [&](int l, int r, int p) {
             int idx[3];
@@ -63,8 +64,8 @@ __device__ void tile_X(const SysDesc &S, const IOPtr &io, int iter, int tile, ch
           });
       out = reinterpret_cast<Cx<double> *>(S.Tq);
     }
-    fft_lines<double, LDSB>(buf, t.nl, t.lg, twl);
-    lines_store<double>(buf, t, [&](int, int, int p, Cx<double> v) { out[p] = v; });
+    const Cx<double> *o = E::transform(buf, t, twl, Wm);
+    E::store(o, t, [&](int, int, int p, Cx<double> v) { out[p] = v; });
   }
   const double s = wg_sum(acc, red);
   if (threadIdx.x == 0) S.part[tile] = s;
@@ -79,10 +80,12 @@ __device__ void tile_X(const SysDesc &S, const IOPtr &io, int iter, int tile, ch
 //   Last strided pass (2-D K_Y, 3-D K_Y1I): output T' and the partial of
 //     gamma_{j+1}^2 = <z_{j+1}, v_{j+1}> = <T', Tv_{j+1}> (W_c orthogonal).
 // ---------------------------------------------------------------------------
-template <typename R, int D, int LDSB>
+template <typename R, int D, int LDSB, class E>
 __device__ void tile_Y(const SysDesc &S, int kind, int iter, int tile, char *smem, double *red) {
   Cx<R> *buf = reinterpret_cast<Cx<R> *>(smem);
   const int ax = (kind == K_Y) ? 0 : 1;
+  const R *Wm = (sizeof(R) == 8) ? reinterpret_cast<const R *>(S.Wm[ax])
+                                 : reinterpret_cast<const R *>(S.Wmf[ax]);
   Cx<R> *twl = reinterpret_cast<Cx<R> *>(smem + LDSB);
   load_twiddles<R>(twl, S.lg[ax]);
   Cx<R> *T = reinterpret_cast<Cx<R> *>(S.T);
@@ -95,7 +98,7 @@ __device__ void tile_Y(const SysDesc &S, int kind, int iter, int tile, char *sme
   if (first) {
     if (j == 0) {
       const double2 *__restrict__ v1 = S.Tv[1];
-      lines_fill<R>(buf, t, [&](int, int, int p) { return to_cx<R>(v1[p]); });
+      E::template fill<4>(buf, t, [&](int, int, int p) { return to_cx<R>(v1[p]); });
     } else {
       const Ctl *C = S.ctl;
       const double g = ld_ctl(&C->gamma), go = ld_ctl(&C->gamma_old);
@@ -108,7 +111,7 @@ __device__ void tile_Y(const SysDesc &S, int kind, int iter, int tile, char *sme
       struct In3 {
         double2 q, v1, v0;
       };
-      lines_fill2<R, 4>(
+      E::template fill2<4>(
           buf, t,
           [&](int, int, int p) {
             In3 in;
@@ -125,9 +128,9 @@ __device__ void tile_Y(const SysDesc &S, int kind, int iter, int tile, char *sme
           });
     }
   } else {
-    lines_fill<R>(buf, t, [&](int, int, int p) { return T[p]; });
+    E::template fill<4>(buf, t, [&](int, int, int p) { return T[p]; });
   }
-  fft_lines<R, LDSB>(buf, t.nl, t.lg, twl);
+  Cx<R> *o = E::transform(buf, t, twl, Wm);
   if (kind == K_Y) {
     const R ab = (sizeof(R) == 8) ? (R)S.abar : (R)S.abar_f;
     const R al = (sizeof(R) == 8) ? (R)S.alpha : (R)S.alpha_f;
@@ -146,7 +149,7 @@ __device__ void tile_Y(const SysDesc &S, int kind, int iter, int tile, char *sme
     }
     // gamma_{j+1}^2 = <P^{-1} v, v> = sum_k s_k |(W v)_k|^2: here W v is the
     // fully transformed Lanczos vector, so its partial comes from this pass.
-    gacc += lines_scale_extend<R>(buf, t, [&](int l, int r) -> R {
+    gacc += E::scale_transform(buf, t, twl, Wm, [&](int l, int r) -> R {
       R lam;
       if (D == 2) {
         lam = mu0[r] + mu1[t.c0 + l];
@@ -155,10 +158,9 @@ __device__ void tile_Y(const SysDesc &S, int kind, int iter, int tile, char *sme
       }
       const R sh = ab * lam + al;
       return (R)1 / sqrt(sh * sh + be * be);
-    });
-    fft_lines<R, LDSB>(buf, t.nl, t.lg, twl);
+    }, &o);
   }
-  lines_store<R>(buf, t, [&](int, int, int p, Cx<R> v) { T[p] = v; });
+  E::store(o, t, [&](int, int, int p, Cx<R> v) { T[p] = v; });
   }
   if (kind == K_Y) {
     const double sg = wg_sum(gacc, red);
@@ -172,8 +174,10 @@ __device__ void tile_Y(const SysDesc &S, int kind, int iter, int tile, char *sme
 //   w_{j+1} = (zhat_j - e3 w_{j-1} - e2 w_j) / e1,  x_j = x_{j-1} + ceta w_{j+1}
 // with x held as its conjugate (the user's z).
 // ---------------------------------------------------------------------------
-template <typename R, int D, int LDSB>
+template <typename R, int D, int LDSB, class E>
 __device__ void tile_Z(const SysDesc &S, const IOPtr &io, int iter, int tile, char *smem) {
+  const R *Wm = (sizeof(R) == 8) ? reinterpret_cast<const R *>(S.Wm[D - 1])
+                                 : reinterpret_cast<const R *>(S.Wmf[D - 1]);
   Cx<R> *buf = reinterpret_cast<Cx<R> *>(smem);
   Cx<R> *twl = reinterpret_cast<Cx<R> *>(smem + LDSB);
   load_twiddles<R>(twl, S.lg[D - 1]);
@@ -187,10 +191,10 @@ __device__ void tile_Z(const SysDesc &S, const IOPtr &io, int iter, int tile, ch
   const bool store_z = (g != 0.0);
   const double ig = store_z ? 1.0 / g : 0.0;
   double2 *__restrict__ znew = S.Z[(j + 1) & 1];
-  lines_fill<R, 8>(buf, t, [&](int, int, int p) { return T[p]; });
-  fft_lines<R, LDSB>(buf, t.nl, t.lg, twl);
+  E::template fill<8>(buf, t, [&](int, int, int p) { return T[p]; });
+  const Cx<R> *o = E::transform(buf, t, twl, Wm);
   if (j == 0) {
-    lines_store<R>(buf, t, [&](int, int, int p, Cx<R> v) {
+    E::store(o, t, [&](int, int, int p, Cx<R> v) {
       znew[p] = make_double2((double)v.x * ig, (double)v.y * ig);
     });
     continue;
@@ -206,8 +210,8 @@ __device__ void tile_Z(const SysDesc &S, const IOPtr &io, int iter, int tile, ch
   struct In4 {
     double2 z, w0, w1, x;
   };
-  lines_store2<R, 4>(
-      buf, t,
+  E::template store2<4>(
+      o, t,
       [&](int p) {
         In4 in;
         in.z = zj[p];
@@ -257,18 +261,30 @@ template <int LDSB>
 __device__ void process_tile(const SysDesc &S, const IOPtr &io, int kind, int iter, int tile,
                              char *smem, double *red) {
   const bool d3 = (S.d == 3);
+  const int ax = (kind == K_X || kind == K_Z) ? S.d - 1 : (kind == K_Y ? 0 : 1);
+  const bool g = S.gemm[ax] != 0;
+  typedef FftEng<double, LDSB> F64;
+  typedef FftEng<float, LDSB> F32;
+  typedef GemmEng<double, LDSB> G64;
+  typedef GemmEng<float, LDSB> G32;
   switch (kind) {
     case K_X:
-      if (d3) tile_X<3, LDSB>(S, io, iter, tile, smem, red);
-      else tile_X<2, LDSB>(S, io, iter, tile, smem, red);
+      if (d3) g ? tile_X<3, LDSB, G64>(S, io, iter, tile, smem, red)
+                : tile_X<3, LDSB, F64>(S, io, iter, tile, smem, red);
+      else g ? tile_X<2, LDSB, G64>(S, io, iter, tile, smem, red)
+             : tile_X<2, LDSB, F64>(S, io, iter, tile, smem, red);
       break;
     case K_Z:
       if (S.prec) {
-        if (d3) tile_Z<float, 3, LDSB>(S, io, iter, tile, smem);
-        else tile_Z<float, 2, LDSB>(S, io, iter, tile, smem);
+        if (d3) g ? tile_Z<float, 3, LDSB, G32>(S, io, iter, tile, smem)
+                  : tile_Z<float, 3, LDSB, F32>(S, io, iter, tile, smem);
+        else g ? tile_Z<float, 2, LDSB, G32>(S, io, iter, tile, smem)
+               : tile_Z<float, 2, LDSB, F32>(S, io, iter, tile, smem);
       } else {
-        if (d3) tile_Z<double, 3, LDSB>(S, io, iter, tile, smem);
-        else tile_Z<double, 2, LDSB>(S, io, iter, tile, smem);
+        if (d3) g ? tile_Z<double, 3, LDSB, G64>(S, io, iter, tile, smem)
+                  : tile_Z<double, 3, LDSB, F64>(S, io, iter, tile, smem);
+        else g ? tile_Z<double, 2, LDSB, G64>(S, io, iter, tile, smem)
+               : tile_Z<double, 2, LDSB, F64>(S, io, iter, tile, smem);
       }
       break;
     case K_PR:
@@ -277,11 +293,15 @@ __device__ void process_tile(const SysDesc &S, const IOPtr &io, int kind, int it
       break;
     default:
       if (S.prec) {
-        if (d3) tile_Y<float, 3, LDSB>(S, kind, iter, tile, smem, red);
-        else tile_Y<float, 2, LDSB>(S, kind, iter, tile, smem, red);
+        if (d3) g ? tile_Y<float, 3, LDSB, G32>(S, kind, iter, tile, smem, red)
+                  : tile_Y<float, 3, LDSB, F32>(S, kind, iter, tile, smem, red);
+        else g ? tile_Y<float, 2, LDSB, G32>(S, kind, iter, tile, smem, red)
+               : tile_Y<float, 2, LDSB, F32>(S, kind, iter, tile, smem, red);
       } else {
-        if (d3) tile_Y<double, 3, LDSB>(S, kind, iter, tile, smem, red);
-        else tile_Y<double, 2, LDSB>(S, kind, iter, tile, smem, red);
+        if (d3) g ? tile_Y<double, 3, LDSB, G64>(S, kind, iter, tile, smem, red)
+                  : tile_Y<double, 3, LDSB, F64>(S, kind, iter, tile, smem, red);
+        else g ? tile_Y<double, 2, LDSB, G64>(S, kind, iter, tile, smem, red)
+               : tile_Y<double, 2, LDSB, F64>(S, kind, iter, tile, smem, red);
       }
       break;
   }
@@ -291,7 +311,7 @@ __device__ void process_tile(const SysDesc &S, const IOPtr &io, int kind, int it
 // Stand-alone P^{-1}: rows forward (x -> T), strided passes, rows inverse
 // (T -> y), all in the preconditioner precision R.
 // ---------------------------------------------------------------------------
-template <typename R, int D, int LDSB>
+template <typename R, int D, int LDSB, class E>
 __device__ void tile_pinv(const SysDesc &S, int pass, const double2 *x, double2 *y, int tile,
                           char *smem) {
   Cx<R> *buf = reinterpret_cast<Cx<R> *>(smem);
@@ -302,9 +322,11 @@ __device__ void tile_pinv(const SysDesc &S, int pass, const double2 *x, double2 
   const LineTile t = line_tile(S, ax, lp, tile);
   Cx<R> *twl = reinterpret_cast<Cx<R> *>(smem + LDSB);
   load_twiddles<R>(twl, t.lg);
-  if (pass == 0) lines_fill<R>(buf, t, [&](int, int, int p) { return to_cx<R>(x[p]); });
-  else lines_fill<R>(buf, t, [&](int, int, int p) { return T[p]; });
-  fft_lines<R, LDSB>(buf, t.nl, t.lg, twl);
+  const R *Wm = (sizeof(R) == 8) ? reinterpret_cast<const R *>(S.Wm[ax])
+                                 : reinterpret_cast<const R *>(S.Wmf[ax]);
+  if (pass == 0) E::template fill<4>(buf, t, [&](int, int, int p) { return to_cx<R>(x[p]); });
+  else E::template fill<4>(buf, t, [&](int, int, int p) { return T[p]; });
+  Cx<R> *o = E::transform(buf, t, twl, Wm);
   if (pass == 2) {
     const R ab = (sizeof(R) == 8) ? (R)S.abar : (R)S.abar_f;
     const R al = (sizeof(R) == 8) ? (R)S.alpha : (R)S.alpha_f;
@@ -321,7 +343,7 @@ __device__ void tile_pinv(const SysDesc &S, int pass, const double2 *x, double2 
       mu1 = reinterpret_cast<const R *>(S.mu_f[1]);
       mu2 = reinterpret_cast<const R *>(S.mu_f[2]);
     }
-    lines_scale_extend<R>(buf, t, [&](int l, int r) -> R {
+    (void)E::scale_transform(buf, t, twl, Wm, [&](int l, int r) -> R {
       R lam;
       if (D == 2) {
         lam = mu0[r] + mu1[t.c0 + l];
@@ -330,15 +352,14 @@ __device__ void tile_pinv(const SysDesc &S, int pass, const double2 *x, double2 
       }
       const R sh = ab * lam + al;
       return (R)1 / sqrt(sh * sh + be * be);
-    });
-    fft_lines<R, LDSB>(buf, t.nl, t.lg, twl);
+    }, &o);
   }
   if (pass == 4) {
-    lines_store<R>(buf, t, [&](int, int, int p, Cx<R> v) {
+    E::store(o, t, [&](int, int, int p, Cx<R> v) {
       y[p] = make_double2((double)v.x, (double)v.y);
     });
   } else {
-    lines_store<R>(buf, t, [&](int, int, int p, Cx<R> v) { T[p] = v; });
+    E::store(o, t, [&](int, int, int p, Cx<R> v) { T[p] = v; });
   }
 }
 
@@ -508,9 +529,9 @@ __device__ void epilogue(const SysDesc &S, const SolveParams &P, int kind, int i
 // workgroups exit when every system is done or the time limit passes.
 // ---------------------------------------------------------------------------
 template <int LDSB>
-__global__ __launch_bounds__(NT) void solve_kernel(const SysDesc *__restrict__ sys,
-                                                   const IOPtr *__restrict__ io, IOPtr io0,
-                                                   int nsys, SolveParams P, Glob *G) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void solve_kernel(
+    const SysDesc *__restrict__ sys, const IOPtr *__restrict__ io, IOPtr io0, int nsys,
+    SolveParams P, Glob *G) {
   extern __shared__ __align__(16) char smem[];
   __shared__ double red[NT / 64];
   __shared__ int sh_s, sh_tile, sh_kind, sh_iter, sh_last;
@@ -649,7 +670,10 @@ template <typename R, int D, int LDSB>
 __global__ __launch_bounds__(NT) void pinv_pass_kernel(const SysDesc *__restrict__ sys, int pass,
                                                        const double2 *x, double2 *y) {
   extern __shared__ __align__(16) char smem[];
-  tile_pinv<R, D, LDSB>(*sys, pass, x, y, blockIdx.x, smem);
+  const SysDesc &S = *sys;
+  const int ax = (pass == 0 || pass == 4) ? D - 1 : (pass == 2 ? 0 : 1);
+  if (S.gemm[ax]) tile_pinv<R, D, LDSB, GemmEng<R, LDSB>>(S, pass, x, y, blockIdx.x, smem);
+  else tile_pinv<R, D, LDSB, FftEng<R, LDSB>>(S, pass, x, y, blockIdx.x, smem);
 }
 
 // Face coefficients of axis ax divided by h_ax^2: harmonic mean of the two

@@ -9,6 +9,9 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "csl.h"
@@ -66,6 +69,31 @@ int ilog2(int v) {
   while ((1 << l) < v) ++l;
   return l;
 }
+
+// Axes whose sine transform may run as a dense matrix product on the matrix
+// cores: the padded length np = n + 1 keeps the two LDS operands of a chunk
+// (2 lp np elements) inside the FFT's lp L budget, L = 2(n + 1), and
+// n <= 127 keeps the n^2 products per line within reach of the FFT's cost.
+bool gemm_eligible(int n) { return n >= 15 && n <= 127; }
+int gemm_pad(int n) { return (n + 15) & ~15; }
+
+// Orthonormal DST-I matrix sqrt(2/(n+1)) sin(pi (m+1)(k+1)/(n+1)), zero
+// padded to np x np; the angle is reduced exactly in integers first.
+void sine_matrix(int n, int np, std::vector<double> &W) {
+  W.assign((size_t)np * np, 0.0);
+  const int N2 = 2 * (n + 1);
+  const double sc = std::sqrt(2.0 / (n + 1));
+  for (int m = 0; m < n; ++m)
+    for (int k = 0; k < n; ++k) {
+      const int j = ((m + 1) * (k + 1)) % N2;
+      W[(size_t)m * np + k] = sc * std::sin(M_PI * (double)j / (double)(n + 1));
+    }
+}
+
+// Engine choices made by timing, per device and grid shape and precision.
+typedef std::tuple<int, int, int, int, int, int> ShapeKey;   // dev, d, n0, n1, n2, prec
+std::map<ShapeKey, int> g_engine_cache;                      // value: GEMM axis mask
+std::mutex g_engine_mu;
 
 }  // namespace
 
@@ -224,6 +252,64 @@ void free_problem(csl_problem p) {
   delete p;
 }
 
+// P^{-1} x as its sequence of transform passes: 0 rows forward, 1 axis-1
+// forward (3-D), 2 axis 0 with the mode scaling, 3 axis-1 inverse (3-D),
+// 4 rows inverse.
+hipError_t launch_pinv_all(csl_problem p, const double2 *x, double2 *y, hipStream_t s) {
+  const SysDesc &h = p->h;
+  const int nrow = (h.rows + h.lpt_z - 1) / h.lpt_z;
+  const int pass[5] = {0, 1, 2, 3, 4};
+  for (int k = 0; k < 5; ++k) {
+    if (h.d == 2 && (pass[k] == 1 || pass[k] == 3)) continue;
+    const int nt = pass[k] == 0 || pass[k] == 4 ? nrow
+                   : pass[k] == 2             ? h.ntile[K_Y]
+                   : pass[k] == 1             ? h.ntile[K_Y1]
+                                              : h.ntile[K_Y1I];
+    const hipError_t e = launch_pinv_pass(p->d_desc, h.d, h.prec, pass[k], nt, p->smem, x, y, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Choose the matrix-core axes by timing: P^{-1} applications with every
+// admissible subset of the eligible axes, the fastest kept (the FFT wins
+// ties).  Runs on p's workspaces and leaves p's device descriptor to be
+// rewritten by the caller.
+csl_status tune_engines(csl_problem p, int elig, hipStream_t s, int *best_mask) {
+  *best_mask = 0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(CSL_ERR_HIP, "hipEventCreate failed");
+  }
+  SysDesc h = p->h;
+  const int reps = std::max(3, std::min(50, (1 << 22) / std::max(1, h.M)));
+  hipError_t err = hipMemsetAsync(p->ytmp, 0, sizeof(double2) * (size_t)h.M, s);
+  float best = INFINITY;
+  for (int mask = 0; mask < 8 && err == hipSuccess; ++mask) {
+    if (mask & ~elig) continue;
+    for (int ax = 0; ax < 3; ++ax) h.gemm[ax] = (mask >> ax) & 1;
+    err = hipMemcpyAsync(p->d_desc, &h, sizeof(SysDesc), hipMemcpyHostToDevice, s);
+    for (int r = 0; r < 2 && err == hipSuccess; ++r) err = launch_pinv_all(p, p->ytmp, p->gtmp, s);
+    if (err == hipSuccess) err = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && err == hipSuccess; ++r)
+      err = launch_pinv_all(p, p->ytmp, p->gtmp, s);
+    if (err == hipSuccess) err = hipEventRecord(e1, s);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    if (err == hipSuccess && ms < best) {
+      best = ms;
+      *best_mask = mask;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess) return fail(CSL_ERR_HIP, std::string("engine timing: ") + hipGetErrorString(err));
+  return CSL_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -350,6 +436,15 @@ csl_status create_problem(const csl_grid *grid, const double *a_nodal, double al
   const size_t o_ytmp = take(vec);
   const size_t o_gtmp = take(vec);
   const size_t o_apart = take(sizeof(double) * 2 * p->adj_nblk);
+  size_t o_w[3] = {0, 0, 0}, o_wf[3] = {0, 0, 0};
+  int elig = 0;
+  for (int ax = 0; ax < h.d; ++ax) {
+    if (!gemm_eligible(h.n[ax])) continue;
+    elig |= 1 << ax;
+    const size_t np2 = (size_t)gemm_pad(h.n[ax]) * gemm_pad(h.n[ax]);
+    o_w[ax] = take(sizeof(double) * np2);
+    o_wf[ax] = take(sizeof(float) * np2);
+  }
   hipError_t e = hipMalloc(&p->mem, off);
   if (e != hipSuccess) {
     delete p;
@@ -380,6 +475,11 @@ csl_status create_problem(const csl_grid *grid, const double *a_nodal, double al
   p->ytmp = (double2 *)(base + o_ytmp);
   p->gtmp = (double2 *)(base + o_gtmp);
   p->adj_part = (double *)(base + o_apart);
+  for (int ax = 0; ax < 3; ++ax) {
+    h.gemm[ax] = 0;
+    h.Wm[ax] = (elig >> ax & 1) ? (const double *)(base + o_w[ax]) : nullptr;
+    h.Wmf[ax] = (elig >> ax & 1) ? (const float *)(base + o_wf[ax]) : nullptr;
+  }
 
   // per-axis eigenvalues of L: (4/h^2) sin^2(k pi / (2(n+1)))
   std::vector<double> mu(nmu);
@@ -408,6 +508,19 @@ csl_status create_problem(const csl_grid *grid, const double *a_nodal, double al
   PCHK(hipMemcpyAsync(d_a, a_nodal, sizeof(double) * h.M, hipMemcpyDeviceToDevice, s));
   PCHK(hipMemcpyAsync(d_mu, mu.data(), sizeof(double) * nmu, hipMemcpyHostToDevice, s));
   PCHK(hipMemcpyAsync(d_muf, muf.data(), sizeof(float) * nmu, hipMemcpyHostToDevice, s));
+  std::vector<double> Wt[3];
+  std::vector<float> Wtf[3];
+  for (int ax = 0; ax < h.d; ++ax) {
+    if (!(elig >> ax & 1)) continue;
+    const int np = gemm_pad(h.n[ax]);
+    sine_matrix(h.n[ax], np, Wt[ax]);
+    Wtf[ax].resize(Wt[ax].size());
+    for (size_t i = 0; i < Wt[ax].size(); ++i) Wtf[ax][i] = (float)Wt[ax][i];
+    PCHK(hipMemcpyAsync((void *)h.Wm[ax], Wt[ax].data(), sizeof(double) * Wt[ax].size(),
+                        hipMemcpyHostToDevice, s));
+    PCHK(hipMemcpyAsync((void *)h.Wmf[ax], Wtf[ax].data(), sizeof(float) * Wtf[ax].size(),
+                        hipMemcpyHostToDevice, s));
+  }
   PCHK(hipMemcpyAsync(p->d_desc, &h, sizeof(SysDesc), hipMemcpyHostToDevice, s));
   PCHK(launch_coef_stats(p->d_desc, h.d, h.M, p->stats_part, p->stats_nblk, p->stats, s));
   for (int ax = 0; ax < h.d; ++ax)
@@ -450,6 +563,37 @@ csl_status create_problem(const csl_grid *grid, const double *a_nodal, double al
   p->h = h;
   PCHK(hipMemcpyAsync(p->d_desc, &p->h, sizeof(SysDesc), hipMemcpyHostToDevice, s));
   PCHK(hipStreamSynchronize(s));
+  if (o.dst_engine < CSL_DST_AUTO || o.dst_engine > CSL_DST_GEMM) {
+    free_problem(p);
+    return fail(CSL_ERR_ARG, "unknown sine-transform engine");
+  }
+  int mask = 0;
+  if (o.dst_engine == CSL_DST_GEMM) {
+    mask = elig;
+  } else if (o.dst_engine == CSL_DST_AUTO && elig) {
+    const ShapeKey key{dev, h.d, h.n[0], h.n[1], h.n[2], h.prec};
+    bool have = false;
+    {
+      std::lock_guard<std::mutex> lk(g_engine_mu);
+      auto it = g_engine_cache.find(key);
+      if (it != g_engine_cache.end()) {
+        mask = it->second;
+        have = true;
+      }
+    }
+    if (!have) {
+      const csl_status st = tune_engines(p, elig, s, &mask);
+      if (st != CSL_OK) {
+        free_problem(p);
+        return st;
+      }
+      std::lock_guard<std::mutex> lk(g_engine_mu);
+      g_engine_cache[key] = mask;
+    }
+  }
+  for (int ax = 0; ax < 3; ++ax) p->h.gemm[ax] = (mask >> ax) & 1;
+  PCHK(hipMemcpyAsync(p->d_desc, &p->h, sizeof(SysDesc), hipMemcpyHostToDevice, s));
+  PCHK(hipStreamSynchronize(s));
   int bpc = 0;
   PCHK(solve_occupancy(p->smem, &bpc));
   const int cap = std::max(1, bpc) * p->cus;
@@ -473,6 +617,12 @@ csl_status problem_info(csl_problem p, double *abar, double *a_min, double *a_ma
   return CSL_OK;
 }
 
+csl_status problem_dst_engines(csl_problem p, int engines[3]) {
+  if (!p || !engines) return fail(CSL_ERR_ARG, "NULL argument");
+  for (int ax = 0; ax < 3; ++ax) engines[ax] = p->h.gemm[ax] ? CSL_DST_GEMM : CSL_DST_FFT;
+  return CSL_OK;
+}
+
 csl_status apply_A(csl_problem p, const double *x, double *y, hipStream_t s) {
   if (!p || !x || !y) return fail(CSL_ERR_ARG, "NULL argument");
   if (x == y) return fail(CSL_ERR_ARG, "apply_A: x and y must not alias");
@@ -482,20 +632,7 @@ csl_status apply_A(csl_problem p, const double *x, double *y, hipStream_t s) {
 
 csl_status apply_Pinv(csl_problem p, const double *x, double *y, hipStream_t s) {
   if (!p || !x || !y) return fail(CSL_ERR_ARG, "NULL argument");
-  const SysDesc &h = p->h;
-  const double2 *xi = (const double2 *)x;
-  double2 *yo = (double2 *)y;
-  // passes: 0 rows forward, 1 axis-1 forward, 2 axis 0 with scaling,
-  // 3 axis-1 inverse, 4 rows inverse
-  std::vector<std::pair<int, int>> passes;
-  const int nrow = (h.rows + h.lpt_z - 1) / h.lpt_z;
-  passes.push_back({0, nrow});
-  if (h.d == 3) passes.push_back({1, h.ntile[K_Y1]});
-  passes.push_back({2, h.ntile[K_Y]});
-  if (h.d == 3) passes.push_back({3, h.ntile[K_Y1I]});
-  passes.push_back({4, nrow});
-  for (auto &pp : passes)
-    HIPCHK(launch_pinv_pass(p->d_desc, h.d, h.prec, pp.first, pp.second, p->smem, xi, yo, s));
+  HIPCHK(launch_pinv_all(p, (const double2 *)x, (double2 *)y, s));
   return CSL_OK;
 }
 
