@@ -44,14 +44,15 @@ template <typename R, int LDSB> struct MaxElts {
 // stages; each stage reads all of its inputs into registers, synchronises,
 // and writes the outputs in place.  Output is in natural order.
 // ---------------------------------------------------------------------------
-// LDS bytes reserved after the line buffer for the twiddles of one length.
-constexpr int TW_LDS_BYTES = 8192;
+// LDS bytes reserved after a line buffer of LDSB bytes for the twiddles of
+// one length: L/4 entries, L <= 1024 with a 32 KiB buffer, L <= 2048 else.
+constexpr int tw_lds_bytes(int ldsb) { return ldsb <= 32768 ? 4096 : 8192; }
 
 // Stage exp(-2 pi i m / L), m < L/4, into LDS: every radix-4 stage of a
 // length-L Stockham FFT uses w1 = exp(-2 pi i k / (4 Ns)), k < Ns, which is
 // entry k L / (4 Ns) < L/4 of that table.
 template <typename R>
-__device__ void load_twiddles(Cx<R> *twl, int lg) {
+__device__ __forceinline__ void load_twiddles(Cx<R> *twl, int lg) {
   const Cx<R> *tw = twiddles<R>();
   const int q = (1 << lg) >> 2;
   const int step = TWN >> lg;
@@ -60,7 +61,7 @@ __device__ void load_twiddles(Cx<R> *twl, int lg) {
 }
 
 template <typename R, int LDSB>
-__device__ void fft_lines(Cx<R> *buf, int nl, int lg, const Cx<R> *twl) {
+__device__ __forceinline__ void fft_lines(Cx<R> *buf, int nl, int lg, const Cx<R> *twl) {
   constexpr int MAXE = MaxElts<R, LDSB>::value;
   const int tid = threadIdx.x;
   const int L = 1 << lg;
@@ -210,7 +211,7 @@ __device__ __forceinline__ int tile_elems(const LineTile &t) {
 
 // Fill the LDS lines with the odd extension [0, x_1..x_n, 0, -x_n..-x_1].
 template <typename R, int U = 4, class Load>
-__device__ void lines_fill(Cx<R> *buf, const LineTile &t, Load &&load) {
+__device__ __forceinline__ void lines_fill(Cx<R> *buf, const LineTile &t, Load &&load) {
   const int tid = threadIdx.x;
   const int L = 1 << t.lg, N = L >> 1;
   const int total = tile_elems(t);
@@ -253,7 +254,7 @@ __device__ __forceinline__ Cx<R> dst_out(Cx<R> Y, R c) { return {-c * Y.y, c * Y
 // Returns this thread's share of sum_k s_k |U_k|^2 over the tile, U the
 // transform coefficients before scaling.
 template <typename R, class Scale>
-__device__ double lines_scale_extend(Cx<R> *buf, const LineTile &t, Scale &&scale) {
+__device__ __forceinline__ double lines_scale_extend(Cx<R> *buf, const LineTile &t, Scale &&scale) {
   const int tid = threadIdx.x;
   const int L = 1 << t.lg, N = L >> 1;
   const R c = (R)1 / sqrt((R)L);
@@ -281,7 +282,7 @@ __device__ double lines_scale_extend(Cx<R> *buf, const LineTile &t, Scale &&scal
 }
 
 template <typename R, class Store>
-__device__ void lines_store(const Cx<R> *buf, const LineTile &t, Store &&store) {
+__device__ __forceinline__ void lines_store(const Cx<R> *buf, const LineTile &t, Store &&store) {
   const int tid = threadIdx.x;
   const int L = 1 << t.lg;
   const R c = (R)1 / sqrt((R)L);
@@ -299,7 +300,7 @@ __device__ void lines_store(const Cx<R> *buf, const LineTile &t, Store &&store) 
 // any of them is consumed (make / post), so U elements' loads are in flight
 // together.
 template <typename R, int U, class Pre, class Make>
-__device__ void lines_fill2(Cx<R> *buf, const LineTile &t, Pre &&pre, Make &&make) {
+__device__ __forceinline__ void lines_fill2(Cx<R> *buf, const LineTile &t, Pre &&pre, Make &&make) {
   using PT = decltype(pre(0, 0, 0));
   const int tid = threadIdx.x;
   const int L = 1 << t.lg, N = L >> 1;
@@ -336,7 +337,7 @@ __device__ void lines_fill2(Cx<R> *buf, const LineTile &t, Pre &&pre, Make &&mak
 }
 
 template <typename R, int U, class Pre, class Post>
-__device__ void lines_store2(const Cx<R> *buf, const LineTile &t, Pre &&pre, Post &&post) {
+__device__ __forceinline__ void lines_store2(const Cx<R> *buf, const LineTile &t, Pre &&pre, Post &&post) {
   using PT = decltype(pre(0));
   const int tid = threadIdx.x;
   const int L = 1 << t.lg;
@@ -451,7 +452,7 @@ template <> struct Mfma<float> {
 // W from the cache hierarchy and X from LDS, so that only a handful of
 // registers are live beside the accumulator.
 template <typename R>
-__device__ void gemm_lines(const Cx<R> *X, Cx<R> *Y, int np, int lp, const R *__restrict__ W) {
+__device__ __forceinline__ void gemm_lines(const Cx<R> *X, Cx<R> *Y, int np, int lp, const R *__restrict__ W) {
   constexpr int KU = 4;   // K steps in flight
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int nrb = np >> 4;

@@ -23,7 +23,7 @@ __device__ __forceinline__ Cx<R> to_cx(double2 v) {
 //           Tq = W_c q.
 // ---------------------------------------------------------------------------
 template <int D, int LDSB, class E>
-__device__ void tile_X(const SysDesc &S, const IOPtr &io, int iter, int tile, char *smem,
+__device__ __forceinline__ void tile_X(const SysDesc &S, const IOPtr &io, int iter, int tile, char *smem,
                        double *red) {
   const double *Wm = S.Wm[D - 1];
   Cx<double> *buf = reinterpret_cast<Cx<double> *>(smem);
@@ -81,7 +81,7 @@ __device__ void tile_X(const SysDesc &S, const IOPtr &io, int iter, int tile, ch
 //     gamma_{j+1}^2 = <z_{j+1}, v_{j+1}> = <T', Tv_{j+1}> (W_c orthogonal).
 // ---------------------------------------------------------------------------
 template <typename R, int D, int LDSB, class E>
-__device__ void tile_Y(const SysDesc &S, int kind, int iter, int tile, char *smem, double *red) {
+__device__ __forceinline__ void tile_Y(const SysDesc &S, int kind, int iter, int tile, char *smem, double *red) {
   Cx<R> *buf = reinterpret_cast<Cx<R> *>(smem);
   const int ax = (kind == K_Y) ? 0 : 1;
   const R *Wm = (sizeof(R) == 8) ? reinterpret_cast<const R *>(S.Wm[ax])
@@ -175,7 +175,7 @@ __device__ void tile_Y(const SysDesc &S, int kind, int iter, int tile, char *sme
 // with x held as its conjugate (the user's z).
 // ---------------------------------------------------------------------------
 template <typename R, int D, int LDSB, class E>
-__device__ void tile_Z(const SysDesc &S, const IOPtr &io, int iter, int tile, char *smem) {
+__device__ __forceinline__ void tile_Z(const SysDesc &S, const IOPtr &io, int iter, int tile, char *smem) {
   const R *Wm = (sizeof(R) == 8) ? reinterpret_cast<const R *>(S.Wm[D - 1])
                                  : reinterpret_cast<const R *>(S.Wmf[D - 1]);
   Cx<R> *buf = reinterpret_cast<Cx<R> *>(smem);
@@ -232,7 +232,7 @@ __device__ void tile_Z(const SysDesc &S, const IOPtr &io, int iter, int tile, ch
 
 // True residual partial ||f - (K + lambda I) z||^2 with z the user output.
 template <int D>
-__device__ void tile_PR(const SysDesc &S, const IOPtr &io, int tile, double *red) {
+__device__ __forceinline__ void tile_PR(const SysDesc &S, const IOPtr &io, int tile, double *red) {
   const int nlast = S.n[D - 1];
   const int r0 = tile * S.cpt[K_PR] * S.rpt;
   const int r1 = min(S.rows, r0 + S.cpt[K_PR] * S.rpt);
@@ -258,7 +258,7 @@ __device__ void tile_PR(const SysDesc &S, const IOPtr &io, int tile, double *red
 }
 
 template <int LDSB>
-__device__ void process_tile(const SysDesc &S, const IOPtr &io, int kind, int iter, int tile,
+__device__ __forceinline__ void process_tile(const SysDesc &S, const IOPtr &io, int kind, int iter, int tile,
                              char *smem, double *red) {
   const bool d3 = (S.d == 3);
   const int ax = (kind == K_X || kind == K_Z) ? S.d - 1 : (kind == K_Y ? 0 : 1);
@@ -312,7 +312,7 @@ __device__ void process_tile(const SysDesc &S, const IOPtr &io, int kind, int it
 // (T -> y), all in the preconditioner precision R.
 // ---------------------------------------------------------------------------
 template <typename R, int D, int LDSB, class E>
-__device__ void tile_pinv(const SysDesc &S, int pass, const double2 *x, double2 *y, int tile,
+__device__ __forceinline__ void tile_pinv(const SysDesc &S, int pass, const double2 *x, double2 *y, int tile,
                           char *smem) {
   Cx<R> *buf = reinterpret_cast<Cx<R> *>(smem);
   Cx<R> *T = reinterpret_cast<Cx<R> *>(S.T);
@@ -369,14 +369,14 @@ __device__ void tile_pinv(const SysDesc &S, int pass, const double2 *x, double2 
 // Givens recurrences, takes the stopping decision and publishes the next
 // phase of this system.
 // ---------------------------------------------------------------------------
-__device__ void publish(Ctl *C, int iter, int kind) {
+__device__ __forceinline__ void publish(Ctl *C, int iter, int kind) {
   __hip_atomic_store(&C->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __threadfence();
   __hip_atomic_exchange(&C->word, (unsigned long long)make_word(iter, kind), __ATOMIC_RELEASE,
                         __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ void finish(const SysDesc &S, Glob *G, int iter, int status, int iters, double rt) {
+__device__ __forceinline__ void finish(const SysDesc &S, Glob *G, int iter, int status, int iters, double rt) {
   DevInfo *I = S.info;
   I->status = status;
   I->iters = iters;
@@ -389,7 +389,7 @@ __device__ void finish(const SysDesc &S, Glob *G, int iter, int status, int iter
 
 enum { ST_OK = 0, ST_NOT_CONVERGED = 3, ST_BREAKDOWN = 4, ST_NONFINITE = 5 };
 
-__device__ void epilogue(const SysDesc &S, const SolveParams &P, int kind, int iter, Glob *G,
+__device__ __forceinline__ void epilogue(const SysDesc &S, const SolveParams &P, int kind, int iter, Glob *G,
                          double *red) {
   const int nt = S.ntile[kind];
   const bool last_strided = (kind == K_Y);   // carries the gamma^2 partials
@@ -911,10 +911,10 @@ hipError_t launch_init(const SysDesc *dsys, int nsys, Glob *G, hipStream_t s) {
 hipError_t launch_solve(const SysDesc *dsys, const IOPtr *dio, IOPtr io0, int nsys,
                         const SolveParams &P, Glob *G, int grid, size_t smem, hipStream_t s) {
   if (smem <= 32768)
-    hipLaunchKernelGGL(solve_kernel<32768>, dim3(grid), dim3(NT), 32768 + TW_LDS_BYTES, s, dsys, dio,
+    hipLaunchKernelGGL(solve_kernel<32768>, dim3(grid), dim3(NT), 32768 + tw_lds_bytes(32768), s, dsys, dio,
                        io0, nsys, P, G);
   else
-    hipLaunchKernelGGL(solve_kernel<65536>, dim3(grid), dim3(NT), 65536 + TW_LDS_BYTES, s, dsys, dio,
+    hipLaunchKernelGGL(solve_kernel<65536>, dim3(grid), dim3(NT), 65536 + tw_lds_bytes(65536), s, dsys, dio,
                        io0, nsys, P, G);
   return hipGetLastError();
 }
@@ -922,9 +922,9 @@ hipError_t launch_solve(const SysDesc *dsys, const IOPtr *dio, IOPtr io0, int ns
 hipError_t solve_occupancy(size_t smem, int *blocks_per_cu) {
   if (smem <= 32768)
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, solve_kernel<32768>, NT,
-                                                        32768 + TW_LDS_BYTES);
+                                                        32768 + tw_lds_bytes(32768));
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, solve_kernel<65536>, NT,
-                                                      65536 + TW_LDS_BYTES);
+                                                      65536 + tw_lds_bytes(65536));
 }
 
 hipError_t launch_apply_A(const SysDesc *dsys, int d, int M, const double2 *x, double2 *y,
@@ -953,8 +953,8 @@ static void pinv_launch(const SysDesc *dsys, int d, int prec, int pass, int ntil
 
 hipError_t launch_pinv_pass(const SysDesc *dsys, int d, int prec, int pass, int ntile, size_t smem,
                             const double2 *x, double2 *y, hipStream_t s) {
-  if (smem <= 32768) pinv_launch<32768>(dsys, d, prec, pass, ntile, 32768 + TW_LDS_BYTES, x, y, s);
-  else pinv_launch<65536>(dsys, d, prec, pass, ntile, 65536 + TW_LDS_BYTES, x, y, s);
+  if (smem <= 32768) pinv_launch<32768>(dsys, d, prec, pass, ntile, 32768 + tw_lds_bytes(32768), x, y, s);
+  else pinv_launch<65536>(dsys, d, prec, pass, ntile, 65536 + tw_lds_bytes(65536), x, y, s);
   return hipGetLastError();
 }
 

@@ -207,7 +207,8 @@ void choose_tiles(SysDesc &h, int tile_elems, size_t *smem_out) {
   int mx = 0;
   for (int k = 0; k < K_NKINDS; ++k) mx = std::max(mx, h.ntile[k]);
   h.maxtile = mx;
-  *smem_out = smem <= 32768 ? smem : 65536;
+  // the 32 KiB variant stages twiddles for lengths up to 1024 only
+  *smem_out = (smem <= 32768 && Lmax <= 1024) ? smem : 65536;
 }
 
 // Group chunks into tiles of about `points` grid points each (1 chunk per

@@ -314,3 +314,19 @@ def test_autograd_function(csl):
     assert rel(f.grad.cpu().numpy(), go["f"]) <= 1e-9
     assert al.grad.item() == pytest.approx(go["alpha"], rel=1e-9)
     assert be.grad.item() == pytest.approx(go["beta"], rel=1e-9)
+
+
+@pytest.mark.parametrize("tile_elems", [256, 1024])
+def test_small_tiles_long_lines(csl, tile_elems):
+    # lines of 2048 (n = 1023) with small tiles: the twiddle staging for the
+    # long lines must still get its LDS
+    shape = (1023, 15)
+    _say("small tiles long lines", tile_elems)
+    a = _coef(shape, 21)
+    x = _crand(shape, 22)
+    p = csl.Problem(cuda(a), -10.0, 30.0, tile_elems=tile_elems)
+    y = csl.apply_Pinv(p, cuda(x)).cpu().numpy()
+    assert rel(y, O.apply_Pinv(x, p.abar, -10.0, 30.0)) <= 1e-13
+    f = _crand(shape, 23)
+    z, info = csl.minres_solve(p, cuda(f), raise_on_error=False, timeout_ms=30000)
+    assert info["status"] == 0 and info["relres_true"] <= 1e-8
