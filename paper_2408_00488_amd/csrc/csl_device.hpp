@@ -33,6 +33,56 @@ template <> __device__ __forceinline__ const Cx<float> *twiddles<float>() {
   return reinterpret_cast<const Cx<float> *>(g_tw32);
 }
 
+// Global-memory views of the pointers held in the descriptors.  Accesses
+// through an address-space-1 pointer compile to global_* instructions
+// instead of flat_* ones; flat accesses also count against the LDS wait
+// counter, so every LDS wait would otherwise stall on outstanding HBM loads
+// and stores.
+#define CSL_G __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ CSL_G T *gbl(T *p) {
+  return (CSL_G T *)p;
+}
+template <typename T>
+__device__ __forceinline__ const CSL_G T *gbl(const T *p) {
+  return (const CSL_G T *)p;
+}
+
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef float nt_f2 __attribute__((ext_vector_type(2)));
+
+// Loads through the global views (the vector classes cannot be copied out of
+// another address space, the builtin vector types can).
+__device__ __forceinline__ double2 ldg(const CSL_G double2 *p) {
+  const nt_d2 v = *(const CSL_G nt_d2 *)p;
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ Cx<double> ldg(const CSL_G Cx<double> *p) {
+  const nt_d2 v = *(const CSL_G nt_d2 *)p;
+  return Cx<double>{v.x, v.y};
+}
+__device__ __forceinline__ Cx<float> ldg(const CSL_G Cx<float> *p) {
+  const nt_f2 v = *(const CSL_G nt_f2 *)p;
+  return Cx<float>{v.x, v.y};
+}
+
+// Streaming stores for vectors that the next phase reads from other
+// workgroups: the nontemporal hint keeps them from lingering dirty in L2,
+// which both speeds up the stream and shortens the L2 write-back that every
+// tile's release performs.
+__device__ __forceinline__ void st_nt(CSL_G double2 *p, double x, double y) {
+  const nt_d2 v = {x, y};
+  __builtin_nontemporal_store(v, (CSL_G nt_d2 *)p);
+}
+__device__ __forceinline__ void st_nt(CSL_G Cx<double> *p, Cx<double> c) {
+  const nt_d2 v = {c.x, c.y};
+  __builtin_nontemporal_store(v, (CSL_G nt_d2 *)p);
+}
+__device__ __forceinline__ void st_nt(CSL_G Cx<float> *p, Cx<float> c) {
+  const nt_f2 v = {c.x, c.y};
+  __builtin_nontemporal_store(v, (CSL_G nt_f2 *)p);
+}
+
 // Elements of the LDS line buffer for an LDS budget of LDSB bytes.
 template <typename R, int LDSB> struct MaxElts {
   static constexpr int value = LDSB / (int)sizeof(Cx<R>);
@@ -58,6 +108,23 @@ __device__ __forceinline__ void load_twiddles(Cx<R> *twl, int lg) {
   const int step = TWN >> lg;
   for (int m = threadIdx.x; m < q; m += NT) twl[m] = tw[m * step];
   __syncthreads();
+}
+
+// Persistent workgroups keep the staged table between tiles: the key (length
+// and precision of the table in LDS) is reset at kernel start and the table
+// is reloaded only when a tile needs another one.
+__shared__ int s_twkey;
+
+__device__ __forceinline__ void twiddle_cache_reset() {
+  if (threadIdx.x == 0) s_twkey = -1;
+}
+
+template <typename R>
+__device__ __forceinline__ void load_twiddles_cached(Cx<R> *twl, int lg) {
+  const int key = lg * 2 + (sizeof(R) == 4 ? 1 : 0);
+  if (s_twkey == key) return;   // uniform: every thread reads the same LDS word
+  load_twiddles<R>(twl, lg);
+  if (threadIdx.x == 0) s_twkey = key;
 }
 
 template <typename R, int LDSB>
@@ -381,20 +448,21 @@ struct StencilIn {
 
 template <int D>
 __device__ __forceinline__ StencilIn<D> stencil_load(const SysDesc &S,
-                                                     const double2 *__restrict__ u, int p,
+                                                     const CSL_G double2 *__restrict__ u, int p,
                                                      const int (&idx)[3]) {
   StencilIn<D> in;
-  in.c = u[p];
+  in.c = ldg(u + p);
 #pragma unroll
   for (int ax = 0; ax < D; ++ax) {
     const int st = S.st[ax];
     int fi = 0;
 #pragma unroll
     for (int k = 0; k < D; ++k) fi += idx[k] * S.fst[ax][k];
-    in.fb[ax] = S.F[ax][fi];
-    in.fa[ax] = S.F[ax][fi + S.fst[ax][ax]];
-    in.b[ax] = idx[ax] > 0 ? u[p - st] : make_double2(0.0, 0.0);
-    in.a[ax] = idx[ax] < S.n[ax] - 1 ? u[p + st] : make_double2(0.0, 0.0);
+    const CSL_G double *__restrict__ F = gbl(S.F[ax]);
+    in.fb[ax] = F[fi];
+    in.fa[ax] = F[fi + S.fst[ax][ax]];
+    in.b[ax] = idx[ax] > 0 ? ldg(u + (p - st)) : make_double2(0.0, 0.0);
+    in.a[ax] = idx[ax] < S.n[ax] - 1 ? ldg(u + (p + st)) : make_double2(0.0, 0.0);
   }
   return in;
 }
@@ -411,7 +479,7 @@ __device__ __forceinline__ double2 stencil_apply(const StencilIn<D> &in) {
 }
 
 template <int D>
-__device__ __forceinline__ double2 stencil_K(const SysDesc &S, const double2 *__restrict__ u,
+__device__ __forceinline__ double2 stencil_K(const SysDesc &S, const CSL_G double2 *__restrict__ u,
                                              int p, const int (&idx)[3]) {
   return stencil_apply<D>(stencil_load<D>(S, u, p, idx));
 }
@@ -467,7 +535,7 @@ __device__ __forceinline__ void gemm_lines(const Cx<R> *X, Cx<R> *Y, int np, int
     const int col = cb * 16 + (lane & 15);
     const bool valid = col < 2 * lp;
     const int line = valid ? (col >> 1) : 0, part = col & 1;
-    const R *wrow = W + m * np + kl;
+    const CSL_G R *wrow = gbl(W) + m * np + kl;
     const R *xcol = Xr + (line * np + kl) * 2 + part;
     typename Mfma<R>::acc c = {0, 0, 0, 0};
     for (int kk = 0; kk < kq; kk += KU) {

@@ -28,24 +28,24 @@ __device__ __forceinline__ void tile_X(const SysDesc &S, const IOPtr &io, int it
   const double *Wm = S.Wm[D - 1];
   Cx<double> *buf = reinterpret_cast<Cx<double> *>(smem);
   Cx<double> *twl = reinterpret_cast<Cx<double> *>(smem + LDSB);
-  load_twiddles<double>(twl, S.lg[D - 1]);
+  load_twiddles_cached<double>(twl, S.lg[D - 1]);
   double acc = 0.0;
   const int c1 = min(S.nchunk[K_X], (tile + 1) * S.cpt[K_X]);
   for (int chunk = tile * S.cpt[K_X]; chunk < c1; ++chunk) {
     const LineTile t = line_tile(S, D - 1, S.lpt_x, chunk);
-    Cx<double> *out;
+    CSL_G Cx<double> *out;
     if (iter == 0) {
-      const double2 *__restrict__ f = io.f;
-      double2 *__restrict__ X = io.x;
+      const CSL_G double2 *__restrict__ f = gbl(io.f);
+      CSL_G double2 *__restrict__ X = gbl(io.x);
       E::template fill<4>(buf, t, [&](int, int, int p) {
-        const double2 v = f[p];
+        const double2 v = ldg(f + p);
         acc += v.x * v.x + v.y * v.y;
-        X[p] = make_double2(0.0, 0.0);
+        st_nt(X + p, 0.0, 0.0);
         return Cx<double>{v.x, v.y};
       });
-      out = reinterpret_cast<Cx<double> *>(S.Tv[1]);
+      out = gbl(reinterpret_cast<Cx<double> *>(S.Tv[1]));
     } else {
-      const double2 *__restrict__ zj = S.Z[iter & 1];
+      const CSL_G double2 *__restrict__ zj = gbl(S.Z[iter & 1]);
       const double al = S.alpha, be = S.beta;
       E::template fill2<2>(
           buf, t,
@@ -62,10 +62,10 @@ __device__ __forceinline__ void tile_X(const SysDesc &S, const IOPtr &io, int it
             acc += zz.x * qx + zz.y * qy;
             return Cx<double>{qx, qy};
           });
-      out = reinterpret_cast<Cx<double> *>(S.Tq);
+      out = gbl(reinterpret_cast<Cx<double> *>(S.Tq));
     }
     const Cx<double> *o = E::transform(buf, t, twl, Wm);
-    E::store(o, t, [&](int, int, int p, Cx<double> v) { out[p] = v; });
+    E::store(o, t, [&](int, int, int p, Cx<double> v) { st_nt(out + p, v); });
   }
   const double s = wg_sum(acc, red);
   if (threadIdx.x == 0) S.part[tile] = s;
@@ -87,8 +87,8 @@ __device__ __forceinline__ void tile_Y(const SysDesc &S, int kind, int iter, int
   const R *Wm = (sizeof(R) == 8) ? reinterpret_cast<const R *>(S.Wm[ax])
                                  : reinterpret_cast<const R *>(S.Wmf[ax]);
   Cx<R> *twl = reinterpret_cast<Cx<R> *>(smem + LDSB);
-  load_twiddles<R>(twl, S.lg[ax]);
-  Cx<R> *T = reinterpret_cast<Cx<R> *>(S.T);
+  load_twiddles_cached<R>(twl, S.lg[ax]);
+  CSL_G Cx<R> *T = gbl(reinterpret_cast<Cx<R> *>(S.T));
   const bool first = (kind == K_Y1) || (D == 2);
   const int j = iter;
   double gacc = 0.0;
@@ -97,16 +97,16 @@ __device__ __forceinline__ void tile_Y(const SysDesc &S, int kind, int iter, int
   const LineTile t = line_tile(S, ax, S.lpt_s[ax], chunk);
   if (first) {
     if (j == 0) {
-      const double2 *__restrict__ v1 = S.Tv[1];
-      E::template fill<4>(buf, t, [&](int, int, int p) { return to_cx<R>(v1[p]); });
+      const CSL_G double2 *__restrict__ v1 = gbl(S.Tv[1]);
+      E::template fill<4>(buf, t, [&](int, int, int p) { return to_cx<R>(ldg(v1 + p)); });
     } else {
       const Ctl *C = S.ctl;
       const double g = ld_ctl(&C->gamma), go = ld_ctl(&C->gamma_old);
       const double dl = ld_ctl(&C->delta);
       const double cd = dl / g, cg = g / go;
-      const double2 *__restrict__ tq = S.Tq;
-      const double2 *__restrict__ vj = S.Tv[j & 1];
-      double2 *__restrict__ vout = S.Tv[(j + 1) & 1];   // holds Tv_{j-1}
+      const CSL_G double2 *__restrict__ tq = gbl(S.Tq);
+      const CSL_G double2 *__restrict__ vj = gbl(S.Tv[j & 1]);
+      CSL_G double2 *__restrict__ vout = gbl(S.Tv[(j + 1) & 1]);   // holds Tv_{j-1}
       const bool has_vm1 = j >= 2;
       struct In3 {
         double2 q, v1, v0;
@@ -115,37 +115,37 @@ __device__ __forceinline__ void tile_Y(const SysDesc &S, int kind, int iter, int
           buf, t,
           [&](int, int, int p) {
             In3 in;
-            in.q = tq[p];
-            in.v1 = vj[p];
-            in.v0 = has_vm1 ? vout[p] : make_double2(0.0, 0.0);
+            in.q = ldg(tq + p);
+            in.v1 = ldg(vj + p);
+            in.v0 = has_vm1 ? ldg(vout + p) : make_double2(0.0, 0.0);
             return in;
           },
           [&](int, int, int p, const In3 &in) {
             const double vx = in.q.x - cd * in.v1.x - cg * in.v0.x;
             const double vy = in.q.y - cd * in.v1.y - cg * in.v0.y;
-            vout[p] = make_double2(vx, vy);
+            st_nt(vout + p, vx, vy);
             return Cx<R>{(R)vx, (R)vy};
           });
     }
   } else {
-    E::template fill<4>(buf, t, [&](int, int, int p) { return T[p]; });
+    E::template fill<4>(buf, t, [&](int, int, int p) { return ldg(T + p); });
   }
   Cx<R> *o = E::transform(buf, t, twl, Wm);
   if (kind == K_Y) {
     const R ab = (sizeof(R) == 8) ? (R)S.abar : (R)S.abar_f;
     const R al = (sizeof(R) == 8) ? (R)S.alpha : (R)S.alpha_f;
     const R be = (sizeof(R) == 8) ? (R)S.beta : (R)S.beta_f;
-    const R *mu0;
-    const R *mu1;
-    const R *mu2;
+    const CSL_G R *mu0;
+    const CSL_G R *mu1;
+    const CSL_G R *mu2;
     if constexpr (sizeof(R) == 8) {
-      mu0 = reinterpret_cast<const R *>(S.mu[0]);
-      mu1 = reinterpret_cast<const R *>(S.mu[1]);
-      mu2 = reinterpret_cast<const R *>(S.mu[2]);
+      mu0 = gbl(reinterpret_cast<const R *>(S.mu[0]));
+      mu1 = gbl(reinterpret_cast<const R *>(S.mu[1]));
+      mu2 = gbl(reinterpret_cast<const R *>(S.mu[2]));
     } else {
-      mu0 = reinterpret_cast<const R *>(S.mu_f[0]);
-      mu1 = reinterpret_cast<const R *>(S.mu_f[1]);
-      mu2 = reinterpret_cast<const R *>(S.mu_f[2]);
+      mu0 = gbl(reinterpret_cast<const R *>(S.mu_f[0]));
+      mu1 = gbl(reinterpret_cast<const R *>(S.mu_f[1]));
+      mu2 = gbl(reinterpret_cast<const R *>(S.mu_f[2]));
     }
     // gamma_{j+1}^2 = <P^{-1} v, v> = sum_k s_k |(W v)_k|^2: here W v is the
     // fully transformed Lanczos vector, so its partial comes from this pass.
@@ -160,7 +160,7 @@ __device__ __forceinline__ void tile_Y(const SysDesc &S, int kind, int iter, int
       return (R)1 / sqrt(sh * sh + be * be);
     }, &o);
   }
-  E::store(o, t, [&](int, int, int p, Cx<R> v) { T[p] = v; });
+  E::store(o, t, [&](int, int, int p, Cx<R> v) { st_nt(T + p, v); });
   }
   if (kind == K_Y) {
     const double sg = wg_sum(gacc, red);
@@ -180,32 +180,32 @@ __device__ __forceinline__ void tile_Z(const SysDesc &S, const IOPtr &io, int it
                                  : reinterpret_cast<const R *>(S.Wmf[D - 1]);
   Cx<R> *buf = reinterpret_cast<Cx<R> *>(smem);
   Cx<R> *twl = reinterpret_cast<Cx<R> *>(smem + LDSB);
-  load_twiddles<R>(twl, S.lg[D - 1]);
+  load_twiddles_cached<R>(twl, S.lg[D - 1]);
   const int c1 = min(S.nchunk[K_Z], (tile + 1) * S.cpt[K_Z]);
   for (int chunk = tile * S.cpt[K_Z]; chunk < c1; ++chunk) {
   const LineTile t = line_tile(S, D - 1, S.lpt_z, chunk);
-  const Cx<R> *T = reinterpret_cast<const Cx<R> *>(S.T);
+  const CSL_G Cx<R> *T = gbl(reinterpret_cast<const Cx<R> *>(S.T));
   const int j = iter;
   const Ctl *C = S.ctl;
   const double g = ld_ctl(&C->gamma);
   const bool store_z = (g != 0.0);
   const double ig = store_z ? 1.0 / g : 0.0;
-  double2 *__restrict__ znew = S.Z[(j + 1) & 1];
-  E::template fill<8>(buf, t, [&](int, int, int p) { return T[p]; });
+  CSL_G double2 *__restrict__ znew = gbl(S.Z[(j + 1) & 1]);
+  E::template fill<8>(buf, t, [&](int, int, int p) { return ldg(T + p); });
   const Cx<R> *o = E::transform(buf, t, twl, Wm);
   if (j == 0) {
     E::store(o, t, [&](int, int, int p, Cx<R> v) {
-      znew[p] = make_double2((double)v.x * ig, (double)v.y * ig);
+      st_nt(znew + p, (double)v.x * ig, (double)v.y * ig);
     });
     continue;
   }
   const double e1 = ld_ctl(&C->e1), e2 = ld_ctl(&C->e2), e3 = ld_ctl(&C->e3);
   const double ceta = ld_ctl(&C->ceta);
   const double ie1 = 1.0 / e1;
-  const double2 *__restrict__ zj = S.Z[j & 1];
-  double2 *__restrict__ wnew = S.W[(j + 1) & 1];   // holds w_{j-1} before the update
-  const double2 *__restrict__ wj = S.W[j & 1];
-  double2 *__restrict__ X = io.x;
+  const CSL_G double2 *__restrict__ zj = gbl(S.Z[j & 1]);
+  CSL_G double2 *__restrict__ wnew = gbl(S.W[(j + 1) & 1]);   // holds w_{j-1} before the update
+  const CSL_G double2 *__restrict__ wj = gbl(S.W[j & 1]);
+  CSL_G double2 *__restrict__ X = gbl(io.x);
   const bool use_wm1 = j > 2, use_wj = j > 1, use_x = j > 1;
   struct In4 {
     double2 z, w0, w1, x;
@@ -214,18 +214,18 @@ __device__ __forceinline__ void tile_Z(const SysDesc &S, const IOPtr &io, int it
       o, t,
       [&](int p) {
         In4 in;
-        in.z = zj[p];
-        in.w0 = use_wm1 ? wnew[p] : make_double2(0.0, 0.0);
-        in.w1 = use_wj ? wj[p] : make_double2(0.0, 0.0);
-        in.x = use_x ? X[p] : make_double2(0.0, 0.0);
+        in.z = ldg(zj + p);
+        in.w0 = use_wm1 ? ldg(wnew + p) : make_double2(0.0, 0.0);
+        in.w1 = use_wj ? ldg(wj + p) : make_double2(0.0, 0.0);
+        in.x = use_x ? ldg(X + p) : make_double2(0.0, 0.0);
         return in;
       },
       [&](int p, Cx<R> v, const In4 &in) {
-        if (store_z) znew[p] = make_double2((double)v.x * ig, (double)v.y * ig);
+        if (store_z) st_nt(znew + p, (double)v.x * ig, (double)v.y * ig);
         const double wx = (in.z.x - e3 * in.w0.x - e2 * in.w1.x) * ie1;
         const double wy = (in.z.y - e3 * in.w0.y - e2 * in.w1.y) * ie1;
-        wnew[p] = make_double2(wx, wy);
-        X[p] = make_double2(in.x.x + ceta * wx, in.x.y - ceta * wy);
+        st_nt(wnew + p, wx, wy);
+        st_nt(X + p, in.x.x + ceta * wx, in.x.y - ceta * wy);
       });
   }
 }
@@ -237,8 +237,8 @@ __device__ __forceinline__ void tile_PR(const SysDesc &S, const IOPtr &io, int t
   const int r0 = tile * S.cpt[K_PR] * S.rpt;
   const int r1 = min(S.rows, r0 + S.cpt[K_PR] * S.rpt);
   const int p0 = r0 * nlast, p1 = r1 * nlast;
-  const double2 *__restrict__ X = io.x;
-  const double2 *__restrict__ f = io.f;
+  const CSL_G double2 *__restrict__ X = gbl(io.x);
+  const CSL_G double2 *__restrict__ f = gbl(io.f);
   const double al = S.alpha, be = S.beta;
   double acc = 0.0;
   for (int p = p0 + (int)threadIdx.x; p < p1; p += NT) {
@@ -246,10 +246,10 @@ __device__ __forceinline__ void tile_PR(const SysDesc &S, const IOPtr &io, int t
     int idx[3];
     row_index<D>(S, row, p - row * nlast, idx);
     const double2 kx = stencil_K<D>(S, X, p, idx);
-    const double2 xv = X[p];
+    const double2 xv = ldg(X + p);
     const double ux = kx.x + al * xv.x - be * xv.y;
     const double uy = kx.y + al * xv.y + be * xv.x;
-    const double2 fv = f[p];
+    const double2 fv = ldg(f + p);
     const double rx = fv.x - ux, ry = fv.y - uy;
     acc += rx * rx + ry * ry;
   }
@@ -331,17 +331,17 @@ __device__ __forceinline__ void tile_pinv(const SysDesc &S, int pass, const doub
     const R ab = (sizeof(R) == 8) ? (R)S.abar : (R)S.abar_f;
     const R al = (sizeof(R) == 8) ? (R)S.alpha : (R)S.alpha_f;
     const R be = (sizeof(R) == 8) ? (R)S.beta : (R)S.beta_f;
-    const R *mu0;
-    const R *mu1;
-    const R *mu2;
+    const CSL_G R *mu0;
+    const CSL_G R *mu1;
+    const CSL_G R *mu2;
     if constexpr (sizeof(R) == 8) {
-      mu0 = reinterpret_cast<const R *>(S.mu[0]);
-      mu1 = reinterpret_cast<const R *>(S.mu[1]);
-      mu2 = reinterpret_cast<const R *>(S.mu[2]);
+      mu0 = gbl(reinterpret_cast<const R *>(S.mu[0]));
+      mu1 = gbl(reinterpret_cast<const R *>(S.mu[1]));
+      mu2 = gbl(reinterpret_cast<const R *>(S.mu[2]));
     } else {
-      mu0 = reinterpret_cast<const R *>(S.mu_f[0]);
-      mu1 = reinterpret_cast<const R *>(S.mu_f[1]);
-      mu2 = reinterpret_cast<const R *>(S.mu_f[2]);
+      mu0 = gbl(reinterpret_cast<const R *>(S.mu_f[0]));
+      mu1 = gbl(reinterpret_cast<const R *>(S.mu_f[1]));
+      mu2 = gbl(reinterpret_cast<const R *>(S.mu_f[2]));
     }
     (void)E::scale_transform(buf, t, twl, Wm, [&](int l, int r) -> R {
       R lam;
@@ -536,6 +536,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void so
   __shared__ double red[NT / 64];
   __shared__ int sh_s, sh_tile, sh_kind, sh_iter, sh_last;
   const int tid = threadIdx.x;
+  twiddle_cache_reset();
   int cur = blockIdx.x % nsys;
   const long long t0 = wall_clock64();
   int backoff = 0;
@@ -657,7 +658,7 @@ __global__ __launch_bounds__(NT) void apply_A_kernel(const SysDesc *__restrict__
     const int row = p / nlast;
     int idx[3];
     row_index<D>(S, row, p - row * nlast, idx);
-    const double2 kx = stencil_K<D>(S, x, p, idx);
+    const double2 kx = stencil_K<D>(S, gbl(x), p, idx);
     const double2 xv = x[p];
     // y = (K + lambda I) conj(x) = conj(K x + conj(lambda) x)
     const double ux = kx.x + S.alpha * xv.x + S.beta * xv.y;
