@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=40,
                     help="systems of the batch timed with the CPU oracle")
     ap.add_argument("--count", type=int, default=64)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the creation-time batch schedule")
     ap.add_argument("--batch-only", action="store_true",
                     help="time only the batched solve (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -160,6 +162,10 @@ def main():
     batch = C.Batch(probs32, tol=1e-8, maxit=1000, check_true=True, use_graph=True)
     Z = [torch.empty_like(f) for f in F]
     stream = torch.cuda.current_stream()
+    # schedule (tile size, LDS budget) chosen by the batch autotuner, outside
+    # the timed region
+    tuning = batch.tune(F, Z) if not args.no_tune else None
+    log("schedule:", tuning)
     zs, infos = batch.solve(F, Z)
     log("batch iters:", [i["iters"] for i in infos])
     for _ in range(args.warmup):
@@ -243,7 +249,8 @@ def main():
                                "(16 each), a=1+0.5 sin(2 pi x) sin(2 pi y), alpha-circulant "
                                "shifts tau=1/64 gamma=1e-2, FP32 preconditioner, tol 1e-8, "
                                "one hipGraph replay",
-                   "systems": len(w.systems), "points": points},
+                   "systems": len(w.systems), "points": points,
+                   "schedule": tuning},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": measured_traffic(),
                      "kernel": "solve_kernel", "avg_launch_ms": avg_launch_s * 1e3,

@@ -193,10 +193,25 @@ typedef struct csl_batch_opts {
     int timeout_ms;
     int grid_size;          /* workgroups of the persistent launch; 0 = auto   */
     int use_graph;          /* 1: replay a captured hipGraph per solve          */
-    int reserved[3];        /* reserved[0]: grid points per scheduling tile
-                               (0 = 8192); larger tiles mean fewer
-                               cross-workgroup hand-offs                    */
+    int tile_points;        /* grid points per scheduling tile (0 = 8192);
+                               larger tiles mean fewer cross-workgroup
+                               hand-offs, smaller ones more parallelism    */
+    int lds_bytes;          /* LDS line budget per workgroup: 0 = per
+                               problem (32 KiB unless lines of 2048 need
+                               64), 65536 = 64 KiB for every problem (twice
+                               the lines per strided tile); 32768 = 0      */
+    int reserved[1];
 } csl_batch_opts;
+
+/* Schedule chosen by batch_tune. */
+typedef struct csl_batch_tuning {
+    int tile_points;        /* chosen grid points per tile                      */
+    int lds_bytes;          /* chosen LDS budget (32768 or 65536)               */
+    int grid_size;          /* workgroups of the persistent launch              */
+    int candidates;         /* schedules timed                                  */
+    double ms;              /* time of one solve with the chosen schedule       */
+    double ms_default;      /* time with the creation-time schedule             */
+} csl_batch_tuning;
 
 /* Group `count` problems (any grids, shifts and precisions) into one
  * persistent launch: every workgroup takes tiles from whichever system has
@@ -213,6 +228,13 @@ csl_status batch_create(const csl_problem *problems, int count,
  * non-OK status). */
 csl_status batch_solve(csl_batch b, const double *const *f, double *const *z,
                        csl_solve_info *infos, hipStream_t s);
+
+/* Autotuner of the batch schedule: solves the batch for f (results in z)
+ * with each candidate tile size and LDS budget, timing every candidate on
+ * stream s, and keeps the fastest for later batch_solve calls (the graph is
+ * recaptured).  Blocks until done; out may be NULL. */
+csl_status batch_tune(csl_batch b, const double *const *f, double *const *z,
+                      csl_batch_tuning *out, hipStream_t s);
 
 csl_status batch_destroy(csl_batch b);
 

@@ -65,7 +65,14 @@ class _BatchOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int),
                 ("check_true_residual", ctypes.c_int), ("timeout_ms", ctypes.c_int),
                 ("grid_size", ctypes.c_int), ("use_graph", ctypes.c_int),
-                ("reserved", ctypes.c_int * 3)]
+                ("tile_points", ctypes.c_int), ("lds_bytes", ctypes.c_int),
+                ("reserved", ctypes.c_int * 1)]
+
+
+class _BatchTuning(ctypes.Structure):
+    _fields_ = [("tile_points", ctypes.c_int), ("lds_bytes", ctypes.c_int),
+                ("grid_size", ctypes.c_int), ("candidates", ctypes.c_int),
+                ("ms", ctypes.c_double), ("ms_default", ctypes.c_double)]
 
 
 _lib = None
@@ -102,12 +109,14 @@ def load_library():
     L.batch_solve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp),
                               ctypes.POINTER(_SolveInfo), vp]
     L.batch_destroy.argtypes = [vp]
+    L.batch_tune.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                             ctypes.POINTER(_BatchTuning), vp]
     L.csl_last_error.restype = ctypes.c_char_p
     L.csl_version.restype = ctypes.c_int
     for fn in ("create_problem", "destroy_problem", "problem_info", "problem_dst_engines",
                "apply_A", "apply_Pinv",
                "minres_solve", "minres_adjoint", "batch_create", "batch_solve",
-               "batch_destroy"):
+               "batch_tune", "batch_destroy"):
         getattr(L, fn).restype = ctypes.c_int
     _lib = L
     return L
@@ -300,7 +309,7 @@ class Batch:
     """Several problems solved by one persistent launch (optionally a graph)."""
 
     def __init__(self, problems, tol=1e-8, maxit=1000, check_true=True, timeout_ms=0,
-                 grid_size=0, use_graph=True, tile_points=0):
+                 grid_size=0, use_graph=True, tile_points=0, lds_bytes=0):
         self.problems = list(problems)
         arr = (ctypes.c_void_p * len(self.problems))(*[p.handle for p in self.problems])
         o = _BatchOpts()
@@ -310,7 +319,8 @@ class Batch:
         o.timeout_ms = int(timeout_ms)
         o.grid_size = int(grid_size)
         o.use_graph = 1 if use_graph else 0
-        o.reserved[0] = int(tile_points)
+        o.tile_points = int(tile_points)
+        o.lds_bytes = int(lds_bytes)
         h = ctypes.c_void_p()
         _check(load_library().batch_create(arr, len(self.problems), ctypes.byref(o),
                                            ctypes.byref(h)))
@@ -347,6 +357,27 @@ class Batch:
         if raise_on_error and st != 0:
             _check(st, d)
         return zs, d
+
+    def tune(self, fs, zs=None) -> dict:
+        """Time the candidate schedules on these right-hand sides and keep
+        the fastest (see batch_tune); returns the chosen schedule."""
+        torch = _torch()
+        n = len(self.problems)
+        if len(fs) != n:
+            raise ValueError("need one right-hand side per system")
+        if zs is None:
+            zs = [torch.empty_like(f) for f in fs]
+        for p, f, z in zip(self.problems, fs, zs):
+            p._vec(f, "f")
+            p._vec(z, "z")
+        fa = (ctypes.c_void_p * n)(*[f.data_ptr() for f in fs])
+        za = (ctypes.c_void_p * n)(*[z.data_ptr() for z in zs])
+        t = _BatchTuning()
+        _check(load_library().batch_tune(self._h, fa, za, ctypes.byref(t),
+                                         _stream(self.device)))
+        return {"tile_points": t.tile_points, "lds_bytes": t.lds_bytes,
+                "grid_size": t.grid_size, "candidates": t.candidates, "ms": t.ms,
+                "ms_default": t.ms_default}
 
 
 def batch_create(problems, **kw) -> Batch:

@@ -115,6 +115,7 @@ struct csl_problem_s {
   double amin = 0, amax = 0;
   size_t smem = 0;
   int grid1 = 1;
+  int tile_elems = 0;
 };
 
 struct csl_batch_s {
@@ -135,6 +136,9 @@ struct csl_batch_s {
   hipGraphExec_t exec = nullptr;
   hipEvent_t copy_done = nullptr;
   bool io_valid = false;
+  int grid_opt = 0;      // requested grid (0 = occupancy-filling)
+  int tile_points = 0;   // current schedule
+  int lds_bytes = 0;
 };
 
 namespace {
@@ -153,11 +157,12 @@ SolveParams make_params(double tol, int maxit, int check_true, int timeout_ms, d
 // preconditioner-precision row pass (K_Z), lines per tile of the strided
 // passes, rows per tile of the residual pass; tile counts per phase kind and
 // the LDS bytes a workgroup needs.
-void choose_tiles(SysDesc &h, int tile_elems, size_t *smem_out) {
-  // LDS budget per workgroup: 32 KiB unless a line of 2048 (n = 1023) needs 64
+void choose_tiles(SysDesc &h, int tile_elems, int ldsb_min, size_t *smem_out) {
+  // LDS budget per workgroup: 32 KiB unless a line of 2048 (n = 1023) needs
+  // 64, or the caller asks for 64 (twice the lines per strided tile)
   int Lmax = 0;
   for (int ax = 0; ax < h.d; ++ax) Lmax = std::max(Lmax, 2 * (h.n[ax] + 1));
-  const int ldsb = Lmax > 1024 ? 65536 : 32768;
+  const int ldsb = (Lmax > 1024 || ldsb_min > 32768) ? 65536 : 32768;
   const int eltR = h.prec ? 8 : 16;
   const int maxeR = ldsb / eltR;
   const int maxe64 = ldsb / 16;
@@ -208,7 +213,7 @@ void choose_tiles(SysDesc &h, int tile_elems, size_t *smem_out) {
   for (int k = 0; k < K_NKINDS; ++k) mx = std::max(mx, h.ntile[k]);
   h.maxtile = mx;
   // the 32 KiB variant stages twiddles for lengths up to 1024 only
-  *smem_out = (smem <= 32768 && Lmax <= 1024) ? smem : 65536;
+  *smem_out = (smem <= 32768 && Lmax <= 1024 && ldsb == 32768) ? smem : 65536;
 }
 
 // Group chunks into tiles of about `points` grid points each (1 chunk per
@@ -311,6 +316,60 @@ csl_status tune_engines(csl_problem p, int elig, hipStream_t s, int *best_mask) 
   return CSL_OK;
 }
 
+// Schedule of a batch: descriptor copies tiled for `tile_points` grid points
+// per tile and an LDS budget of at least `lds_bytes`, the grid, and (if
+// asked) the captured graph of one solve.  Called at creation and by the
+// tuner.
+csl_status configure_batch(csl_batch b, int tile_points, int lds_bytes, bool graph) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  std::vector<SysDesc> descs(b->count);
+  size_t smem = 0;
+  for (int i = 0; i < b->count; ++i) {
+    const csl_problem p = b->probs[i];
+    descs[i] = p->h;
+    size_t sm = p->smem;
+    if (lds_bytes > 32768 && p->smem <= 32768) {
+      // a larger budget only lengthens the chunks: chunk counts (and with
+      // them the partial-sum slots each problem allocated) can only shrink
+      choose_tiles(descs[i], p->tile_elems, lds_bytes, &sm);
+    }
+    descs[i].info = b->d_info + i;
+    set_tile_points(descs[i], tile_points);
+    smem = std::max(smem, sm);
+  }
+  HIPCHK(hipMemcpy(b->d_desc, descs.data(), sizeof(SysDesc) * b->count, hipMemcpyHostToDevice));
+  b->smem = smem;
+  b->tile_points = tile_points;
+  b->lds_bytes = smem <= 32768 ? 32768 : 65536;
+  int bpc = 0;
+  HIPCHK(solve_occupancy(smem, &bpc));
+  // tiles are claimed dynamically, so a full-occupancy grid keeps every CU
+  // busy whatever the mix of systems
+  const int cap = std::max(1, bpc) * b->probs[0]->cus;
+  b->grid = std::max(1, b->grid_opt > 0 ? b->grid_opt : cap);
+  if (!graph) return CSL_OK;
+  hipStream_t cs;
+  HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    ok = launch_init(b->d_desc, b->count, b->glob, cs) == hipSuccess;
+    IOPtr none{nullptr, nullptr};
+    ok = ok && launch_solve(b->d_desc, b->d_io, none, b->count, b->params, b->glob, b->grid,
+                            b->smem, cs) == hipSuccess;
+    hipGraph_t g = nullptr;
+    const bool ended = hipStreamEndCapture(cs, &g) == hipSuccess;
+    ok = ok && ended && g;
+    if (ok) ok = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) == hipSuccess;
+    b->graph = g;
+  }
+  (void)hipStreamDestroy(cs);
+  if (!ok) return fail(CSL_ERR_HIP, "hipGraph capture of the batched solve failed");
+  return CSL_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -397,7 +456,8 @@ csl_status create_problem(const csl_grid *grid, const double *a_nodal, double al
     delete p;
     return fail(CSL_ERR_ARG, "tile_elems must be >= 0");
   }
-  choose_tiles(h, o.tile_elems, &p->smem);
+  choose_tiles(h, o.tile_elems, 0, &p->smem);
+  p->tile_elems = o.tile_elems;
   p->stats_nblk = std::min(1024, (h.M + NT - 1) / NT);
   p->adj_nblk = std::min(1024, (h.M + NT - 1) / NT);
 
@@ -733,67 +793,31 @@ csl_status batch_create(const csl_problem *problems, int count, const csl_batch_
   b->d_io = (IOPtr *)(base + o_io);
   b->d_info = (DevInfo *)(base + o_info);
   b->glob = (Glob *)(base + o_glob);
-  std::vector<SysDesc> descs(count);
-  size_t smem = 0;
-  long long total_tiles = 0;
-  const int tile_points = o.reserved[0] > 0 ? o.reserved[0] : 8192;
-  for (int i = 0; i < count; ++i) {
-    descs[i] = problems[i]->h;
-    descs[i].info = b->d_info + i;
-    set_tile_points(descs[i], tile_points);
-    smem = std::max(smem, problems[i]->smem);
-    int mt = 0;
-    for (int k = 0; k < K_NKINDS; ++k) mt = std::max(mt, descs[i].ntile[k]);
-    total_tiles += mt;
-  }
-  b->smem = smem;
-  auto cleanup = [&](const std::string &msg) {
+  auto cleanup = [&](csl_status st, const std::string &msg) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->h_io) (void)hipHostFree(b->h_io);
     if (b->copy_done) (void)hipEventDestroy(b->copy_done);
     (void)hipFree(b->mem);
     delete b;
-    return fail(CSL_ERR_HIP, msg);
+    return fail(st, msg);
   };
-  if (hipMemcpy(b->d_desc, descs.data(), sizeof(SysDesc) * count, hipMemcpyHostToDevice) !=
-      hipSuccess)
-    return cleanup("hipMemcpy of batch descriptors failed");
   if (hipHostMalloc((void **)&b->h_io, sizeof(IOPtr) * count, hipHostMallocDefault) != hipSuccess)
-    return cleanup("hipHostMalloc failed");
+    return cleanup(CSL_ERR_HIP, "hipHostMalloc failed");
   if (hipEventCreateWithFlags(&b->copy_done, hipEventDisableTiming) != hipSuccess)
-    return cleanup("hipEventCreate failed");
-  int bpc = 0;
-  if (solve_occupancy(smem, &bpc) != hipSuccess) return cleanup("occupancy query failed");
-  const int cap = std::max(1, bpc) * problems[0]->cus;
-  // tiles are claimed dynamically, so a full-occupancy grid keeps every CU
-  // busy whatever the mix of systems
-  b->grid = o.grid_size > 0 ? o.grid_size : cap;
-  (void)total_tiles;
-  b->grid = std::max(1, b->grid);
+    return cleanup(CSL_ERR_HIP, "hipEventCreate failed");
+  b->grid_opt = o.grid_size;
   b->params = make_params(o.tol, o.maxit, o.check_true_residual, o.timeout_ms,
                           problems[0]->wall_khz);
   b->use_graph = o.use_graph != 0;
-  if (b->use_graph) {
-    hipStream_t cs;
-    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
-      return cleanup("hipStreamCreate failed");
-    bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
-    if (ok) {
-      ok = launch_init(b->d_desc, count, b->glob, cs) == hipSuccess;
-      IOPtr none{nullptr, nullptr};
-      ok = ok && launch_solve(b->d_desc, b->d_io, none, count, b->params, b->glob, b->grid, smem,
-                              cs) == hipSuccess;
-      hipGraph_t g = nullptr;
-      const bool ended = hipStreamEndCapture(cs, &g) == hipSuccess;
-      ok = ok && ended && g;
-      if (ok) ok = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) == hipSuccess;
-      b->graph = g;
-    }
-    (void)hipStreamDestroy(cs);
-    if (!ok) {
-      if (b->exec) (void)hipGraphExecDestroy(b->exec);
-      if (b->graph) (void)hipGraphDestroy(b->graph);
-      return cleanup("hipGraph capture of the batched solve failed");
-    }
+  if (o.lds_bytes != 0 && o.lds_bytes != 32768 && o.lds_bytes != 65536)
+    return cleanup(CSL_ERR_ARG, "lds_bytes must be 0, 32768 or 65536");
+  if (o.tile_points < 0) return cleanup(CSL_ERR_ARG, "tile_points must be >= 0");
+  const csl_status st = configure_batch(b, o.tile_points > 0 ? o.tile_points : 8192,
+                                        o.lds_bytes, b->use_graph);
+  if (st != CSL_OK) {
+    const std::string msg = g_err;
+    return cleanup(st, msg);
   }
   *out = b;
   return CSL_OK;
@@ -841,6 +865,72 @@ csl_status batch_solve(csl_batch b, const double *const *f, double *const *z,
   }
   if (first != CSL_OK) g_err = "batch: at least one system did not converge";
   return first;
+}
+
+csl_status batch_tune(csl_batch b, const double *const *f, double *const *z,
+                      csl_batch_tuning *out, hipStream_t s) {
+  if (!b || !f || !z) return fail(CSL_ERR_ARG, "NULL argument");
+  const int tp0 = b->tile_points, lds0 = b->lds_bytes;
+  // candidates: the creation-time schedule first, then tile sizes around it
+  // with both LDS budgets
+  std::vector<std::pair<int, int>> cands;
+  cands.push_back({tp0, lds0});
+  for (int lds : {32768, 65536})
+    for (int tp : {6144, 8192, 12288, 16384, 24576})
+      if (!(tp == tp0 && lds == lds0)) cands.push_back({tp, lds});
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(CSL_ERR_HIP, "hipEventCreate failed");
+  }
+  const bool graph = b->use_graph;
+  b->use_graph = false;   // plain launches while timing
+  double best = INFINITY, first = INFINITY;
+  int best_tp = tp0, best_lds = lds0, timed = 0;
+  csl_status st = CSL_OK;
+  for (size_t c = 0; c < cands.size() && st == CSL_OK; ++c) {
+    st = configure_batch(b, cands[c].first, cands[c].second, false);
+    if (st != CSL_OK) break;
+    if (b->lds_bytes != cands[c].second && c > 0) continue;   // budget not applicable
+    st = batch_solve(b, f, z, nullptr, s);   // warm-up (and io upload)
+    if (st != CSL_OK) break;
+    float ms = 0.f, tot = 0.f;
+    const int reps = 2;
+    for (int r = 0; r < reps && st == CSL_OK; ++r) {
+      if (hipEventRecord(e0, s) != hipSuccess) st = fail(CSL_ERR_HIP, "hipEventRecord failed");
+      if (st == CSL_OK) st = batch_solve(b, f, z, nullptr, s);
+      if (st == CSL_OK && (hipEventRecord(e1, s) != hipSuccess ||
+                           hipEventSynchronize(e1) != hipSuccess ||
+                           hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        st = fail(CSL_ERR_HIP, "event timing failed");
+      tot += ms;
+    }
+    if (st != CSL_OK) break;
+    const double avg = tot / reps;
+    ++timed;
+    if (c == 0) first = avg;
+    if (avg < best) {
+      best = avg;
+      best_tp = cands[c].first;
+      best_lds = b->lds_bytes;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->use_graph = graph;
+  const csl_status st2 = configure_batch(b, best_tp, best_lds, graph);
+  if (st != CSL_OK) return st;
+  if (st2 != CSL_OK) return st2;
+  if (out) {
+    out->tile_points = best_tp;
+    out->lds_bytes = b->lds_bytes;
+    out->grid_size = b->grid;
+    out->candidates = timed;
+    out->ms = best;
+    out->ms_default = first;
+  }
+  return CSL_OK;
 }
 
 csl_status batch_destroy(csl_batch b) {

@@ -330,3 +330,41 @@ def test_small_tiles_long_lines(csl, tile_elems):
     f = _crand(shape, 23)
     z, info = csl.minres_solve(p, cuda(f), raise_on_error=False, timeout_ms=30000)
     assert info["status"] == 0 and info["relres_true"] <= 1e-8
+
+
+def test_batch_lds_budget_and_tuner(csl):
+    # the same batch with 32 KiB and 64 KiB line budgets, then autotuned:
+    # schedules change chunk sizes (summation order), not the method
+    w = WL.workload("c4", count_override=8)
+    probs = [csl.Problem(cuda(s.a), s.lam.real, s.lam.imag, pinv_fp32=(j % 2 == 0))
+             for j, s in enumerate(w.systems)]
+    F = [cuda(s.f) for s in w.systems]
+    _say("batch lds budgets")
+    ref = None
+    for lds in (0, 65536):
+        b = csl.Batch(probs, lds_bytes=lds, timeout_ms=30000)
+        zs, infos = b.solve(F)
+        assert all(i["status"] == 0 and i["relres_true"] <= 1e-8 for i in infos), infos
+        zc = [z.cpu().numpy() for z in zs]
+        if ref is None:
+            ref = zc
+        else:
+            for a_, b_ in zip(zc, ref):
+                assert rel(a_, b_) <= 1e-9
+        b.close()
+    b = csl.Batch(probs, timeout_ms=30000)
+    t = b.tune(F)
+    _say("tuned", t)
+    assert t["candidates"] >= 2 and t["lds_bytes"] in (32768, 65536) and t["tile_points"] > 0
+    assert t["ms"] <= t["ms_default"] * 1.0000001
+    zs, infos = b.solve(F)
+    assert all(i["status"] == 0 and i["relres_true"] <= 1e-8 for i in infos), infos
+    for z, r in zip(zs, ref):
+        assert rel(z.cpu().numpy(), r) <= 1e-9
+    # replays of the recaptured graph agree bitwise
+    z1 = [z.cpu().numpy().copy() for z in zs]
+    zs2, _ = b.solve(F)
+    for a_, b_ in zip(z1, zs2):
+        assert np.array_equal(a_, b_.cpu().numpy())
+    with pytest.raises(csl.CSLError):
+        csl.Batch(probs, lds_bytes=12345)
