@@ -74,6 +74,10 @@ struct SysDesc {
   int lpt_x;      // rows per tile of the FP64 contiguous-axis pass (K_X)
   int lpt_z;      // rows per tile of the preconditioner-precision row pass
   int lpt_s[2];   // lines per tile of the strided passes along axes 0, 1
+  int lgB;        // log2 of the block width B of the column-blocked layout
+                  // (= lines per strided tile): Tq, Tv and T store element
+                  // (row, c) at ((c / B) rows + row) B + c % B, so a strided
+                  // tile's lines are one contiguous block
   int rpt;        // rows per tile of the residual pass
   int fst[3][3];  // strides of the face-coefficient array of each axis
   int nchunk[K_NKINDS];  // LDS-sized chunks of each phase kind
@@ -90,9 +94,10 @@ struct SysDesc {
   const float *Wmf[3];     // FP32 copy
   const double *mu[3];     // per-axis eigenvalues of L, FP64
   const float *mu_f[3];    // FP32 copies
-  double2 *Tq;             // W_c (A zhat_j)
-  double2 *Tv[2];          // W_c v_m, by parity of m
-  void *T;                 // preconditioner intermediate (double2 or float2)
+  double2 *Tq;             // W_c (A zhat_j)               (column-blocked)
+  double2 *Tv[2];          // W_c v_m, by parity of m       (column-blocked)
+  void *T;                 // preconditioner intermediate (double2 or float2;
+                           // column-blocked)
   double2 *Z[2];           // zhat_m = P^{-1} v_m / gamma_m, by parity of m
   double2 *W[2];           // search directions w_m, by parity of m
   double *part;            // per-tile partial sums

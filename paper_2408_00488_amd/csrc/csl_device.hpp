@@ -221,6 +221,11 @@ struct LineTile {
   int outer;    // strided passes: index along the remaining axis (3-D)
   int c0;       // strided passes: first index along the contiguous axis
   uint32_t magic;  // ceil(2^32 / n), for e / n with e < 2^14
+  // Column-blocked layout (block width B = 2^lgB): strided tiles address it
+  // through base/stride/lstride directly (their lines are one block);
+  // contiguous-axis tiles use qrow0 = row0 B and qblk = rows B, the offsets
+  // of the tile's first row and of one block.
+  int lgB, qrow0, qblk;
 };
 
 __device__ __forceinline__ int ilog2i(int v) { return 31 - __clz(v); }
@@ -233,6 +238,8 @@ __device__ __forceinline__ LineTile line_tile(const SysDesc &S, int ax, int lp, 
   t.lp = lp;
   t.lgl = ilog2i(t.lp);
   t.magic = (uint32_t)((0x100000000ull + (uint64_t)t.n - 1) / (uint64_t)t.n);
+  t.lgB = S.lgB;
+  t.qblk = S.rows << S.lgB;
   if (ax == S.d - 1) {
     t.row0 = tile * t.lp;
     t.nl = min(t.lp, S.rows - t.row0);
@@ -241,7 +248,11 @@ __device__ __forceinline__ LineTile line_tile(const SysDesc &S, int ax, int lp, 
     t.lstride = t.n;
     t.outer = 0;
     t.c0 = 0;
+    t.qrow0 = t.row0 << S.lgB;
   } else {
+    // strided passes touch only column-blocked vectors: the tile's lp = B
+    // lines c0 .. c0+B-1 are block c0 / B, element (l, r) of the tile at
+    // ((c0 / B) rows + row(r)) B + l with row(r) the row index of position r
     const int nlast = S.n[S.d - 1];
     const int nblk = (nlast + t.lp - 1) / t.lp;
     const int outer = tile / nblk;
@@ -249,13 +260,39 @@ __device__ __forceinline__ LineTile line_tile(const SysDesc &S, int ax, int lp, 
     t.c0 = blk * t.lp;
     t.nl = min(t.lp, nlast - t.c0);
     t.outer = outer;
-    const int o = (S.d == 3) ? (ax == 0 ? 1 : 0) : -1;
-    t.base = (o >= 0 ? outer * S.st[o] : 0) + t.c0;
-    t.stride = S.st[ax];
+    // row(r) = rbase + r * rstep: 2-D axis 0: r; 3-D axis 1: outer n1 + r;
+    // 3-D axis 0: r n1 + outer
+    int rbase = 0, rstep = 1;
+    if (S.d == 3) {
+      if (ax == 1) rbase = outer * S.n[1];
+      else {
+        rbase = outer;
+        rstep = S.n[1];
+      }
+    }
+    t.base = (blk * S.rows + rbase) << S.lgB;
+    t.stride = rstep << S.lgB;
     t.lstride = 1;
     t.row0 = 0;
+    t.qrow0 = 0;
   }
   return t;
+}
+
+// Blocked order for contiguous-axis tiles reading or writing the
+// column-blocked vectors: lanes run over (c % B, row, block), so each block
+// of the tile is one contiguous run of lp B entries.  Returns the tile-local
+// (line, position) and the blocked index q.
+__device__ __forceinline__ int tile_elems_blk(const LineTile &t) {
+  return ((t.n + (1 << t.lgB) - 1) >> t.lgB) << (t.lgB + t.lgl);
+}
+__device__ __forceinline__ bool split_blk(const LineTile &t, int e, int &l, int &r, int &q) {
+  const int cb = e & ((1 << t.lgB) - 1);
+  l = (e >> t.lgB) & (t.lp - 1);
+  const int blk = e >> (t.lgB + t.lgl);
+  r = (blk << t.lgB) + cb;
+  q = blk * t.qblk + t.qrow0 + (l << t.lgB) + cb;
+  return l < t.nl && r < t.n;
 }
 
 // Split a flat element counter into (line, position).  Contiguous-axis
@@ -292,6 +329,42 @@ __device__ __forceinline__ void lines_fill(Cx<R> *buf, const LineTile &t, Load &
       int l, r;
       if (e < total && split_elem(t, e, l, r)) {
         v[u] = load(l, r, t.base + l * t.lstride + r * t.stride);
+        pos[u] = l * L;
+        rr[u] = r;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (pos[u] >= 0) {
+        buf[pos[u] + rr[u] + 1] = v[u];
+        buf[pos[u] + L - 1 - rr[u]] = Cx<R>{-v[u].x, -v[u].y};
+      }
+    }
+  }
+  for (int l = tid; l < t.nl; l += NT) {
+    buf[l * L] = Cx<R>{0, 0};
+    buf[l * L + N] = Cx<R>{0, 0};
+  }
+  __syncthreads();
+}
+
+// lines_fill for a contiguous-axis tile reading a column-blocked vector:
+// load(l, r, q) with q the blocked index.
+template <typename R, int U = 4, class Load>
+__device__ __forceinline__ void lines_fill_blk(Cx<R> *buf, const LineTile &t, Load &&load) {
+  const int tid = threadIdx.x;
+  const int L = 1 << t.lg, N = L >> 1;
+  const int total = tile_elems_blk(t);
+  for (int e0 = 0; e0 < total; e0 += NT * U) {
+    Cx<R> v[U];
+    int pos[U], rr[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * NT + tid;
+      pos[u] = -1;
+      int l, r, q;
+      if (e < total && split_blk(t, e, l, r, q)) {
+        v[u] = load(l, r, q);
         pos[u] = l * L;
         rr[u] = r;
       }
@@ -363,6 +436,21 @@ __device__ __forceinline__ void lines_store(const Cx<R> *buf, const LineTile &t,
   __syncthreads();
 }
 
+// lines_store for a contiguous-axis tile writing a column-blocked vector:
+// store(l, r, q, value) with q the blocked index.
+template <typename R, class Store>
+__device__ __forceinline__ void lines_store_blk(const Cx<R> *buf, const LineTile &t, Store &&store) {
+  const int tid = threadIdx.x;
+  const int L = 1 << t.lg;
+  const R c = (R)1 / sqrt((R)L);
+  const int total = tile_elems_blk(t);
+  for (int e = tid; e < total; e += NT) {
+    int l, r, q;
+    if (split_blk(t, e, l, r, q)) store(l, r, q, dst_out(buf[l * L + r + 1], c));
+  }
+  __syncthreads();
+}
+
 // Two-step variants: every global load of U elements (pre) is issued before
 // any of them is consumed (make / post), so U elements' loads are in flight
 // together.
@@ -372,29 +460,45 @@ __device__ __forceinline__ void lines_fill2(Cx<R> *buf, const LineTile &t, Pre &
   const int tid = threadIdx.x;
   const int L = 1 << t.lg, N = L >> 1;
   const int total = tile_elems(t);
-  for (int e0 = 0; e0 < total; e0 += NT * U) {
+  // Two-deep software pipeline over rounds of NT*U elements: the loads of
+  // the next round are in flight while this round is combined and written.
+  struct Round {
     PT pv[U];
     int ll[U], rr[U], pp[U];
+  };
+  auto issue = [&](Round &q, int e0) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int e = e0 + u * NT + tid;
-      ll[u] = -1;
+      q.ll[u] = -1;
       int l, r;
       if (e < total && split_elem(t, e, l, r)) {
-        ll[u] = l;
-        rr[u] = r;
-        pp[u] = t.base + l * t.lstride + r * t.stride;
-        pv[u] = pre(l, r, pp[u]);
+        q.ll[u] = l;
+        q.rr[u] = r;
+        q.pp[u] = t.base + l * t.lstride + r * t.stride;
+        q.pv[u] = pre(l, r, q.pp[u]);
       }
     }
+  };
+  auto consume = [&](const Round &q) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (ll[u] >= 0) {
-        const Cx<R> v = make(ll[u], rr[u], pp[u], pv[u]);
-        buf[ll[u] * L + rr[u] + 1] = v;
-        buf[ll[u] * L + L - 1 - rr[u]] = Cx<R>{-v.x, -v.y};
+      if (q.ll[u] >= 0) {
+        const Cx<R> v = make(q.ll[u], q.rr[u], q.pp[u], q.pv[u]);
+        buf[q.ll[u] * L + q.rr[u] + 1] = v;
+        buf[q.ll[u] * L + L - 1 - q.rr[u]] = Cx<R>{-v.x, -v.y};
       }
     }
+  };
+  constexpr int step = NT * U;
+  Round A, B;
+  issue(A, 0);
+  for (int e0 = 0; e0 < total; e0 += 2 * step) {
+    if (e0 + step < total) issue(B, e0 + step);
+    consume(A);
+    if (e0 + step >= total) break;
+    if (e0 + 2 * step < total) issue(A, e0 + 2 * step);
+    consume(B);
   }
   for (int l = tid; l < t.nl; l += NT) {
     buf[l * L] = Cx<R>{0, 0};
@@ -410,25 +514,40 @@ __device__ __forceinline__ void lines_store2(const Cx<R> *buf, const LineTile &t
   const int L = 1 << t.lg;
   const R c = (R)1 / sqrt((R)L);
   const int total = tile_elems(t);
-  for (int e0 = 0; e0 < total; e0 += NT * U) {
+  // same two-deep pipeline: the next round's operand loads are in flight
+  // while this round is combined and stored
+  struct Round {
     PT pv[U];
-    Cx<R> vv[U];
-    int pp[U];
+    int pp[U], bi[U];
+  };
+  auto issue = [&](Round &q, int e0) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int e = e0 + u * NT + tid;
-      pp[u] = -1;
+      q.pp[u] = -1;
       int l, r;
       if (e < total && split_elem(t, e, l, r)) {
-        pp[u] = t.base + l * t.lstride + r * t.stride;
-        pv[u] = pre(pp[u]);
-        vv[u] = dst_out(buf[l * L + r + 1], c);
+        q.pp[u] = t.base + l * t.lstride + r * t.stride;
+        q.bi[u] = l * L + r + 1;
+        q.pv[u] = pre(q.pp[u]);
       }
     }
+  };
+  auto consume = [&](const Round &q) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (pp[u] >= 0) post(pp[u], vv[u], pv[u]);
+      if (q.pp[u] >= 0) post(q.pp[u], dst_out(buf[q.bi[u]], c), q.pv[u]);
     }
+  };
+  constexpr int step = NT * U;
+  Round A, B;
+  issue(A, 0);
+  for (int e0 = 0; e0 < total; e0 += 2 * step) {
+    if (e0 + step < total) issue(B, e0 + step);
+    consume(A);
+    if (e0 + step >= total) break;
+    if (e0 + 2 * step < total) issue(A, e0 + 2 * step);
+    consume(B);
   }
   __syncthreads();
 }
@@ -592,6 +711,16 @@ template <typename R, int LDSB> struct FftEng {
                                                 Post &&post) {
     lines_store2<R, U>(out, t, pre, post);
   }
+  // contiguous-axis tiles on column-blocked vectors
+  template <int U, class Load>
+  static __device__ __forceinline__ void fill_blk(Cx<R> *buf, const LineTile &t, Load &&load) {
+    lines_fill_blk<R, U>(buf, t, load);
+  }
+  template <class Store>
+  static __device__ __forceinline__ void store_blk(const Cx<R> *out, const LineTile &t,
+                                                   Store &&st) {
+    lines_store_blk<R>(out, t, st);
+  }
 };
 
 __device__ __forceinline__ int gemm_np(int n) { return (n + 15) & ~15; }
@@ -697,6 +826,41 @@ template <typename R, int LDSB> struct GemmEng {
     for (int e = threadIdx.x; e < total; e += NT) {
       int l, r;
       if (split_elem(t, e, l, r)) st(l, r, t.base + l * t.lstride + r * t.stride, out[l * np + r]);
+    }
+    __syncthreads();
+  }
+  template <int U, class Load>
+  static __device__ __forceinline__ void fill_blk(Cx<R> *buf, const LineTile &t, Load &&load) {
+    const int np = gemm_np(t.n);
+    const int total = tile_elems_blk(t);
+    const int tid = threadIdx.x;
+    for (int e0 = 0; e0 < total; e0 += NT * U) {
+      Cx<R> v[U];
+      int pos[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * NT + tid;
+        pos[u] = -1;
+        int l, r, q;
+        if (e < total && split_blk(t, e, l, r, q)) {
+          v[u] = load(l, r, q);
+          pos[u] = l * np + r;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (pos[u] >= 0) buf[pos[u]] = v[u];
+    }
+    pad(buf, t, np);
+  }
+  template <class Store>
+  static __device__ __forceinline__ void store_blk(const Cx<R> *out, const LineTile &t,
+                                                   Store &&st) {
+    const int np = gemm_np(t.n);
+    const int total = tile_elems_blk(t);
+    for (int e = threadIdx.x; e < total; e += NT) {
+      int l, r, q;
+      if (split_blk(t, e, l, r, q)) st(l, r, q, out[l * np + r]);
     }
     __syncthreads();
   }

@@ -47,7 +47,7 @@ __device__ __forceinline__ void tile_X(const SysDesc &S, const IOPtr &io, int it
     } else {
       const CSL_G double2 *__restrict__ zj = gbl(S.Z[iter & 1]);
       const double al = S.alpha, be = S.beta;
-      E::template fill2<2>(
+      E::template fill2<1>(
           buf, t,
           [&](int l, int r, int p) {
             int idx[3];
@@ -65,7 +65,7 @@ __device__ __forceinline__ void tile_X(const SysDesc &S, const IOPtr &io, int it
       out = gbl(reinterpret_cast<Cx<double> *>(S.Tq));
     }
     const Cx<double> *o = E::transform(buf, t, twl, Wm);
-    E::store(o, t, [&](int, int, int p, Cx<double> v) { st_nt(out + p, v); });
+    E::store_blk(o, t, [&](int, int, int q, Cx<double> v) { st_nt(out + q, v); });
   }
   const double s = wg_sum(acc, red);
   if (threadIdx.x == 0) S.part[tile] = s;
@@ -111,7 +111,7 @@ __device__ __forceinline__ void tile_Y(const SysDesc &S, int kind, int iter, int
       struct In3 {
         double2 q, v1, v0;
       };
-      E::template fill2<4>(
+      E::template fill2<2>(
           buf, t,
           [&](int, int, int p) {
             In3 in;
@@ -191,7 +191,7 @@ __device__ __forceinline__ void tile_Z(const SysDesc &S, const IOPtr &io, int it
   const bool store_z = (g != 0.0);
   const double ig = store_z ? 1.0 / g : 0.0;
   CSL_G double2 *__restrict__ znew = gbl(S.Z[(j + 1) & 1]);
-  E::template fill<8>(buf, t, [&](int, int, int p) { return ldg(T + p); });
+  E::template fill_blk<8>(buf, t, [&](int, int, int q) { return ldg(T + q); });
   const Cx<R> *o = E::transform(buf, t, twl, Wm);
   if (j == 0) {
     E::store(o, t, [&](int, int, int p, Cx<R> v) {
@@ -210,7 +210,7 @@ __device__ __forceinline__ void tile_Z(const SysDesc &S, const IOPtr &io, int it
   struct In4 {
     double2 z, w0, w1, x;
   };
-  E::template store2<4>(
+  E::template store2<2>(
       o, t,
       [&](int p) {
         In4 in;
@@ -324,7 +324,10 @@ __device__ __forceinline__ void tile_pinv(const SysDesc &S, int pass, const doub
   load_twiddles<R>(twl, t.lg);
   const R *Wm = (sizeof(R) == 8) ? reinterpret_cast<const R *>(S.Wm[ax])
                                  : reinterpret_cast<const R *>(S.Wmf[ax]);
+  // T is column-blocked: the row passes reach it in blocked order, the
+  // strided passes through their tile addressing
   if (pass == 0) E::template fill<4>(buf, t, [&](int, int, int p) { return to_cx<R>(x[p]); });
+  else if (pass == 4) E::template fill_blk<4>(buf, t, [&](int, int, int q) { return T[q]; });
   else E::template fill<4>(buf, t, [&](int, int, int p) { return T[p]; });
   Cx<R> *o = E::transform(buf, t, twl, Wm);
   if (pass == 2) {
@@ -358,6 +361,8 @@ __device__ __forceinline__ void tile_pinv(const SysDesc &S, int pass, const doub
     E::store(o, t, [&](int, int, int p, Cx<R> v) {
       y[p] = make_double2((double)v.x, (double)v.y);
     });
+  } else if (pass == 0) {
+    E::store_blk(o, t, [&](int, int, int q, Cx<R> v) { T[q] = v; });
   } else {
     E::store(o, t, [&](int, int, int p, Cx<R> v) { T[p] = v; });
   }

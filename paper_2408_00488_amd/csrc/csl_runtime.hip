@@ -191,6 +191,9 @@ void choose_tiles(SysDesc &h, int tile_elems, int ldsb_min, size_t *smem_out) {
     h.lpt_s[ax] = std::max(1, lp);
     smem = std::max(smem, (size_t)h.lpt_s[ax] * L * eltR);
   }
+  // every strided pass uses the block width of the column-blocked layout
+  if (h.d == 3) h.lpt_s[0] = h.lpt_s[1] = std::min(h.lpt_s[0], h.lpt_s[1]);
+  h.lgB = ilog2(h.lpt_s[0]);
   h.rpt = std::max(1, tgt64 / nlast);
   for (int k = 0; k < K_NKINDS; ++k) {
     h.nchunk[k] = 0;
@@ -463,7 +466,10 @@ csl_status create_problem(const csl_grid *grid, const double *a_nodal, double al
 
   // one allocation for the coefficient copy, tables and workspaces
   const size_t vec = align256(sizeof(double2) * (size_t)h.M);
-  const size_t tsz = align256((size_t)h.M * (h.prec ? 8 : 16));
+  // column-blocked vectors: rows x ceil(n_last / B) B entries, B <= 64
+  const size_t Mb = (size_t)h.rows * (size_t)(h.n[h.d - 1] + 63);
+  const size_t vecb = align256(sizeof(double2) * Mb);
+  const size_t tsz = align256(Mb * (h.prec ? 8 : 16));
   const int nmu = h.n[0] + h.n[1] + h.n[2];
   int nfaces[3] = {0, 0, 0};
   for (int ax = 0; ax < h.d; ++ax) {
@@ -485,7 +491,7 @@ csl_status create_problem(const csl_grid *grid, const double *a_nodal, double al
   const size_t o_mu = take(sizeof(double) * nmu);
   const size_t o_muf = take(sizeof(float) * nmu);
   size_t o_v[7];
-  for (int i = 0; i < 7; ++i) o_v[i] = take(vec);
+  for (int i = 0; i < 7; ++i) o_v[i] = take(i < 3 ? vecb : vec);   // Tq, Tv0, Tv1 blocked
   const size_t o_t = take(tsz);
   const size_t o_part = take(sizeof(double) * std::max(1, h.maxtile));
   const size_t o_ctl = take(sizeof(Ctl));
