@@ -280,20 +280,27 @@ __device__ __forceinline__ LineTile line_tile(const SysDesc &S, int ax, int lp, 
 }
 
 // Blocked order for contiguous-axis tiles reading or writing the
-// column-blocked vectors: lanes run over (c % B, row, block), so each block
-// of the tile is one contiguous run of lp B entries.  Returns the tile-local
-// (line, position) and the blocked index q.
+// column-blocked vectors: lanes run over W consecutive positions of a row,
+// then the lp rows, then the next W positions, so a wave covers whole
+// lp x B blocks (contiguous runs in memory) while its LDS accesses stay
+// conflict-free (a row segment is 256 bytes of LDS).
+// Returns the tile-local (line, position) and the blocked index q.
+template <int LGW>
 __device__ __forceinline__ int tile_elems_blk(const LineTile &t) {
-  return ((t.n + (1 << t.lgB) - 1) >> t.lgB) << (t.lgB + t.lgl);
+  return ((t.n + (1 << LGW) - 1) >> LGW) << (LGW + t.lgl);
 }
+template <int LGW>
 __device__ __forceinline__ bool split_blk(const LineTile &t, int e, int &l, int &r, int &q) {
-  const int cb = e & ((1 << t.lgB) - 1);
-  l = (e >> t.lgB) & (t.lp - 1);
-  const int blk = e >> (t.lgB + t.lgl);
-  r = (blk << t.lgB) + cb;
-  q = blk * t.qblk + t.qrow0 + (l << t.lgB) + cb;
+  const int rl = e & ((1 << LGW) - 1);
+  l = (e >> LGW) & (t.lp - 1);
+  r = ((e >> (LGW + t.lgl)) << LGW) + rl;
+  q = (r >> t.lgB) * t.qblk + t.qrow0 + (l << t.lgB) + (r & ((1 << t.lgB) - 1));
   return l < t.nl && r < t.n;
 }
+// row segment of 256 bytes: 16 FP64 or 32 FP32 complex entries
+template <typename R> struct BlkW {
+  static constexpr int lg = sizeof(R) == 8 ? 4 : 5;
+};
 
 // Split a flat element counter into (line, position).  Contiguous-axis
 // tiles run positions fastest (coalesced rows); strided tiles run lines
@@ -354,7 +361,8 @@ template <typename R, int U = 4, class Load>
 __device__ __forceinline__ void lines_fill_blk(Cx<R> *buf, const LineTile &t, Load &&load) {
   const int tid = threadIdx.x;
   const int L = 1 << t.lg, N = L >> 1;
-  const int total = tile_elems_blk(t);
+  constexpr int LGW = BlkW<R>::lg;
+  const int total = tile_elems_blk<LGW>(t);
   for (int e0 = 0; e0 < total; e0 += NT * U) {
     Cx<R> v[U];
     int pos[U], rr[U];
@@ -363,7 +371,7 @@ __device__ __forceinline__ void lines_fill_blk(Cx<R> *buf, const LineTile &t, Lo
       const int e = e0 + u * NT + tid;
       pos[u] = -1;
       int l, r, q;
-      if (e < total && split_blk(t, e, l, r, q)) {
+      if (e < total && split_blk<LGW>(t, e, l, r, q)) {
         v[u] = load(l, r, q);
         pos[u] = l * L;
         rr[u] = r;
@@ -443,10 +451,11 @@ __device__ __forceinline__ void lines_store_blk(const Cx<R> *buf, const LineTile
   const int tid = threadIdx.x;
   const int L = 1 << t.lg;
   const R c = (R)1 / sqrt((R)L);
-  const int total = tile_elems_blk(t);
+  constexpr int LGW = BlkW<R>::lg;
+  const int total = tile_elems_blk<LGW>(t);
   for (int e = tid; e < total; e += NT) {
     int l, r, q;
-    if (split_blk(t, e, l, r, q)) store(l, r, q, dst_out(buf[l * L + r + 1], c));
+    if (split_blk<LGW>(t, e, l, r, q)) store(l, r, q, dst_out(buf[l * L + r + 1], c));
   }
   __syncthreads();
 }
@@ -832,7 +841,8 @@ template <typename R, int LDSB> struct GemmEng {
   template <int U, class Load>
   static __device__ __forceinline__ void fill_blk(Cx<R> *buf, const LineTile &t, Load &&load) {
     const int np = gemm_np(t.n);
-    const int total = tile_elems_blk(t);
+    constexpr int LGW = BlkW<R>::lg;
+    const int total = tile_elems_blk<LGW>(t);
     const int tid = threadIdx.x;
     for (int e0 = 0; e0 < total; e0 += NT * U) {
       Cx<R> v[U];
@@ -842,7 +852,7 @@ template <typename R, int LDSB> struct GemmEng {
         const int e = e0 + u * NT + tid;
         pos[u] = -1;
         int l, r, q;
-        if (e < total && split_blk(t, e, l, r, q)) {
+        if (e < total && split_blk<LGW>(t, e, l, r, q)) {
           v[u] = load(l, r, q);
           pos[u] = l * np + r;
         }
@@ -857,10 +867,11 @@ template <typename R, int LDSB> struct GemmEng {
   static __device__ __forceinline__ void store_blk(const Cx<R> *out, const LineTile &t,
                                                    Store &&st) {
     const int np = gemm_np(t.n);
-    const int total = tile_elems_blk(t);
+    constexpr int LGW = BlkW<R>::lg;
+    const int total = tile_elems_blk<LGW>(t);
     for (int e = threadIdx.x; e < total; e += NT) {
       int l, r, q;
-      if (split_blk(t, e, l, r, q)) st(l, r, q, out[l * np + r]);
+      if (split_blk<LGW>(t, e, l, r, q)) st(l, r, q, out[l * np + r]);
     }
     __syncthreads();
   }
