@@ -57,6 +57,10 @@ def parse():
     ap.add_argument("--count", type=int, default=64)
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the creation-time batch schedule")
+    ap.add_argument("--tile-points", type=int, default=0,
+                    help="fix the batch schedule's tile size (skips the tuner)")
+    ap.add_argument("--lds-bytes", type=int, default=0,
+                    help="fix the batch schedule's LDS budget (skips the tuner)")
     ap.add_argument("--batch-only", action="store_true",
                     help="time only the batched solve (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -159,12 +163,16 @@ def main():
 
     # ---------------- batched mixed precision (the measured step)
     probs32 = [C.Problem(a, s.lam.real, s.lam.imag, pinv_fp32=True) for a, s in zip(A, w.systems)]
-    batch = C.Batch(probs32, tol=1e-8, maxit=1000, check_true=True, use_graph=True)
+    fixed = args.no_tune or args.tile_points > 0 or args.lds_bytes > 0
+    batch = C.Batch(probs32, tol=1e-8, maxit=1000, check_true=True, use_graph=True,
+                    tile_points=args.tile_points, lds_bytes=args.lds_bytes)
     Z = [torch.empty_like(f) for f in F]
     stream = torch.cuda.current_stream()
     # schedule (tile size, LDS budget) chosen by the batch autotuner, outside
     # the timed region
-    tuning = batch.tune(F, Z) if not args.no_tune else None
+    tuning = batch.tune(F, Z) if not fixed else {"tile_points": args.tile_points or 8192,
+                                                 "lds_bytes": args.lds_bytes or 32768,
+                                                 "fixed": True}
     log("schedule:", tuning)
     zs, infos = batch.solve(F, Z)
     log("batch iters:", [i["iters"] for i in infos])

@@ -590,7 +590,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void so
         backoff = 0;
       } else {
         // nothing ready: stop when every system is done or on error / time
-        // limit, else back off (up to ~4 us) before looking again
+        // limit, else back off exponentially (up to ~14 us) before looking again
         if (__hip_atomic_load(&G->active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= 0 ||
             __hip_atomic_load(&G->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
           found = -2;
@@ -599,7 +599,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void so
             __hip_atomic_fetch_or(&G->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           found = -2;
         } else {
-          backoff = backoff < 16 ? backoff + 1 : 16;
+          backoff = backoff < 64 ? backoff * 2 + 1 : 64;
           for (int i = 0; i < backoff; ++i) __builtin_amdgcn_s_sleep(8);
         }
       }
