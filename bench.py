@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=40,
                     help="systems of the batch timed with the CPU oracle")
     ap.add_argument("--count", type=int, default=64)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the other workloads (c1, c2, c3, adjoint)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the creation-time batch schedule")
     ap.add_argument("--tile-points", type=int, default=0,
@@ -133,6 +135,70 @@ def cpu_baseline(workload, systems_idx, gpu_solutions):
         zg = gpu_solutions[j]
         errs.append(float(np.linalg.norm(zg - zo) / np.linalg.norm(zo)))
     return t_total, errs, iters
+
+
+def time_solve(C, p, f, z, reps):
+    import torch
+    C.minres_solve(p, f, z, want_info=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        C.minres_solve(p, f, z, want_info=False)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    _, info = C.minres_solve(p, f, z)
+    return ms, info
+
+
+def other_configs(C, WL, dev):
+    """The other workloads, each on its own (not part of the timed step):
+    plain FP64 solves of the 2-D cases, the 3-D case with the FP64 and the
+    FP32 preconditioner, and the adjoint workload (solve + adjoint of every
+    shift)."""
+    import torch
+    out = {}
+    for name, fp32s in (("c1", (False,)), ("c2", (False,)), ("c2_const", (False,)),
+                        ("c3", (False, True))):
+        s = WL.workload(name).systems[0]
+        a = torch.from_numpy(s.a).to(dev)
+        f = torch.from_numpy(s.f).to(dev)
+        z = torch.empty_like(f)
+        for fp32 in fp32s:
+            p = C.Problem(a, s.lam.real, s.lam.imag, pinv_fp32=fp32)
+            reps = 20 if s.a.size < 100000 else 3
+            ms, info = time_solve(C, p, f, z, reps)
+            bpp = (248.0 if fp32 else (296.0 if s.a.ndim == 2 else 360.0))
+            out[f"{name}_{'fp32p' if fp32 else 'fp64'}"] = {
+                "points": int(s.a.size), "ms_per_solve": ms, "iters": info["iters"],
+                "relres_true": info["relres_true"], "status": info["status_name"],
+                "alg_GBps": info["iters"] * s.a.size * bpp / ms / 1e6}
+    if "c3_fp64" in out and "c3_fp32p" in out:
+        out["c3_speedup_fp32p_vs_fp64"] = out["c3_fp64"]["ms_per_solve"] / out["c3_fp32p"]["ms_per_solve"]
+    # adjoint workload: 16 shifts sharing one coefficient, loss sum ||z - zt||^2
+    w = WL.workload("c5")
+    at = torch.from_numpy(w.systems[0].a).to(dev)
+    probs = [C.Problem(at, s.lam.real, s.lam.imag) for s in w.systems]
+    fs = [torch.from_numpy(s.f).to(dev) for s in w.systems]
+    zts = [torch.from_numpy(s.z_target).to(dev) for s in w.systems]
+
+    def run():
+        ga = torch.zeros_like(at)
+        worst = 0.0
+        for p, f, zt in zip(probs, fs, zts):
+            z, info = C.minres_solve(p, f)
+            g, ainfo = C.minres_adjoint(p, z, 2.0 * (z - zt), ga=ga)
+            worst = max(worst, info["relres_true"], ainfo["relres_true"])
+        return worst
+
+    run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    worst = run()
+    torch.cuda.synchronize()
+    out["c5_adjoint"] = {"systems": len(w.systems), "points_each": int(w.systems[0].a.size),
+                         "ms_forward_plus_adjoint_all": (time.perf_counter() - t0) * 1e3,
+                         "max_relres": worst}
+    return out
 
 
 def main():
@@ -240,6 +306,7 @@ def main():
         err_vs_oracle = max(errs)
         log("oracle iters", it_o, "gpu", iters[:k], "max rel err vs oracle", err_vs_oracle)
 
+    extra = None if args.no_extra else other_configs(C, WL, dev)
     out = {
         "metric": METRIC,
         "value": value,
@@ -272,6 +339,7 @@ def main():
         "max_relres_true": max(relres),
         "all_converged": all(s == 0 for s in statuses),
         "max_rel_err_vs_fp64_oracle": err_vs_oracle,
+        "other_configs": extra,
     }
     print(json.dumps(out), flush=True)
 
