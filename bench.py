@@ -165,13 +165,16 @@ def other_configs(C, WL, dev):
         z = torch.empty_like(f)
         for fp32 in fp32s:
             p = C.Problem(a, s.lam.real, s.lam.imag, pinv_fp32=fp32)
+            sched = p.tune(f, z)
             reps = 20 if s.a.size < 100000 else 3
             ms, info = time_solve(C, p, f, z, reps)
             bpp = (248.0 if fp32 else (296.0 if s.a.ndim == 2 else 360.0))
             out[f"{name}_{'fp32p' if fp32 else 'fp64'}"] = {
                 "points": int(s.a.size), "ms_per_solve": ms, "iters": info["iters"],
                 "relres_true": info["relres_true"], "status": info["status_name"],
-                "alg_GBps": info["iters"] * s.a.size * bpp / ms / 1e6}
+                "alg_GBps": info["iters"] * s.a.size * bpp / ms / 1e6,
+                "schedule": {"tile_points": sched["tile_points"],
+                             "lds_bytes": sched["lds_bytes"]}}
     if "c3_fp64" in out and "c3_fp32p" in out:
         out["c3_speedup_fp32p_vs_fp64"] = out["c3_fp64"]["ms_per_solve"] / out["c3_fp32p"]["ms_per_solve"]
     # adjoint workload: 16 shifts sharing one coefficient, loss sum ||z - zt||^2
@@ -278,6 +281,14 @@ def main():
     probs64 = [C.Problem(a, s.lam.real, s.lam.imag, pinv_fp32=False)
                for a, s in zip(A, w.systems)]
     Z64 = [torch.empty_like(f) for f in F]
+    # each grid size's single-solve schedule from the problem autotuner
+    plain_sched = {}
+    for p, f, z, s in zip(probs64, F, Z64, w.systems):
+        if s.n not in plain_sched:
+            t = p.tune(f, z)
+            plain_sched[s.n] = (t["tile_points"], t["lds_bytes"])
+        else:
+            p.set_schedule(*plain_sched[s.n])
     for p, f, z in zip(probs64, F, Z64):
         C.minres_solve(p, f, z, want_info=False)
     torch.cuda.synchronize()
@@ -333,7 +344,8 @@ def main():
         "cpu_baseline": cpu,
         "plain_fp64": {"value": plain_value, "unit": "solves/s",
                        "ms_per_64": plain_wall * 1e3,
-                       "iters_min": min(iters64), "iters_max": max(iters64)},
+                       "iters_min": min(iters64), "iters_max": max(iters64),
+                       "schedules": {str(k): v for k, v in plain_sched.items()}},
         "speedup_vs_plain_fp64": value / plain_value,
         "iters": {"min": min(iters), "max": max(iters), "sum": int(sum(iters))},
         "max_relres_true": max(relres),

@@ -146,6 +146,14 @@ csl_status destroy_problem(csl_problem p);
 csl_status problem_info(csl_problem p, double *abar, double *a_min,
                         double *a_max);
 
+/* Schedule of the problem's own solves (minres_solve, minres_adjoint):
+ * tile_points grid points per scheduling tile (0 = about one tile per
+ * workgroup and phase, which lets a single solve fill the device; 1 = one
+ * LDS chunk per tile) and the LDS line budget (0 or 32768 = default, 65536
+ * = 64 KiB).  Batches keep their own schedule.  Synchronises s. */
+csl_status problem_set_schedule(csl_problem p, int tile_points, int lds_bytes,
+                                hipStream_t s);
+
 /* Sine-transform engine in use along each axis (CSL_DST_FFT or
  * CSL_DST_GEMM; entries past the grid's dimension are CSL_DST_FFT). */
 csl_status problem_dst_engines(csl_problem p, int engines[3]);
@@ -203,7 +211,7 @@ typedef struct csl_batch_opts {
     int reserved[1];
 } csl_batch_opts;
 
-/* Schedule chosen by batch_tune. */
+/* Schedule chosen by batch_tune or problem_tune. */
 typedef struct csl_batch_tuning {
     int tile_points;        /* chosen grid points per tile                      */
     int lds_bytes;          /* chosen LDS budget (32768 or 65536)               */
@@ -228,6 +236,13 @@ csl_status batch_create(const csl_problem *problems, int count,
  * non-OK status). */
 csl_status batch_solve(csl_batch b, const double *const *f, double *const *z,
                        csl_solve_info *infos, hipStream_t s);
+
+/* Autotuner of a problem's own schedule: solves (K + lambda I) z = f with
+ * each candidate tile size and LDS budget (tol 1e-8), timing each on
+ * stream s, and keeps the fastest (problem_set_schedule).  Blocks until
+ * done; out may be NULL (its grid_size is the single-solve grid). */
+csl_status problem_tune(csl_problem p, const double *f, double *z,
+                        csl_batch_tuning *out, hipStream_t s);
 
 /* Autotuner of the batch schedule: solves the batch for f (results in z)
  * with each candidate tile size and LDS budget, timing every candidate on

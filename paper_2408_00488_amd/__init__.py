@@ -98,6 +98,8 @@ def load_library():
     L.destroy_problem.argtypes = [vp]
     L.problem_info.argtypes = [vp, dp, dp, dp]
     L.problem_dst_engines.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+    L.problem_set_schedule.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp]
+    L.problem_tune.argtypes = [vp, vp, vp, ctypes.POINTER(_BatchTuning), vp]
     L.apply_A.argtypes = [vp, vp, vp, vp]
     L.apply_Pinv.argtypes = [vp, vp, vp, vp]
     L.minres_solve.argtypes = [vp, vp, vp, ctypes.POINTER(_SolveOpts),
@@ -114,6 +116,7 @@ def load_library():
     L.csl_last_error.restype = ctypes.c_char_p
     L.csl_version.restype = ctypes.c_int
     for fn in ("create_problem", "destroy_problem", "problem_info", "problem_dst_engines",
+               "problem_set_schedule", "problem_tune",
                "apply_A", "apply_Pinv",
                "minres_solve", "minres_adjoint", "batch_create", "batch_solve",
                "batch_tune", "batch_destroy"):
@@ -200,6 +203,25 @@ class Problem:
         if self._h is None:
             raise RuntimeError("problem destroyed")
         return self._h
+
+    def set_schedule(self, tile_points: int = 0, lds_bytes: int = 0):
+        """Schedule of this problem's own solves (see problem_set_schedule)."""
+        _check(load_library().problem_set_schedule(self.handle, int(tile_points), int(lds_bytes),
+                                                   _stream(self.device)))
+
+    def tune(self, f, z=None) -> dict:
+        """Time candidate schedules of minres_solve on f and keep the fastest."""
+        torch = _torch()
+        self._vec(f, "f")
+        if z is None:
+            z = torch.empty_like(f)
+        self._vec(z, "z")
+        t = _BatchTuning()
+        _check(load_library().problem_tune(self.handle, _ptr(f), _ptr(z), ctypes.byref(t),
+                                           _stream(self.device)))
+        return {"tile_points": t.tile_points, "lds_bytes": t.lds_bytes,
+                "grid_size": t.grid_size, "candidates": t.candidates, "ms": t.ms,
+                "ms_default": t.ms_default}
 
     def close(self):
         if getattr(self, "_h", None) is not None:

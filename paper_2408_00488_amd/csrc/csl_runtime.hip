@@ -116,6 +116,11 @@ struct csl_problem_s {
   size_t smem = 0;
   int grid1 = 1;
   int tile_elems = 0;
+  SysDesc h0{};          // creation-time tiling (one chunk per tile)
+  size_t smem0 = 0;
+  int cap = 1;           // workgroups that fill the device at this problem's LDS budget
+  int tile_points = 0;   // current schedule of the problem's own solves
+  int lds_bytes = 0;
 };
 
 struct csl_batch_s {
@@ -270,10 +275,11 @@ hipError_t launch_pinv_all(csl_problem p, const double2 *x, double2 *y, hipStrea
   const int pass[5] = {0, 1, 2, 3, 4};
   for (int k = 0; k < 5; ++k) {
     if (h.d == 2 && (pass[k] == 1 || pass[k] == 3)) continue;
+    // one workgroup per LDS chunk (the solver's tiles may group chunks)
     const int nt = pass[k] == 0 || pass[k] == 4 ? nrow
-                   : pass[k] == 2             ? h.ntile[K_Y]
-                   : pass[k] == 1             ? h.ntile[K_Y1]
-                                              : h.ntile[K_Y1I];
+                   : pass[k] == 2             ? h.nchunk[K_Y]
+                   : pass[k] == 1             ? h.nchunk[K_Y1]
+                                              : h.nchunk[K_Y1I];
     const hipError_t e = launch_pinv_pass(p->d_desc, h.d, h.prec, pass[k], nt, p->smem, x, y, s);
     if (e != hipSuccess) return e;
   }
@@ -319,6 +325,32 @@ csl_status tune_engines(csl_problem p, int elig, hipStream_t s, int *best_mask) 
   return CSL_OK;
 }
 
+// Schedule of a problem's own solves: the creation-time tiling with an LDS
+// budget of at least `lds_bytes` and chunks grouped into tiles of
+// `tile_points` points (0: about one tile per workgroup and phase, since a
+// single solve has the whole device).
+csl_status configure_single(csl_problem p, int tile_points, int lds_bytes, hipStream_t s) {
+  SysDesc h = p->h0;
+  size_t sm = p->smem0;
+  if (lds_bytes > 32768 && p->smem0 <= 32768) choose_tiles(h, p->tile_elems, lds_bytes, &sm);
+  int bpc = 0;
+  HIPCHK(solve_occupancy(sm, &bpc));
+  const int cap = std::max(1, bpc) * p->cus;
+  const int tp = tile_points > 0 ? tile_points : (int)std::min<long long>(1 << 30, h.M / cap);
+  set_tile_points(h, tp);
+  int mt = 1;
+  for (int k = 0; k < K_NKINDS; ++k) mt = std::max(mt, h.ntile[k]);
+  HIPCHK(hipMemcpyAsync(p->d_desc, &h, sizeof(SysDesc), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  p->h = h;
+  p->smem = sm;
+  p->cap = cap;
+  p->grid1 = std::max(1, std::min(mt, cap));
+  p->tile_points = tile_points;
+  p->lds_bytes = sm <= 32768 ? 32768 : 65536;
+  return CSL_OK;
+}
+
 // Schedule of a batch: descriptor copies tiled for `tile_points` grid points
 // per tile and an LDS budget of at least `lds_bytes`, the grid, and (if
 // asked) the captured graph of one solve.  Called at creation and by the
@@ -332,9 +364,9 @@ csl_status configure_batch(csl_batch b, int tile_points, int lds_bytes, bool gra
   size_t smem = 0;
   for (int i = 0; i < b->count; ++i) {
     const csl_problem p = b->probs[i];
-    descs[i] = p->h;
-    size_t sm = p->smem;
-    if (lds_bytes > 32768 && p->smem <= 32768) {
+    descs[i] = p->h0;
+    size_t sm = p->smem0;
+    if (lds_bytes > 32768 && p->smem0 <= 32768) {
       // a larger budget only lengthens the chunks: chunk counts (and with
       // them the partial-sum slots each problem allocated) can only shrink
       choose_tiles(descs[i], p->tile_elems, lds_bytes, &sm);
@@ -661,10 +693,15 @@ csl_status create_problem(const csl_grid *grid, const double *a_nodal, double al
   for (int ax = 0; ax < 3; ++ax) p->h.gemm[ax] = (mask >> ax) & 1;
   PCHK(hipMemcpyAsync(p->d_desc, &p->h, sizeof(SysDesc), hipMemcpyHostToDevice, s));
   PCHK(hipStreamSynchronize(s));
-  int bpc = 0;
-  PCHK(solve_occupancy(p->smem, &bpc));
-  const int cap = std::max(1, bpc) * p->cus;
-  p->grid1 = std::max(1, std::min(h.maxtile, cap));
+  p->h0 = p->h;
+  p->smem0 = p->smem;
+  {
+    const csl_status st = configure_single(p, 0, 0, s);
+    if (st != CSL_OK) {
+      free_problem(p);
+      return st;
+    }
+  }
 #undef PCHK
   *out = p;
   return CSL_OK;
@@ -739,6 +776,77 @@ csl_status minres_solve(csl_problem p, const double *f, double *z, const csl_sol
   if (st != CSL_OK) return st;
   if (!info) return CSL_OK;
   return fetch_single_info(p, info, s);
+}
+
+csl_status problem_set_schedule(csl_problem p, int tile_points, int lds_bytes, hipStream_t s) {
+  if (!p) return fail(CSL_ERR_ARG, "problem is NULL");
+  if (tile_points < 0) return fail(CSL_ERR_ARG, "tile_points must be >= 0");
+  if (lds_bytes != 0 && lds_bytes != 32768 && lds_bytes != 65536)
+    return fail(CSL_ERR_ARG, "lds_bytes must be 0, 32768 or 65536");
+  return configure_single(p, tile_points, lds_bytes, s);
+}
+
+csl_status problem_tune(csl_problem p, const double *f, double *z, csl_batch_tuning *out,
+                        hipStream_t s) {
+  if (!p || !f || !z) return fail(CSL_ERR_ARG, "NULL argument");
+  if (f == z) return fail(CSL_ERR_ARG, "problem_tune: f and z must not alias");
+  const int tp0 = p->tile_points, lds0 = p->lds_bytes;
+  const long long per_wg = std::max<long long>(1, p->h.M / std::max(1, p->cap));
+  std::vector<std::pair<int, int>> cands;
+  cands.push_back({tp0, lds0});
+  for (int lds : {32768, 65536})
+    for (long long tp : {0LL, 1LL, per_wg / 2, per_wg * 2, 8192LL})
+      if (tp >= 0 && !((int)tp == tp0 && lds == lds0)) cands.push_back({(int)tp, lds});
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(CSL_ERR_HIP, "hipEventCreate failed");
+  }
+  const SolveParams P = make_params(0.0, 0, 1, 0, p->wall_khz);
+  double best = INFINITY, first = INFINITY;
+  int best_tp = tp0, best_lds = lds0, timed = 0;
+  csl_status st = CSL_OK;
+  for (size_t c = 0; c < cands.size() && st == CSL_OK; ++c) {
+    st = configure_single(p, cands[c].first, cands[c].second, s);
+    if (st != CSL_OK) break;
+    if (c > 0 && p->lds_bytes != cands[c].second) continue;   // budget not applicable
+    st = run_single(p, (const double2 *)f, (double2 *)z, P, s);   // warm-up
+    float ms = 0.f, tot = 0.f;
+    const int reps = 2;
+    for (int r = 0; r < reps && st == CSL_OK; ++r) {
+      if (hipEventRecord(e0, s) != hipSuccess) st = fail(CSL_ERR_HIP, "hipEventRecord failed");
+      if (st == CSL_OK) st = run_single(p, (const double2 *)f, (double2 *)z, P, s);
+      if (st == CSL_OK && (hipEventRecord(e1, s) != hipSuccess ||
+                           hipEventSynchronize(e1) != hipSuccess ||
+                           hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        st = fail(CSL_ERR_HIP, "event timing failed");
+      tot += ms;
+    }
+    if (st != CSL_OK) break;
+    const double avg = tot / reps;
+    ++timed;
+    if (c == 0) first = avg;
+    if (avg < best) {
+      best = avg;
+      best_tp = cands[c].first;
+      best_lds = p->lds_bytes;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  const csl_status st2 = configure_single(p, best_tp, best_lds, s);
+  if (st != CSL_OK) return st;
+  if (st2 != CSL_OK) return st2;
+  if (out) {
+    out->tile_points = best_tp;
+    out->lds_bytes = p->lds_bytes;
+    out->grid_size = p->grid1;
+    out->candidates = timed;
+    out->ms = best;
+    out->ms_default = first;
+  }
+  return CSL_OK;
 }
 
 csl_status minres_adjoint(csl_problem p, const double *z, const double *gz, double *gf,

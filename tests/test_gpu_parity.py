@@ -368,3 +368,27 @@ def test_batch_lds_budget_and_tuner(csl):
         assert np.array_equal(a_, b_.cpu().numpy())
     with pytest.raises(csl.CSLError):
         csl.Batch(probs, lds_bytes=12345)
+
+
+def test_problem_schedule_and_tuner(csl):
+    # single-solve schedules change the tile grouping and the LDS budget
+    # (summation order), not the method
+    s = WL.workload("c2", n_override=255).systems[0]
+    p = csl.Problem(cuda(s.a), s.lam.real, s.lam.imag)
+    f = cuda(s.f)
+    ref, info0 = csl.minres_solve(p, f)
+    r0 = ref.cpu().numpy()
+    for tp, lds in ((1, 0), (0, 65536), (4096, 0), (16384, 65536)):
+        p.set_schedule(tp, lds)
+        z, info = csl.minres_solve(p, f)
+        assert info["status"] == 0 and abs(info["iters"] - info0["iters"]) <= 1
+        assert rel(z.cpu().numpy(), r0) <= 1e-9
+        y = csl.apply_Pinv(p, f).cpu().numpy()
+        assert rel(y, O.apply_Pinv(s.f, p.abar, s.lam.real, s.lam.imag)) <= 1e-13
+    t = p.tune(f)
+    _say("problem tune", t)
+    assert t["candidates"] >= 2 and t["ms"] <= t["ms_default"] * 1.0000001
+    z, info = csl.minres_solve(p, f)
+    assert info["status"] == 0 and rel(z.cpu().numpy(), r0) <= 1e-9
+    with pytest.raises(csl.CSLError):
+        p.set_schedule(0, 1000)
