@@ -35,10 +35,11 @@ if ROOT not in sys.path:
 METRIC = "MINRES solves/s at relres 1e-8: batched mixed-precision vs plain FP64, 1 GPU"
 PEAK_HBM_GBS = 8000.0
 # Algorithmic HBM bytes per grid point per MINRES iteration (2-D, FP32
-# preconditioner): stencil 40 + Lanczos/w/x updates 160 + 3 sine-transform
-# passes of 16 bytes read + written.
-BYTES_PER_POINT_ITER_2D_FP32P = 248.0
-BYTES_PER_POINT_ITER_2D_FP64 = 296.0
+# preconditioner): stencil 40 + Lanczos/w/x 128 (the w/x updates of two
+# steps share one pass: 32 bytes less per iteration than one pass per step)
+# + 3 sine-transform passes of 16 bytes read + written.
+BYTES_PER_POINT_ITER_2D_FP32P = 216.0
+BYTES_PER_POINT_ITER_2D_FP64 = 264.0
 
 
 def log(*a):
@@ -168,7 +169,7 @@ def other_configs(C, WL, dev):
             sched = p.tune(f, z)
             reps = 20 if s.a.size < 100000 else 3
             ms, info = time_solve(C, p, f, z, reps)
-            bpp = (248.0 if fp32 else (296.0 if s.a.ndim == 2 else 360.0))
+            bpp = (216.0 if fp32 else (264.0 if s.a.ndim == 2 else 328.0))
             out[f"{name}_{'fp32p' if fp32 else 'fp64'}"] = {
                 "points": int(s.a.size), "ms_per_solve": ms, "iters": info["iters"],
                 "relres_true": info["relres_true"], "status": info["status_name"],

@@ -49,10 +49,20 @@ struct alignas(64) Ctl {
   double eta, eta0;          // residual recurrence
   double delta;              // delta_j
   double bnorm;              // ||f||_2
-  double e1, e2, e3, ceta;   // pending update of w and x
-  int has_update;
-  int pad;
+  double e1, e2, e3, ceta;   // update of w and x of the current step
+  double e1p, e2p, e3p, cetap;   // the previous step's, while its update is deferred
+  int zmode;                 // what the K_Z phase does (ZM_*)
+  int pend;                  // 1: the previous step's update is deferred
+  int fin_status, fin_iters; // finish after a ZM_FLUSH phase
 };
+
+// K_Z phase modes.  The w/x updates of MINRES run two steps at a time: a
+// step whose update is deferred (ZM_DEFER) only writes zhat_{j+1}; the next
+// K_Z phase then applies both steps in one pass over w, x and zhat
+// (ZM_PAIR), which halves the reads and writes of w and x.  ZM_SINGLE
+// applies one step (before a residual check or the end); ZM_FLUSH applies
+// a deferred step alone and ends the solve (breakdown, non-finite values).
+enum { ZM_DEFER = 0, ZM_SINGLE = 1, ZM_PAIR = 2, ZM_FLUSH = 3 };
 
 // Result record of one system (device side).
 struct DevInfo {

@@ -180,20 +180,51 @@ __device__ __forceinline__ void tile_Z(const SysDesc &S, const IOPtr &io, int it
                                  : reinterpret_cast<const R *>(S.Wmf[D - 1]);
   Cx<R> *buf = reinterpret_cast<Cx<R> *>(smem);
   Cx<R> *twl = reinterpret_cast<Cx<R> *>(smem + LDSB);
-  load_twiddles_cached<R>(twl, S.lg[D - 1]);
-  const int c1 = min(S.nchunk[K_Z], (tile + 1) * S.cpt[K_Z]);
-  for (int chunk = tile * S.cpt[K_Z]; chunk < c1; ++chunk) {
-  const LineTile t = line_tile(S, D - 1, S.lpt_z, chunk);
-  const CSL_G Cx<R> *T = gbl(reinterpret_cast<const Cx<R> *>(S.T));
-  const int j = iter;
   const Ctl *C = S.ctl;
+  const int j = iter;
+  const int mode = j == 0 ? ZM_DEFER : ld_ctl(&C->zmode);
+  CSL_G double2 *__restrict__ X = gbl(io.x);
+  const int c1 = min(S.nchunk[K_Z], (tile + 1) * S.cpt[K_Z]);
+  if (mode == ZM_FLUSH) {
+    // the deferred step m = j - 1 alone: w_j = (zhat_{j-1} - e3 w_{j-2} -
+    // e2 w_{j-1}) / e1 with step m's coefficients, x += ceta w_j
+    const double e1 = ld_ctl(&C->e1), e2 = ld_ctl(&C->e2), e3 = ld_ctl(&C->e3);
+    const double ceta = ld_ctl(&C->ceta);
+    const double ie1 = 1.0 / e1;
+    const CSL_G double2 *__restrict__ zm = gbl(S.Z[(j + 1) & 1]);
+    CSL_G double2 *__restrict__ wa = gbl(S.W[j & 1]);          // w_{j-2} -> w_j
+    const CSL_G double2 *__restrict__ wb = gbl(S.W[(j + 1) & 1]);   // w_{j-1}
+    const bool use_a = j > 3, use_b = j > 2, use_x = j > 2;
+    for (int chunk = tile * S.cpt[K_Z]; chunk < c1; ++chunk) {
+      const LineTile t = line_tile(S, D - 1, S.lpt_z, chunk);
+      const int total = tile_elems(t);
+      for (int e = threadIdx.x; e < total; e += NT) {
+        int l, r;
+        if (!split_elem(t, e, l, r)) continue;
+        const int p = t.base + l * t.lstride + r * t.stride;
+        const double2 z = ldg(zm + p);
+        const double2 w0 = use_a ? ldg(wa + p) : make_double2(0.0, 0.0);
+        const double2 w1 = use_b ? ldg(wb + p) : make_double2(0.0, 0.0);
+        const double2 x = use_x ? ldg(X + p) : make_double2(0.0, 0.0);
+        const double wx = (z.x - e3 * w0.x - e2 * w1.x) * ie1;
+        const double wy = (z.y - e3 * w0.y - e2 * w1.y) * ie1;
+        st_nt(wa + p, wx, wy);
+        st_nt(X + p, x.x + ceta * wx, x.y - ceta * wy);
+      }
+    }
+    return;
+  }
+  load_twiddles_cached<R>(twl, S.lg[D - 1]);
+  const CSL_G Cx<R> *T = gbl(reinterpret_cast<const Cx<R> *>(S.T));
   const double g = ld_ctl(&C->gamma);
   const bool store_z = (g != 0.0);
   const double ig = store_z ? 1.0 / g : 0.0;
   CSL_G double2 *__restrict__ znew = gbl(S.Z[(j + 1) & 1]);
+  for (int chunk = tile * S.cpt[K_Z]; chunk < c1; ++chunk) {
+  const LineTile t = line_tile(S, D - 1, S.lpt_z, chunk);
   E::template fill_blk<8>(buf, t, [&](int, int, int q) { return ldg(T + q); });
   const Cx<R> *o = E::transform(buf, t, twl, Wm);
-  if (j == 0) {
+  if (mode == ZM_DEFER) {
     E::store(o, t, [&](int, int, int p, Cx<R> v) {
       st_nt(znew + p, (double)v.x * ig, (double)v.y * ig);
     });
@@ -203,29 +234,69 @@ __device__ __forceinline__ void tile_Z(const SysDesc &S, const IOPtr &io, int it
   const double ceta = ld_ctl(&C->ceta);
   const double ie1 = 1.0 / e1;
   const CSL_G double2 *__restrict__ zj = gbl(S.Z[j & 1]);
-  CSL_G double2 *__restrict__ wnew = gbl(S.W[(j + 1) & 1]);   // holds w_{j-1} before the update
-  const CSL_G double2 *__restrict__ wj = gbl(S.W[j & 1]);
-  CSL_G double2 *__restrict__ X = gbl(io.x);
-  const bool use_wm1 = j > 2, use_wj = j > 1, use_x = j > 1;
-  struct In4 {
-    double2 z, w0, w1, x;
+  if (mode == ZM_SINGLE) {
+    CSL_G double2 *__restrict__ wnew = gbl(S.W[(j + 1) & 1]);   // holds w_{j-1} before the update
+    const CSL_G double2 *__restrict__ wj = gbl(S.W[j & 1]);
+    const bool use_wm1 = j > 2, use_wj = j > 1, use_x = j > 1;
+    struct In4 {
+      double2 z, w0, w1, x;
+    };
+    E::template store2<2>(
+        o, t,
+        [&](int p) {
+          In4 in;
+          in.z = ldg(zj + p);
+          in.w0 = use_wm1 ? ldg(wnew + p) : make_double2(0.0, 0.0);
+          in.w1 = use_wj ? ldg(wj + p) : make_double2(0.0, 0.0);
+          in.x = use_x ? ldg(X + p) : make_double2(0.0, 0.0);
+          return in;
+        },
+        [&](int p, Cx<R> v, const In4 &in) {
+          if (store_z) st_nt(znew + p, (double)v.x * ig, (double)v.y * ig);
+          const double wx = (in.z.x - e3 * in.w0.x - e2 * in.w1.x) * ie1;
+          const double wy = (in.z.y - e3 * in.w0.y - e2 * in.w1.y) * ie1;
+          st_nt(wnew + p, wx, wy);
+          st_nt(X + p, in.x.x + ceta * wx, in.x.y - ceta * wy);
+        });
+    continue;
+  }
+  // ZM_PAIR: steps j-1 (deferred, coefficients e*p) and j:
+  //   w_j     = (zhat_{j-1} - e3p w_{j-2} - e2p w_{j-1}) / e1p
+  //   w_{j+1} = (zhat_j     - e3  w_{j-1} - e2  w_j    ) / e1
+  //   x += cetap w_j, then x += ceta w_{j+1}
+  // zhat_{j-1} sits in the buffer that receives zhat_{j+1}, w_{j-2} in the
+  // one that receives w_j: each entry is read before it is overwritten by
+  // the same thread.
+  const double e1p = ld_ctl(&C->e1p), e2p = ld_ctl(&C->e2p), e3p = ld_ctl(&C->e3p);
+  const double cetap = ld_ctl(&C->cetap);
+  const double ie1p = 1.0 / e1p;
+  CSL_G double2 *__restrict__ wa = gbl(S.W[j & 1]);           // w_{j-2} -> w_j
+  CSL_G double2 *__restrict__ wb = gbl(S.W[(j + 1) & 1]);     // w_{j-1} -> w_{j+1}
+  const bool use_a = j > 3, use_b = j > 2, use_x = j > 2;
+  struct In5 {
+    double2 zm, z, wa, wb, x;
   };
-  E::template store2<2>(
+  E::template store2<1>(
       o, t,
       [&](int p) {
-        In4 in;
+        In5 in;
+        in.zm = ldg(znew + p);   // zhat_{j-1}
         in.z = ldg(zj + p);
-        in.w0 = use_wm1 ? ldg(wnew + p) : make_double2(0.0, 0.0);
-        in.w1 = use_wj ? ldg(wj + p) : make_double2(0.0, 0.0);
+        in.wa = use_a ? ldg(wa + p) : make_double2(0.0, 0.0);
+        in.wb = use_b ? ldg(wb + p) : make_double2(0.0, 0.0);
         in.x = use_x ? ldg(X + p) : make_double2(0.0, 0.0);
         return in;
       },
-      [&](int p, Cx<R> v, const In4 &in) {
+      [&](int p, Cx<R> v, const In5 &in) {
         if (store_z) st_nt(znew + p, (double)v.x * ig, (double)v.y * ig);
-        const double wx = (in.z.x - e3 * in.w0.x - e2 * in.w1.x) * ie1;
-        const double wy = (in.z.y - e3 * in.w0.y - e2 * in.w1.y) * ie1;
-        st_nt(wnew + p, wx, wy);
-        st_nt(X + p, in.x.x + ceta * wx, in.x.y - ceta * wy);
+        const double ax = (in.zm.x - e3p * in.wa.x - e2p * in.wb.x) * ie1p;
+        const double ay = (in.zm.y - e3p * in.wa.y - e2p * in.wb.y) * ie1p;
+        const double bx = (in.z.x - e3 * in.wb.x - e2 * ax) * ie1;
+        const double by = (in.z.y - e3 * in.wb.y - e2 * ay) * ie1;
+        st_nt(wa + p, ax, ay);
+        st_nt(wb + p, bx, by);
+        const double xx = in.x.x + cetap * ax, xy = in.x.y - cetap * ay;
+        st_nt(X + p, xx + ceta * bx, xy - ceta * by);
       });
   }
 }
@@ -394,6 +465,22 @@ __device__ __forceinline__ void finish(const SysDesc &S, Glob *G, int iter, int 
 
 enum { ST_OK = 0, ST_NOT_CONVERGED = 3, ST_BREAKDOWN = 4, ST_NONFINITE = 5 };
 
+// End a solve early at iteration iter with the iterate x_{iters}: if the
+// update of step iter - 1 is still deferred, run one K_Z phase that applies
+// it alone (ZM_FLUSH) and finish from its epilogue.
+__device__ __forceinline__ void end_solve(const SysDesc &S, Glob *G, Ctl *C, int iter, int status,
+                                          int iters) {
+  if (C->pend) {
+    C->pend = 0;
+    C->zmode = ZM_FLUSH;
+    C->fin_status = status;
+    C->fin_iters = iters;
+    publish(C, iter, K_Z);
+  } else {
+    finish(S, G, iter, status, iters, __longlong_as_double(0x7ff8000000000000ll));
+  }
+}
+
 __device__ __forceinline__ void epilogue(const SysDesc &S, const SolveParams &P, int kind, int iter, Glob *G,
                          double *red) {
   const int nt = S.ntile[kind];
@@ -422,7 +509,7 @@ __device__ __forceinline__ void epilogue(const SysDesc &S, const SolveParams &P,
         publish(C, 0, first_strided);
       }
     } else if (!isfinite(sum)) {
-      finish(S, G, iter, ST_NONFINITE, iter - 1, nan);
+      end_solve(S, G, C, iter, ST_NONFINITE, iter - 1);
     } else {
       C->delta = sum;
       publish(C, iter, first_strided);
@@ -441,7 +528,8 @@ __device__ __forceinline__ void epilogue(const SysDesc &S, const SolveParams &P,
     const double g2 = sum;
     if (!isfinite(g2)) {
       S.info->relres_est = nan;
-      finish(S, G, iter, ST_NONFINITE, iter > 0 ? iter - 1 : 0, nan);
+      if (iter == 0) finish(S, G, iter, ST_NONFINITE, 0, nan);
+      else end_solve(S, G, C, iter, ST_NONFINITE, iter - 1);
       return;
     }
     if (iter == 0) {
@@ -460,11 +548,12 @@ __device__ __forceinline__ void epilogue(const SysDesc &S, const SolveParams &P,
       C->s = 0.0;
       C->s_old = 0.0;
       C->after_z = 0;
+      C->pend = 0;
       publish(C, 0, S.d == 3 ? K_Y1I : K_Z);
       return;
     }
     if (g2 < 0.0) {
-      finish(S, G, iter, ST_BREAKDOWN, iter - 1, nan);
+      end_solve(S, G, C, iter, ST_BREAKDOWN, iter - 1);
       return;
     }
     // Givens rotations of column j of the Lanczos tridiagonal (step j)
@@ -476,6 +565,13 @@ __device__ __forceinline__ void epilogue(const SysDesc &S, const SolveParams &P,
     const double e2 = s * dl + co * c * g;
     const double e3 = so * g;
     const double cn = e0 / e1, sn = gn / e1;
+    if (C->pend) {
+      // step j-1's update is still to be applied (with this step's)
+      C->e1p = C->e1;
+      C->e2p = C->e2;
+      C->e3p = C->e3;
+      C->cetap = C->ceta;
+    }
     C->e1 = e1;
     C->e2 = e2;
     C->e3 = e3;
@@ -502,11 +598,15 @@ __device__ __forceinline__ void epilogue(const SysDesc &S, const SolveParams &P,
     } else {
       C->after_z = 0;
     }
+    const int zm = C->pend ? ZM_PAIR : (C->after_z != 0 ? ZM_SINGLE : ZM_DEFER);
+    C->zmode = zm;
+    C->pend = (zm == ZM_DEFER);
     publish(C, iter, S.d == 3 ? K_Y1I : K_Z);
     return;
   }
   if (kind == K_Z) {
-    if (iter == 0 || C->after_z == 0) publish(C, iter + 1, K_X);
+    if (iter > 0 && C->zmode == ZM_FLUSH) finish(S, G, iter, C->fin_status, C->fin_iters, nan);
+    else if (iter == 0 || C->after_z == 0) publish(C, iter + 1, K_X);
     else publish(C, iter, K_PR);
     return;
   }
@@ -638,6 +738,8 @@ __global__ void init_kernel(const SysDesc *__restrict__ sys, int nsys, Glob *G) 
     C->done = 0;
     C->finishing = -1;
     C->after_z = 0;
+    C->pend = 0;
+    C->zmode = ZM_DEFER;
     DevInfo *I = sys[s].info;
     I->status = -1;
     I->iters = 0;
