@@ -392,3 +392,20 @@ def test_problem_schedule_and_tuner(csl):
     assert info["status"] == 0 and rel(z.cpu().numpy(), r0) <= 1e-9
     with pytest.raises(csl.CSLError):
         p.set_schedule(0, 1000)
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_iterate_after_k_steps(csl, fp32):
+    # stopping at every k exercises the paired w/x updates in all their
+    # forms: a deferred step applied alone (odd k) or with its successor
+    # (even k), against the oracle's iterate after exactly k steps
+    s = WL.workload("c1", n_override=31).systems[0]
+    p = csl.Problem(cuda(s.a), s.lam.real, s.lam.imag, pinv_fp32=fp32)
+    po = O.Problem(s.a, s.lam.real, s.lam.imag, abar_rule="given", abar=p.abar)
+    f = cuda(s.f)
+    for k in range(1, 8):
+        z, info = csl.minres_solve(p, f, maxit=k, tol=1e-30, raise_on_error=False)
+        assert info["iters"] == k and info["status_name"] == "ERR_NOT_CONVERGED", info
+        zo, io = po.solve(s.f, fixed_iters=k)
+        assert rel(z.cpu().numpy(), zo) <= (1e-6 if fp32 else 1e-12), k
+        assert info["relres_est"] == pytest.approx(io["relres_est"], rel=1e-5 if fp32 else 1e-9)
