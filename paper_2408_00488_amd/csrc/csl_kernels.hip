@@ -445,9 +445,12 @@ __device__ __forceinline__ void tile_pinv(const SysDesc &S, int pass, const doub
 // Givens recurrences, takes the stopping decision and publishes the next
 // phase of this system.
 // ---------------------------------------------------------------------------
+// The release exchange orders every earlier write of this thread (the reset
+// completion count, the scalars) before the new ticket word; on gfx950 an
+// agent-scope release writes back the L2, an acquire invalidates it, so no
+// fence beyond the one the protocol needs is issued.
 __device__ __forceinline__ void publish(Ctl *C, int iter, int kind) {
   __hip_atomic_store(&C->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __threadfence();
   __hip_atomic_exchange(&C->word, (unsigned long long)make_word(iter, kind), __ATOMIC_RELEASE,
                         __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -669,8 +672,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void so
           mask &= mask - 1ull;
           int got = 0;
           if (lane == ln) {
+            // relaxed claim; the acquire fence below, taken only when a tile
+            // was obtained, synchronises with the release that published the
+            // phase (an acquiring increment would invalidate the L2 on every
+            // attempt, a second time on success)
             const uint64_t w2 = __hip_atomic_fetch_add(&sys[sl].ctl->word, 1ull,
-                                                       __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const int kd2 = word_kind(w2);
             if (kd2 < K_NKINDS && word_next(w2) < (uint32_t)sys[sl].ntile[kd2]) {
               got = 1;
@@ -714,11 +721,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void so
       const IOPtr iop = io ? io[s] : io0;
       process_tile<LDSB>(S, iop, kind, iter, tile, smem, red);
       // every wave's stores are complete at the barrier; one agent-scope
-      // release then publishes them with the completion count
+      // release fence then publishes them with the (relaxed) completion
+      // count, and only the workgroup that completes the phase acquires
       __syncthreads();
       if (tid == 0) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const unsigned old = __hip_atomic_fetch_add(&S.ctl->done, 1u, __ATOMIC_ACQ_REL,
+        const unsigned old = __hip_atomic_fetch_add(&S.ctl->done, 1u, __ATOMIC_RELAXED,
                                                      __HIP_MEMORY_SCOPE_AGENT);
         const int last = (old + 1 == (unsigned)S.ntile[kind]);
         if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
