@@ -64,6 +64,8 @@ def parse():
                     help="fix the batch schedule's tile size (skips the tuner)")
     ap.add_argument("--lds-bytes", type=int, default=0,
                     help="fix the batch schedule's LDS budget (skips the tuner)")
+    ap.add_argument("--block-threads", type=int, default=0,
+                    help="fix the batch solver's workgroup size, 256 or 512 (skips the tuner)")
     ap.add_argument("--batch-only", action="store_true",
                     help="time only the batched solve (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -175,7 +177,8 @@ def other_configs(C, WL, dev):
                 "relres_true": info["relres_true"], "status": info["status_name"],
                 "alg_GBps": info["iters"] * s.a.size * bpp / ms / 1e6,
                 "schedule": {"tile_points": sched["tile_points"],
-                             "lds_bytes": sched["lds_bytes"]}}
+                             "lds_bytes": sched["lds_bytes"],
+                             "block_threads": sched["block_threads"]}}
     if "c3_fp64" in out and "c3_fp32p" in out:
         out["c3_speedup_fp32p_vs_fp64"] = out["c3_fp64"]["ms_per_solve"] / out["c3_fp32p"]["ms_per_solve"]
     # adjoint workload: 16 shifts sharing one coefficient, loss sum ||z - zt||^2
@@ -233,16 +236,15 @@ def main():
 
     # ---------------- batched mixed precision (the measured step)
     probs32 = [C.Problem(a, s.lam.real, s.lam.imag, pinv_fp32=True) for a, s in zip(A, w.systems)]
-    fixed = args.no_tune or args.tile_points > 0 or args.lds_bytes > 0
+    fixed = args.no_tune or args.tile_points > 0 or args.lds_bytes > 0 or args.block_threads > 0
     batch = C.Batch(probs32, tol=1e-8, maxit=1000, check_true=True, use_graph=True,
-                    tile_points=args.tile_points, lds_bytes=args.lds_bytes)
+                    tile_points=args.tile_points, lds_bytes=args.lds_bytes,
+                    block_threads=args.block_threads)
     Z = [torch.empty_like(f) for f in F]
     stream = torch.cuda.current_stream()
-    # schedule (tile size, LDS budget) chosen by the batch autotuner, outside
+    # schedule (tile size, LDS budget, workgroup size) chosen by the batch autotuner, outside
     # the timed region
-    tuning = batch.tune(F, Z) if not fixed else {"tile_points": args.tile_points or 8192,
-                                                 "lds_bytes": args.lds_bytes or 32768,
-                                                 "fixed": True}
+    tuning = batch.tune(F, Z) if not fixed else dict(batch.schedule, fixed=True)
     log("schedule:", tuning)
     zs, infos = batch.solve(F, Z)
     log("batch iters:", [i["iters"] for i in infos])
@@ -287,7 +289,7 @@ def main():
     for p, f, z, s in zip(probs64, F, Z64, w.systems):
         if s.n not in plain_sched:
             t = p.tune(f, z)
-            plain_sched[s.n] = (t["tile_points"], t["lds_bytes"])
+            plain_sched[s.n] = (t["tile_points"], t["lds_bytes"], t["block_threads"])
         else:
             p.set_schedule(*plain_sched[s.n])
     for p, f, z in zip(probs64, F, Z64):

@@ -149,10 +149,13 @@ csl_status problem_info(csl_problem p, double *abar, double *a_min,
 /* Schedule of the problem's own solves (minres_solve, minres_adjoint):
  * tile_points grid points per scheduling tile (0 = about one tile per
  * workgroup and phase, which lets a single solve fill the device; 1 = one
- * LDS chunk per tile) and the LDS line budget (0 or 32768 = default, 65536
- * = 64 KiB).  Batches keep their own schedule.  Synchronises s. */
+ * LDS chunk per tile), the LDS line budget (0 or 32768 = default, 65536
+ * = 64 KiB) and the workgroup size of the persistent solver, block_threads:
+ * 0 = 512 where allowed, else 256; 256; or 512, which is allowed for 2-D
+ * problems whose sine transforms all run on the FFT (CSL_ERR_ARG otherwise).
+ * Batches keep their own schedule.  Synchronises s. */
 csl_status problem_set_schedule(csl_problem p, int tile_points, int lds_bytes,
-                                hipStream_t s);
+                                int block_threads, hipStream_t s);
 
 /* Sine-transform engine in use along each axis (CSL_DST_FFT or
  * CSL_DST_GEMM; entries past the grid's dimension are CSL_DST_FFT). */
@@ -208,10 +211,14 @@ typedef struct csl_batch_opts {
                                problem (32 KiB unless lines of 2048 need
                                64), 65536 = 64 KiB for every problem (twice
                                the lines per strided tile); 32768 = 0      */
-    int reserved[1];
+    int block_threads;      /* workgroup size of the persistent solver: 0 =
+                               512 if every problem allows it (2-D, FFT on
+                               both axes), else 256; 256; 512 (CSL_ERR_ARG
+                               unless every problem allows it)             */
 } csl_batch_opts;
 
-/* Schedule chosen by batch_tune or problem_tune. */
+/* Schedule chosen by batch_tune or problem_tune, or in use
+ * (problem_schedule, batch_schedule: candidates = 0, ms = ms_default = 0). */
 typedef struct csl_batch_tuning {
     int tile_points;        /* chosen grid points per tile                      */
     int lds_bytes;          /* chosen LDS budget (32768 or 65536)               */
@@ -219,6 +226,8 @@ typedef struct csl_batch_tuning {
     int candidates;         /* schedules timed                                  */
     double ms;              /* time of one solve with the chosen schedule       */
     double ms_default;      /* time with the creation-time schedule             */
+    int block_threads;      /* workgroup size of the persistent solver          */
+    int reserved;
 } csl_batch_tuning;
 
 /* Group `count` problems (any grids, shifts and precisions) into one
@@ -238,18 +247,25 @@ csl_status batch_solve(csl_batch b, const double *const *f, double *const *z,
                        csl_solve_info *infos, hipStream_t s);
 
 /* Autotuner of a problem's own schedule: solves (K + lambda I) z = f with
- * each candidate tile size and LDS budget (tol 1e-8), timing each on
- * stream s, and keeps the fastest (problem_set_schedule).  Blocks until
- * done; out may be NULL (its grid_size is the single-solve grid). */
+ * each candidate tile size, LDS budget and allowed workgroup size (tol
+ * 1e-8), timing each on stream s, and keeps the fastest
+ * (problem_set_schedule).  Blocks until done; out may be NULL (its
+ * grid_size is the single-solve grid). */
 csl_status problem_tune(csl_problem p, const double *f, double *z,
                         csl_batch_tuning *out, hipStream_t s);
 
 /* Autotuner of the batch schedule: solves the batch for f (results in z)
- * with each candidate tile size and LDS budget, timing every candidate on
- * stream s, and keeps the fastest for later batch_solve calls (the graph is
- * recaptured).  Blocks until done; out may be NULL. */
+ * with each candidate tile size, LDS budget and allowed workgroup size,
+ * timing every candidate on stream s, and keeps the fastest for later
+ * batch_solve calls (the graph is recaptured).  Blocks until done; out may
+ * be NULL. */
 csl_status batch_tune(csl_batch b, const double *const *f, double *const *z,
                       csl_batch_tuning *out, hipStream_t s);
+
+/* Schedule in use for the problem's own solves / for the batch (host
+ * state only; no device work). */
+csl_status problem_schedule(csl_problem p, csl_batch_tuning *out);
+csl_status batch_schedule(csl_batch b, csl_batch_tuning *out);
 
 csl_status batch_destroy(csl_batch b);
 

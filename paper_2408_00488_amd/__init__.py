@@ -66,13 +66,20 @@ class _BatchOpts(ctypes.Structure):
                 ("check_true_residual", ctypes.c_int), ("timeout_ms", ctypes.c_int),
                 ("grid_size", ctypes.c_int), ("use_graph", ctypes.c_int),
                 ("tile_points", ctypes.c_int), ("lds_bytes", ctypes.c_int),
-                ("reserved", ctypes.c_int * 1)]
+                ("block_threads", ctypes.c_int)]
 
 
 class _BatchTuning(ctypes.Structure):
     _fields_ = [("tile_points", ctypes.c_int), ("lds_bytes", ctypes.c_int),
                 ("grid_size", ctypes.c_int), ("candidates", ctypes.c_int),
-                ("ms", ctypes.c_double), ("ms_default", ctypes.c_double)]
+                ("ms", ctypes.c_double), ("ms_default", ctypes.c_double),
+                ("block_threads", ctypes.c_int), ("reserved", ctypes.c_int)]
+
+
+def _tuning_dict(t: _BatchTuning) -> dict:
+    return {"tile_points": t.tile_points, "lds_bytes": t.lds_bytes,
+            "grid_size": t.grid_size, "block_threads": t.block_threads,
+            "candidates": t.candidates, "ms": t.ms, "ms_default": t.ms_default}
 
 
 _lib = None
@@ -98,7 +105,9 @@ def load_library():
     L.destroy_problem.argtypes = [vp]
     L.problem_info.argtypes = [vp, dp, dp, dp]
     L.problem_dst_engines.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
-    L.problem_set_schedule.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp]
+    L.problem_set_schedule.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]
+    L.problem_schedule.argtypes = [vp, ctypes.POINTER(_BatchTuning)]
+    L.batch_schedule.argtypes = [vp, ctypes.POINTER(_BatchTuning)]
     L.problem_tune.argtypes = [vp, vp, vp, ctypes.POINTER(_BatchTuning), vp]
     L.apply_A.argtypes = [vp, vp, vp, vp]
     L.apply_Pinv.argtypes = [vp, vp, vp, vp]
@@ -116,7 +125,7 @@ def load_library():
     L.csl_last_error.restype = ctypes.c_char_p
     L.csl_version.restype = ctypes.c_int
     for fn in ("create_problem", "destroy_problem", "problem_info", "problem_dst_engines",
-               "problem_set_schedule", "problem_tune",
+               "problem_set_schedule", "problem_tune", "problem_schedule", "batch_schedule",
                "apply_A", "apply_Pinv",
                "minres_solve", "minres_adjoint", "batch_create", "batch_solve",
                "batch_tune", "batch_destroy"):
@@ -204,10 +213,17 @@ class Problem:
             raise RuntimeError("problem destroyed")
         return self._h
 
-    def set_schedule(self, tile_points: int = 0, lds_bytes: int = 0):
+    def set_schedule(self, tile_points: int = 0, lds_bytes: int = 0, block_threads: int = 0):
         """Schedule of this problem's own solves (see problem_set_schedule)."""
         _check(load_library().problem_set_schedule(self.handle, int(tile_points), int(lds_bytes),
-                                                   _stream(self.device)))
+                                                   int(block_threads), _stream(self.device)))
+
+    @property
+    def schedule(self) -> dict:
+        """Schedule in use for this problem's own solves."""
+        t = _BatchTuning()
+        _check(load_library().problem_schedule(self.handle, ctypes.byref(t)))
+        return _tuning_dict(t)
 
     def tune(self, f, z=None) -> dict:
         """Time candidate schedules of minres_solve on f and keep the fastest."""
@@ -219,9 +235,7 @@ class Problem:
         t = _BatchTuning()
         _check(load_library().problem_tune(self.handle, _ptr(f), _ptr(z), ctypes.byref(t),
                                            _stream(self.device)))
-        return {"tile_points": t.tile_points, "lds_bytes": t.lds_bytes,
-                "grid_size": t.grid_size, "candidates": t.candidates, "ms": t.ms,
-                "ms_default": t.ms_default}
+        return _tuning_dict(t)
 
     def close(self):
         if getattr(self, "_h", None) is not None:
@@ -331,7 +345,7 @@ class Batch:
     """Several problems solved by one persistent launch (optionally a graph)."""
 
     def __init__(self, problems, tol=1e-8, maxit=1000, check_true=True, timeout_ms=0,
-                 grid_size=0, use_graph=True, tile_points=0, lds_bytes=0):
+                 grid_size=0, use_graph=True, tile_points=0, lds_bytes=0, block_threads=0):
         self.problems = list(problems)
         arr = (ctypes.c_void_p * len(self.problems))(*[p.handle for p in self.problems])
         o = _BatchOpts()
@@ -343,6 +357,7 @@ class Batch:
         o.use_graph = 1 if use_graph else 0
         o.tile_points = int(tile_points)
         o.lds_bytes = int(lds_bytes)
+        o.block_threads = int(block_threads)
         h = ctypes.c_void_p()
         _check(load_library().batch_create(arr, len(self.problems), ctypes.byref(o),
                                            ctypes.byref(h)))
@@ -397,9 +412,14 @@ class Batch:
         t = _BatchTuning()
         _check(load_library().batch_tune(self._h, fa, za, ctypes.byref(t),
                                          _stream(self.device)))
-        return {"tile_points": t.tile_points, "lds_bytes": t.lds_bytes,
-                "grid_size": t.grid_size, "candidates": t.candidates, "ms": t.ms,
-                "ms_default": t.ms_default}
+        return _tuning_dict(t)
+
+    @property
+    def schedule(self) -> dict:
+        """Schedule in use for this batch."""
+        t = _BatchTuning()
+        _check(load_library().batch_schedule(self._h, ctypes.byref(t)))
+        return _tuning_dict(t)
 
 
 def batch_create(problems, **kw) -> Batch:

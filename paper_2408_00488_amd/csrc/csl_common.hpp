@@ -6,7 +6,6 @@
 
 namespace csl {
 
-constexpr int NT = 256;        // threads per workgroup (4 wave64)
 constexpr int TWN = 2048;      // twiddle table length = longest FFT
 constexpr int MAX_LG = 11;     // log2(TWN)
 

@@ -2,10 +2,30 @@
 // transforms (DST-I through a radix-4/2 Stockham FFT of the odd extension),
 // the variable-coefficient stencil, and the phase tiles of the MINRES
 // iteration.  Everything here runs inside workgroups of NT threads.
+//
+// The device code is compiled once per workgroup size: CSL_NT threads, in
+// namespace csl::CSL_KNS (256 threads in csl::wg256 unless the including
+// file says otherwise), so that each instance has its own kernels, twiddle
+// tables and register allocation.
 #pragma once
 #include "csl_common.hpp"
 
+#ifndef CSL_NT
+#define CSL_NT 256
+#endif
+#ifndef CSL_KNS
+#define CSL_KNS wg256
+#endif
+
+// Elements per thread and round of the pipelined fills and stores, scaled
+// with the block size so that a workgroup keeps the same number of loads in
+// flight (and a thread the same registers per element) at either size.
+#define CSL_U(u) ((u) * 256 / CSL_NT > 0 ? (u) * 256 / CSL_NT : 1)
+
 namespace csl {
+namespace CSL_KNS {
+
+constexpr int NT = CSL_NT;   // threads per workgroup (NT / 64 wave64)
 
 template <typename R>
 struct alignas(2 * sizeof(R)) Cx {
@@ -946,4 +966,5 @@ __device__ __forceinline__ int ld_ctl(const int *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+}  // namespace CSL_KNS
 }  // namespace csl

@@ -2,12 +2,26 @@
 // (arXiv:2408.00488): the persistent multi-system scheduler, the phase tiles
 // of one MINRES iteration, stand-alone A and P^{-1} applications, the
 // adjoint reduction and the coefficient set-up reductions.
+//
+// This file is the 256-thread instance (namespace csl::wg256).  It is also
+// compiled, through csl_kernels_wg512.hip, as a 512-thread instance of the
+// persistent solver alone (CSL_SOLVE_ONLY) for 2-D systems whose transforms
+// all run on the LDS FFT (CSL_2D_FFT_ONLY): eight waves per workgroup at 128
+// registers keep twice the waves per CU in flight on those paths.
 #include <math.h>
 
 #include "csl_device.hpp"
 #include "csl_kernels.hpp"
 
+#ifndef CSL_SOLVE_ONLY
+#define CSL_SOLVE_ONLY 0
+#endif
+#ifndef CSL_2D_FFT_ONLY
+#define CSL_2D_FFT_ONLY 0
+#endif
+
 namespace csl {
+namespace CSL_KNS {
 
 template <typename R>
 __device__ __forceinline__ Cx<R> to_cx(double2 v) {
@@ -111,7 +125,7 @@ __device__ __forceinline__ void tile_Y(const SysDesc &S, int kind, int iter, int
       struct In3 {
         double2 q, v1, v0;
       };
-      E::template fill2<2>(
+      E::template fill2<CSL_U(2)>(
           buf, t,
           [&](int, int, int p) {
             In3 in;
@@ -222,7 +236,7 @@ __device__ __forceinline__ void tile_Z(const SysDesc &S, const IOPtr &io, int it
   CSL_G double2 *__restrict__ znew = gbl(S.Z[(j + 1) & 1]);
   for (int chunk = tile * S.cpt[K_Z]; chunk < c1; ++chunk) {
   const LineTile t = line_tile(S, D - 1, S.lpt_z, chunk);
-  E::template fill_blk<8>(buf, t, [&](int, int, int q) { return ldg(T + q); });
+  E::template fill_blk<CSL_U(8)>(buf, t, [&](int, int, int q) { return ldg(T + q); });
   const Cx<R> *o = E::transform(buf, t, twl, Wm);
   if (mode == ZM_DEFER) {
     E::store(o, t, [&](int, int, int p, Cx<R> v) {
@@ -241,7 +255,7 @@ __device__ __forceinline__ void tile_Z(const SysDesc &S, const IOPtr &io, int it
     struct In4 {
       double2 z, w0, w1, x;
     };
-    E::template store2<2>(
+    E::template store2<CSL_U(2)>(
         o, t,
         [&](int p) {
           In4 in;
@@ -331,9 +345,14 @@ __device__ __forceinline__ void tile_PR(const SysDesc &S, const IOPtr &io, int t
 template <int LDSB>
 __device__ __forceinline__ void process_tile(const SysDesc &S, const IOPtr &io, int kind, int iter, int tile,
                              char *smem, double *red) {
+#if CSL_2D_FFT_ONLY
+  const bool d3 = false;
+  const bool g = false;
+#else
   const bool d3 = (S.d == 3);
   const int ax = (kind == K_X || kind == K_Z) ? S.d - 1 : (kind == K_Y ? 0 : 1);
   const bool g = S.gemm[ax] != 0;
+#endif
   typedef FftEng<double, LDSB> F64;
   typedef FftEng<float, LDSB> F32;
   typedef GemmEng<double, LDSB> G64;
@@ -378,6 +397,7 @@ __device__ __forceinline__ void process_tile(const SysDesc &S, const IOPtr &io, 
   }
 }
 
+#if !CSL_SOLVE_ONLY
 // ---------------------------------------------------------------------------
 // Stand-alone P^{-1}: rows forward (x -> T), strided passes, rows inverse
 // (T -> y), all in the preconditioner precision R.
@@ -438,6 +458,8 @@ __device__ __forceinline__ void tile_pinv(const SysDesc &S, int pass, const doub
     E::store(o, t, [&](int, int, int p, Cx<R> v) { T[p] = v; });
   }
 }
+
+#endif  // !CSL_SOLVE_ONLY
 
 // ---------------------------------------------------------------------------
 // Phase epilogue, run by the workgroup that completed the last tile of a
@@ -637,7 +659,7 @@ __device__ __forceinline__ void epilogue(const SysDesc &S, const SolveParams &P,
 // workgroups exit when every system is done or the time limit passes.
 // ---------------------------------------------------------------------------
 template <int LDSB>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void solve_kernel(
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) void solve_kernel(
     const SysDesc *__restrict__ sys, const IOPtr *__restrict__ io, IOPtr io0, int nsys,
     SolveParams P, Glob *G) {
   extern __shared__ __align__(16) char smem[];
@@ -739,6 +761,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void so
   }
 }
 
+#if !CSL_SOLVE_ONLY
 __global__ void init_kernel(const SysDesc *__restrict__ sys, int nsys, Glob *G) {
   for (int s = threadIdx.x; s < nsys; s += blockDim.x) {
     Ctl *C = sys[s].ctl;
@@ -1010,6 +1033,8 @@ __global__ __launch_bounds__(NT) void coef_stats_final_kernel(const double *__re
   }
 }
 
+#endif  // !CSL_SOLVE_ONLY
+
 // ---------------------------------------------------------------------------
 // Host-side launch wrappers (declared in csl_kernels.hpp).
 // ---------------------------------------------------------------------------
@@ -1017,11 +1042,6 @@ hipError_t upload_twiddles(const double2 *tw64, const float2 *tw32) {
   hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(g_tw64), tw64, sizeof(double2) * TWN);
   if (e != hipSuccess) return e;
   return hipMemcpyToSymbol(HIP_SYMBOL(g_tw32), tw32, sizeof(float2) * TWN);
-}
-
-hipError_t launch_init(const SysDesc *dsys, int nsys, Glob *G, hipStream_t s) {
-  hipLaunchKernelGGL(init_kernel, dim3(1), dim3(64), 0, s, dsys, nsys, G);
-  return hipGetLastError();
 }
 
 hipError_t launch_solve(const SysDesc *dsys, const IOPtr *dio, IOPtr io0, int nsys,
@@ -1041,6 +1061,12 @@ hipError_t solve_occupancy(size_t smem, int *blocks_per_cu) {
                                                         32768 + tw_lds_bytes(32768));
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, solve_kernel<65536>, NT,
                                                       65536 + tw_lds_bytes(65536));
+}
+
+#if !CSL_SOLVE_ONLY
+hipError_t launch_init(const SysDesc *dsys, int nsys, Glob *G, hipStream_t s) {
+  hipLaunchKernelGGL(init_kernel, dim3(1), dim3(64), 0, s, dsys, nsys, G);
+  return hipGetLastError();
 }
 
 hipError_t launch_apply_A(const SysDesc *dsys, int d, int M, const double2 *x, double2 *y,
@@ -1112,4 +1138,7 @@ hipError_t launch_coef_stats(const SysDesc *dsys, int d, int M, double *part, in
   return hipGetLastError();
 }
 
+#endif  // !CSL_SOLVE_ONLY
+
+}  // namespace CSL_KNS
 }  // namespace csl

@@ -1,8 +1,16 @@
-// Host-callable launch wrappers of the gfx950 kernels.
+// Host-callable launch wrappers of the gfx950 kernels.  The device code is
+// built twice: csl::wg256 (256-thread workgroups; every kernel) and
+// csl::wg512 (512-thread workgroups; the persistent solver for 2-D systems
+// whose transforms all run on the LDS FFT).
 #pragma once
 #include "csl_common.hpp"
 
 namespace csl {
+
+// Threads per workgroup of the stand-alone and set-up kernels (wg256).
+constexpr int kAuxThreads = 256;
+
+namespace wg256 {
 
 hipError_t upload_twiddles(const double2 *tw64, const float2 *tw32);
 hipError_t launch_init(const SysDesc *dsys, int nsys, Glob *G, hipStream_t s);
@@ -20,5 +28,16 @@ hipError_t launch_adjoint(const SysDesc *dsys, int d, int M, const double2 *ytil
 hipError_t launch_conj(const double2 *x, double2 *y, int M, hipStream_t s);
 hipError_t launch_coef_stats(const SysDesc *dsys, int d, int M, double *part, int nblk,
                              double *out, hipStream_t s);
+
+}  // namespace wg256
+
+namespace wg512 {
+
+hipError_t upload_twiddles(const double2 *tw64, const float2 *tw32);
+hipError_t launch_solve(const SysDesc *dsys, const IOPtr *dio, IOPtr io0, int nsys,
+                        const SolveParams &P, Glob *G, int grid, size_t smem, hipStream_t s);
+hipError_t solve_occupancy(size_t smem, int *blocks_per_cu);
+
+}  // namespace wg512
 
 }  // namespace csl

@@ -51,7 +51,8 @@ csl_status ensure_twiddles(int dev) {
     t64[m] = make_double2(std::cos(th), -std::sin(th));
     t32[m] = make_float2((float)t64[m].x, (float)t64[m].y);
   }
-  HIPCHK(upload_twiddles(t64.data(), t32.data()));
+  HIPCHK(wg256::upload_twiddles(t64.data(), t32.data()));
+  HIPCHK(wg512::upload_twiddles(t64.data(), t32.data()));
   g_tw_ready[dev] = true;
   return CSL_OK;
 }
@@ -90,6 +91,25 @@ void sine_matrix(int n, int np, std::vector<double> &W) {
     }
 }
 
+// The persistent solver instance of a workgroup size: 512 threads (2-D
+// systems with the FFT on both axes only) or 256.
+hipError_t solve_launch(int wg, const SysDesc *dsys, const IOPtr *dio, IOPtr io0, int nsys,
+                        const SolveParams &P, Glob *G, int grid, size_t smem, hipStream_t s) {
+  return wg == 512 ? wg512::launch_solve(dsys, dio, io0, nsys, P, G, grid, smem, s)
+                   : wg256::launch_solve(dsys, dio, io0, nsys, P, G, grid, smem, s);
+}
+hipError_t solve_occupancy_wg(int wg, size_t smem, int *blocks_per_cu) {
+  return wg == 512 ? wg512::solve_occupancy(smem, blocks_per_cu)
+                   : wg256::solve_occupancy(smem, blocks_per_cu);
+}
+// Workgroup size for a request (0 = the larger one where allowed).
+int resolve_wg(int block_threads, bool wg512_ok) {
+  if (block_threads == 256) return 256;
+  if (block_threads == 512) return 512;
+  return wg512_ok ? 512 : 256;
+}
+bool valid_block_threads(int v) { return v == 0 || v == 256 || v == 512; }
+
 // Engine choices made by timing, per device and grid shape and precision.
 typedef std::tuple<int, int, int, int, int, int> ShapeKey;   // dev, d, n0, n1, n2, prec
 std::map<ShapeKey, int> g_engine_cache;                      // value: GEMM axis mask
@@ -121,6 +141,8 @@ struct csl_problem_s {
   int cap = 1;           // workgroups that fill the device at this problem's LDS budget
   int tile_points = 0;   // current schedule of the problem's own solves
   int lds_bytes = 0;
+  int block_threads = 256;
+  bool wg512_ok = false; // 2-D with the FFT on both axes: the 512-thread solver applies
 };
 
 struct csl_batch_s {
@@ -144,6 +166,8 @@ struct csl_batch_s {
   int grid_opt = 0;      // requested grid (0 = occupancy-filling)
   int tile_points = 0;   // current schedule
   int lds_bytes = 0;
+  int block_threads = 256;
+  bool wg512_ok = false; // every problem allows the 512-thread solver
 };
 
 namespace {
@@ -280,7 +304,7 @@ hipError_t launch_pinv_all(csl_problem p, const double2 *x, double2 *y, hipStrea
                    : pass[k] == 2             ? h.nchunk[K_Y]
                    : pass[k] == 1             ? h.nchunk[K_Y1]
                                               : h.nchunk[K_Y1I];
-    const hipError_t e = launch_pinv_pass(p->d_desc, h.d, h.prec, pass[k], nt, p->smem, x, y, s);
+    const hipError_t e = wg256::launch_pinv_pass(p->d_desc, h.d, h.prec, pass[k], nt, p->smem, x, y, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -329,12 +353,14 @@ csl_status tune_engines(csl_problem p, int elig, hipStream_t s, int *best_mask) 
 // budget of at least `lds_bytes` and chunks grouped into tiles of
 // `tile_points` points (0: about one tile per workgroup and phase, since a
 // single solve has the whole device).
-csl_status configure_single(csl_problem p, int tile_points, int lds_bytes, hipStream_t s) {
+csl_status configure_single(csl_problem p, int tile_points, int lds_bytes, int block_threads,
+                            hipStream_t s) {
   SysDesc h = p->h0;
   size_t sm = p->smem0;
   if (lds_bytes > 32768 && p->smem0 <= 32768) choose_tiles(h, p->tile_elems, lds_bytes, &sm);
+  const int wg = resolve_wg(block_threads, p->wg512_ok);
   int bpc = 0;
-  HIPCHK(solve_occupancy(sm, &bpc));
+  HIPCHK(solve_occupancy_wg(wg, sm, &bpc));
   const int cap = std::max(1, bpc) * p->cus;
   const int tp = tile_points > 0 ? tile_points : (int)std::min<long long>(1 << 30, h.M / cap);
   set_tile_points(h, tp);
@@ -348,6 +374,7 @@ csl_status configure_single(csl_problem p, int tile_points, int lds_bytes, hipSt
   p->grid1 = std::max(1, std::min(mt, cap));
   p->tile_points = tile_points;
   p->lds_bytes = sm <= 32768 ? 32768 : 65536;
+  p->block_threads = wg;
   return CSL_OK;
 }
 
@@ -355,7 +382,8 @@ csl_status configure_single(csl_problem p, int tile_points, int lds_bytes, hipSt
 // per tile and an LDS budget of at least `lds_bytes`, the grid, and (if
 // asked) the captured graph of one solve.  Called at creation and by the
 // tuner.
-csl_status configure_batch(csl_batch b, int tile_points, int lds_bytes, bool graph) {
+csl_status configure_batch(csl_batch b, int tile_points, int lds_bytes, int block_threads,
+                           bool graph) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   b->exec = nullptr;
@@ -379,8 +407,9 @@ csl_status configure_batch(csl_batch b, int tile_points, int lds_bytes, bool gra
   b->smem = smem;
   b->tile_points = tile_points;
   b->lds_bytes = smem <= 32768 ? 32768 : 65536;
+  b->block_threads = resolve_wg(block_threads, b->wg512_ok);
   int bpc = 0;
-  HIPCHK(solve_occupancy(smem, &bpc));
+  HIPCHK(solve_occupancy_wg(b->block_threads, smem, &bpc));
   // tiles are claimed dynamically, so a full-occupancy grid keeps every CU
   // busy whatever the mix of systems
   const int cap = std::max(1, bpc) * b->probs[0]->cus;
@@ -390,10 +419,10 @@ csl_status configure_batch(csl_batch b, int tile_points, int lds_bytes, bool gra
   HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
   if (ok) {
-    ok = launch_init(b->d_desc, b->count, b->glob, cs) == hipSuccess;
+    ok = wg256::launch_init(b->d_desc, b->count, b->glob, cs) == hipSuccess;
     IOPtr none{nullptr, nullptr};
-    ok = ok && launch_solve(b->d_desc, b->d_io, none, b->count, b->params, b->glob, b->grid,
-                            b->smem, cs) == hipSuccess;
+    ok = ok && solve_launch(b->block_threads, b->d_desc, b->d_io, none, b->count, b->params,
+                            b->glob, b->grid, b->smem, cs) == hipSuccess;
     hipGraph_t g = nullptr;
     const bool ended = hipStreamEndCapture(cs, &g) == hipSuccess;
     ok = ok && ended && g;
@@ -493,8 +522,8 @@ csl_status create_problem(const csl_grid *grid, const double *a_nodal, double al
   }
   choose_tiles(h, o.tile_elems, 0, &p->smem);
   p->tile_elems = o.tile_elems;
-  p->stats_nblk = std::min(1024, (h.M + NT - 1) / NT);
-  p->adj_nblk = std::min(1024, (h.M + NT - 1) / NT);
+  p->stats_nblk = std::min(1024, (h.M + kAuxThreads - 1) / kAuxThreads);
+  p->adj_nblk = std::min(1024, (h.M + kAuxThreads - 1) / kAuxThreads);
 
   // one allocation for the coefficient copy, tables and workspaces
   const size_t vec = align256(sizeof(double2) * (size_t)h.M);
@@ -621,9 +650,9 @@ csl_status create_problem(const csl_grid *grid, const double *a_nodal, double al
                         hipMemcpyHostToDevice, s));
   }
   PCHK(hipMemcpyAsync(p->d_desc, &h, sizeof(SysDesc), hipMemcpyHostToDevice, s));
-  PCHK(launch_coef_stats(p->d_desc, h.d, h.M, p->stats_part, p->stats_nblk, p->stats, s));
+  PCHK(wg256::launch_coef_stats(p->d_desc, h.d, h.M, p->stats_part, p->stats_nblk, p->stats, s));
   for (int ax = 0; ax < h.d; ++ax)
-    PCHK(launch_faces(p->d_desc, h.d, ax, nfaces[ax], (double *)h.F[ax], s));
+    PCHK(wg256::launch_faces(p->d_desc, h.d, ax, nfaces[ax], (double *)h.F[ax], s));
   PCHK(hipMemcpyAsync(st4, p->stats, sizeof(st4), hipMemcpyDeviceToHost, s));
   PCHK(hipStreamSynchronize(s));
   if (st4[3] != 0.0) {
@@ -695,8 +724,9 @@ csl_status create_problem(const csl_grid *grid, const double *a_nodal, double al
   PCHK(hipStreamSynchronize(s));
   p->h0 = p->h;
   p->smem0 = p->smem;
+  p->wg512_ok = h.d == 2 && !p->h.gemm[0] && !p->h.gemm[1];
   {
-    const csl_status st = configure_single(p, 0, 0, s);
+    const csl_status st = configure_single(p, 0, 0, 0, s);
     if (st != CSL_OK) {
       free_problem(p);
       return st;
@@ -730,7 +760,7 @@ csl_status problem_dst_engines(csl_problem p, int engines[3]) {
 csl_status apply_A(csl_problem p, const double *x, double *y, hipStream_t s) {
   if (!p || !x || !y) return fail(CSL_ERR_ARG, "NULL argument");
   if (x == y) return fail(CSL_ERR_ARG, "apply_A: x and y must not alias");
-  HIPCHK(launch_apply_A(p->d_desc, p->h.d, p->h.M, (const double2 *)x, (double2 *)y, s));
+  HIPCHK(wg256::launch_apply_A(p->d_desc, p->h.d, p->h.M, (const double2 *)x, (double2 *)y, s));
   return CSL_OK;
 }
 
@@ -742,9 +772,10 @@ csl_status apply_Pinv(csl_problem p, const double *x, double *y, hipStream_t s) 
 
 static csl_status run_single(csl_problem p, const double2 *f, double2 *x, const SolveParams &P,
                              hipStream_t s) {
-  HIPCHK(launch_init(p->d_desc, 1, p->glob, s));
+  HIPCHK(wg256::launch_init(p->d_desc, 1, p->glob, s));
   IOPtr io0{f, x};
-  HIPCHK(launch_solve(p->d_desc, nullptr, io0, 1, P, p->glob, p->grid1, p->smem, s));
+  HIPCHK(solve_launch(p->block_threads, p->d_desc, nullptr, io0, 1, P, p->glob, p->grid1, p->smem,
+                      s));
   return CSL_OK;
 }
 
@@ -778,25 +809,49 @@ csl_status minres_solve(csl_problem p, const double *f, double *z, const csl_sol
   return fetch_single_info(p, info, s);
 }
 
-csl_status problem_set_schedule(csl_problem p, int tile_points, int lds_bytes, hipStream_t s) {
+csl_status problem_set_schedule(csl_problem p, int tile_points, int lds_bytes, int block_threads,
+                                hipStream_t s) {
   if (!p) return fail(CSL_ERR_ARG, "problem is NULL");
   if (tile_points < 0) return fail(CSL_ERR_ARG, "tile_points must be >= 0");
   if (lds_bytes != 0 && lds_bytes != 32768 && lds_bytes != 65536)
     return fail(CSL_ERR_ARG, "lds_bytes must be 0, 32768 or 65536");
-  return configure_single(p, tile_points, lds_bytes, s);
+  if (!valid_block_threads(block_threads))
+    return fail(CSL_ERR_ARG, "block_threads must be 0, 256 or 512");
+  if (block_threads == 512 && !p->wg512_ok)
+    return fail(CSL_ERR_ARG, "block_threads 512 needs a 2-D problem with the FFT on both axes");
+  return configure_single(p, tile_points, lds_bytes, block_threads, s);
+}
+
+csl_status problem_schedule(csl_problem p, csl_batch_tuning *out) {
+  if (!p || !out) return fail(CSL_ERR_ARG, "NULL argument");
+  *out = csl_batch_tuning{};
+  out->tile_points = p->tile_points;
+  out->lds_bytes = p->lds_bytes;
+  out->grid_size = p->grid1;
+  out->block_threads = p->block_threads;
+  return CSL_OK;
 }
 
 csl_status problem_tune(csl_problem p, const double *f, double *z, csl_batch_tuning *out,
                         hipStream_t s) {
   if (!p || !f || !z) return fail(CSL_ERR_ARG, "NULL argument");
   if (f == z) return fail(CSL_ERR_ARG, "problem_tune: f and z must not alias");
-  const int tp0 = p->tile_points, lds0 = p->lds_bytes;
+  const int tp0 = p->tile_points, lds0 = p->lds_bytes, wg0 = p->block_threads;
   const long long per_wg = std::max<long long>(1, p->h.M / std::max(1, p->cap));
-  std::vector<std::pair<int, int>> cands;
-  cands.push_back({tp0, lds0});
-  for (int lds : {32768, 65536})
-    for (long long tp : {0LL, 1LL, per_wg / 2, per_wg * 2, 8192LL})
-      if (tp >= 0 && !((int)tp == tp0 && lds == lds0)) cands.push_back({(int)tp, lds});
+  // candidates: the current schedule first, then tile sizes around one tile
+  // per workgroup with both LDS budgets and every allowed workgroup size
+  struct Cand {
+    int tp, lds, wg;
+  };
+  std::vector<Cand> cands;
+  cands.push_back({tp0, lds0, wg0});
+  for (int wg : {256, 512}) {
+    if (wg == 512 && !p->wg512_ok) continue;
+    for (int lds : {32768, 65536})
+      for (long long tp : {0LL, 1LL, per_wg / 2, per_wg * 2, 8192LL})
+        if (tp >= 0 && !((int)tp == tp0 && lds == lds0 && wg == wg0))
+          cands.push_back({(int)tp, lds, wg});
+  }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -805,12 +860,12 @@ csl_status problem_tune(csl_problem p, const double *f, double *z, csl_batch_tun
   }
   const SolveParams P = make_params(0.0, 0, 1, 0, p->wall_khz);
   double best = INFINITY, first = INFINITY;
-  int best_tp = tp0, best_lds = lds0, timed = 0;
+  int best_tp = tp0, best_lds = lds0, best_wg = wg0, timed = 0;
   csl_status st = CSL_OK;
   for (size_t c = 0; c < cands.size() && st == CSL_OK; ++c) {
-    st = configure_single(p, cands[c].first, cands[c].second, s);
+    st = configure_single(p, cands[c].tp, cands[c].lds, cands[c].wg, s);
     if (st != CSL_OK) break;
-    if (c > 0 && p->lds_bytes != cands[c].second) continue;   // budget not applicable
+    if (c > 0 && p->lds_bytes != cands[c].lds) continue;   // budget not applicable
     st = run_single(p, (const double2 *)f, (double2 *)z, P, s);   // warm-up
     float ms = 0.f, tot = 0.f;
     const int reps = 2;
@@ -829,22 +884,25 @@ csl_status problem_tune(csl_problem p, const double *f, double *z, csl_batch_tun
     if (c == 0) first = avg;
     if (avg < best) {
       best = avg;
-      best_tp = cands[c].first;
+      best_tp = cands[c].tp;
       best_lds = p->lds_bytes;
+      best_wg = p->block_threads;
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  const csl_status st2 = configure_single(p, best_tp, best_lds, s);
+  const csl_status st2 = configure_single(p, best_tp, best_lds, best_wg, s);
   if (st != CSL_OK) return st;
   if (st2 != CSL_OK) return st2;
   if (out) {
+    *out = csl_batch_tuning{};
     out->tile_points = best_tp;
     out->lds_bytes = p->lds_bytes;
     out->grid_size = p->grid1;
     out->candidates = timed;
     out->ms = best;
     out->ms_default = first;
+    out->block_threads = p->block_threads;
   }
   return CSL_OK;
 }
@@ -859,10 +917,10 @@ csl_status minres_adjoint(csl_problem p, const double *z, const double *gz, doub
   const int M = p->h.M;
   // y = (K + conj(lambda) I)^{-1} G  <=>  A (block) u = conj(G) with u = y;
   // the solve stores conj(u) = conj(y) in ytmp.
-  HIPCHK(launch_conj((const double2 *)gz, p->gtmp, M, s));
+  HIPCHK(wg256::launch_conj((const double2 *)gz, p->gtmp, M, s));
   csl_status st = run_single(p, p->gtmp, p->ytmp, P, s);
   if (st != CSL_OK) return st;
-  HIPCHK(launch_adjoint(p->d_desc, p->h.d, M, p->ytmp, (const double2 *)z, (double2 *)gf, ga,
+  HIPCHK(wg256::launch_adjoint(p->d_desc, p->h.d, M, p->ytmp, (const double2 *)z, (double2 *)gf, ga,
                         p->adj_part, p->adj_nblk, galpha, gbeta, s));
   if (!info) return CSL_OK;
   return fetch_single_info(p, info, s);
@@ -927,8 +985,14 @@ csl_status batch_create(const csl_problem *problems, int count, const csl_batch_
   if (o.lds_bytes != 0 && o.lds_bytes != 32768 && o.lds_bytes != 65536)
     return cleanup(CSL_ERR_ARG, "lds_bytes must be 0, 32768 or 65536");
   if (o.tile_points < 0) return cleanup(CSL_ERR_ARG, "tile_points must be >= 0");
+  if (!valid_block_threads(o.block_threads))
+    return cleanup(CSL_ERR_ARG, "block_threads must be 0, 256 or 512");
+  b->wg512_ok = true;
+  for (int i = 0; i < count; ++i) b->wg512_ok = b->wg512_ok && problems[i]->wg512_ok;
+  if (o.block_threads == 512 && !b->wg512_ok)
+    return cleanup(CSL_ERR_ARG, "block_threads 512 needs 2-D problems with the FFT on both axes");
   const csl_status st = configure_batch(b, o.tile_points > 0 ? o.tile_points : 8192,
-                                        o.lds_bytes, b->use_graph);
+                                        o.lds_bytes, o.block_threads, b->use_graph);
   if (st != CSL_OK) {
     const std::string msg = g_err;
     return cleanup(st, msg);
@@ -961,10 +1025,10 @@ csl_status batch_solve(csl_batch b, const double *const *f, double *const *z,
   if (b->use_graph) {
     HIPCHK(hipGraphLaunch(b->exec, s));
   } else {
-    HIPCHK(launch_init(b->d_desc, b->count, b->glob, s));
+    HIPCHK(wg256::launch_init(b->d_desc, b->count, b->glob, s));
     IOPtr none{nullptr, nullptr};
-    HIPCHK(launch_solve(b->d_desc, b->d_io, none, b->count, b->params, b->glob, b->grid, b->smem,
-                        s));
+    HIPCHK(solve_launch(b->block_threads, b->d_desc, b->d_io, none, b->count, b->params, b->glob,
+                        b->grid, b->smem, s));
   }
   if (!infos) return CSL_OK;
   std::vector<DevInfo> di(b->count);
@@ -984,14 +1048,20 @@ csl_status batch_solve(csl_batch b, const double *const *f, double *const *z,
 csl_status batch_tune(csl_batch b, const double *const *f, double *const *z,
                       csl_batch_tuning *out, hipStream_t s) {
   if (!b || !f || !z) return fail(CSL_ERR_ARG, "NULL argument");
-  const int tp0 = b->tile_points, lds0 = b->lds_bytes;
+  const int tp0 = b->tile_points, lds0 = b->lds_bytes, wg0 = b->block_threads;
   // candidates: the creation-time schedule first, then tile sizes around it
-  // with both LDS budgets
-  std::vector<std::pair<int, int>> cands;
-  cands.push_back({tp0, lds0});
-  for (int lds : {32768, 65536})
-    for (int tp : {6144, 8192, 12288, 16384, 24576})
-      if (!(tp == tp0 && lds == lds0)) cands.push_back({tp, lds});
+  // with both LDS budgets and every allowed workgroup size
+  struct Cand {
+    int tp, lds, wg;
+  };
+  std::vector<Cand> cands;
+  cands.push_back({tp0, lds0, wg0});
+  for (int wg : {256, 512}) {
+    if (wg == 512 && !b->wg512_ok) continue;
+    for (int lds : {32768, 65536})
+      for (int tp : {6144, 8192, 12288, 16384, 24576})
+        if (!(tp == tp0 && lds == lds0 && wg == wg0)) cands.push_back({tp, lds, wg});
+  }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -1001,12 +1071,12 @@ csl_status batch_tune(csl_batch b, const double *const *f, double *const *z,
   const bool graph = b->use_graph;
   b->use_graph = false;   // plain launches while timing
   double best = INFINITY, first = INFINITY;
-  int best_tp = tp0, best_lds = lds0, timed = 0;
+  int best_tp = tp0, best_lds = lds0, best_wg = wg0, timed = 0;
   csl_status st = CSL_OK;
   for (size_t c = 0; c < cands.size() && st == CSL_OK; ++c) {
-    st = configure_batch(b, cands[c].first, cands[c].second, false);
+    st = configure_batch(b, cands[c].tp, cands[c].lds, cands[c].wg, false);
     if (st != CSL_OK) break;
-    if (b->lds_bytes != cands[c].second && c > 0) continue;   // budget not applicable
+    if (b->lds_bytes != cands[c].lds && c > 0) continue;   // budget not applicable
     st = batch_solve(b, f, z, nullptr, s);   // warm-up (and io upload)
     if (st != CSL_OK) break;
     float ms = 0.f, tot = 0.f;
@@ -1026,24 +1096,37 @@ csl_status batch_tune(csl_batch b, const double *const *f, double *const *z,
     if (c == 0) first = avg;
     if (avg < best) {
       best = avg;
-      best_tp = cands[c].first;
+      best_tp = cands[c].tp;
       best_lds = b->lds_bytes;
+      best_wg = b->block_threads;
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   b->use_graph = graph;
-  const csl_status st2 = configure_batch(b, best_tp, best_lds, graph);
+  const csl_status st2 = configure_batch(b, best_tp, best_lds, best_wg, graph);
   if (st != CSL_OK) return st;
   if (st2 != CSL_OK) return st2;
   if (out) {
+    *out = csl_batch_tuning{};
     out->tile_points = best_tp;
     out->lds_bytes = b->lds_bytes;
     out->grid_size = b->grid;
     out->candidates = timed;
     out->ms = best;
     out->ms_default = first;
+    out->block_threads = b->block_threads;
   }
+  return CSL_OK;
+}
+
+csl_status batch_schedule(csl_batch b, csl_batch_tuning *out) {
+  if (!b || !out) return fail(CSL_ERR_ARG, "NULL argument");
+  *out = csl_batch_tuning{};
+  out->tile_points = b->tile_points;
+  out->lds_bytes = b->lds_bytes;
+  out->grid_size = b->grid;
+  out->block_threads = b->block_threads;
   return CSL_OK;
 }
 

@@ -392,6 +392,8 @@ def test_problem_schedule_and_tuner(csl):
     assert info["status"] == 0 and rel(z.cpu().numpy(), r0) <= 1e-9
     with pytest.raises(csl.CSLError):
         p.set_schedule(0, 1000)
+    with pytest.raises(csl.CSLError):
+        p.set_schedule(0, 0, 384)
 
 
 @pytest.mark.parametrize("fp32", [False, True])
