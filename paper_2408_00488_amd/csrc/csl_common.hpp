@@ -88,7 +88,6 @@ struct SysDesc {
                   // (row, c) at ((c / B) rows + row) B + c % B, so a strided
                   // tile's lines are one contiguous block
   int rpt;        // rows per tile of the residual pass
-  int fst[3][3];  // strides of the face-coefficient array of each axis
   int nchunk[K_NKINDS];  // LDS-sized chunks of each phase kind
   int cpt[K_NKINDS];     // chunks per tile (one scheduling unit)
   int ntile[K_NKINDS];   // ceil(nchunk / cpt)
@@ -96,8 +95,7 @@ struct SysDesc {
   double h2[3];   // 1 / h_k^2
   double alpha, beta, abar;
   float alpha_f, beta_f, abar_f;
-  const double *a;         // nodal coefficient
-  const double *F[3];      // face coefficients / h_k^2 of each axis
+  const double *a;         // nodal coefficient (face coefficients are formed from it)
   int gemm[3];             // 1: sine transforms along this axis by MFMA matrix product
   const double *Wm[3];     // padded orthonormal DST-I matrix per axis (FP64), if gemm
   const float *Wmf[3];     // FP32 copy

@@ -583,15 +583,19 @@ __device__ __forceinline__ void lines_store2(const Cx<R> *buf, const LineTile &t
 
 // ---------------------------------------------------------------------------
 // Stencil: (K u)_p = sum over the 2d faces e of p of c_e (u_p - u_nbr(e)) / h^2
-// with u = 0 outside the grid.  F[ax] holds c_e / h_ax^2 for every face of
-// axis ax (harmonic means of neighbouring nodal samples inside, the adjacent
-// sample on the boundary), in an array with n_ax + 1 entries along ax.
+// with u = 0 outside the grid.  The face coefficient is formed from the
+// nodal samples a on the fly: the harmonic mean 2 a_p a_q / (a_p + a_q) of
+// the two nodes of an interior face, the adjacent sample a_p on a boundary
+// face.  The loads (u and a at p and its neighbours) are separated from the
+// arithmetic so that pipelined fills can issue them early.
 // ---------------------------------------------------------------------------
 template <int D>
 struct StencilIn {
   double2 c;          // u_p
   double2 b[D], a[D]; // neighbours below / above along each axis (0 outside)
-  double fb[D], fa[D];
+  double ap;          // a_p
+  double ab[D], aa[D];// a at those neighbours (a_p outside)
+  unsigned inb, ina;  // bit ax: the neighbour below / above is inside
 };
 
 template <int D>
@@ -599,29 +603,42 @@ __device__ __forceinline__ StencilIn<D> stencil_load(const SysDesc &S,
                                                      const CSL_G double2 *__restrict__ u, int p,
                                                      const int (&idx)[3]) {
   StencilIn<D> in;
+  const CSL_G double *__restrict__ A = gbl(S.a);
   in.c = ldg(u + p);
+  in.ap = A[p];
+  in.inb = 0u;
+  in.ina = 0u;
 #pragma unroll
   for (int ax = 0; ax < D; ++ax) {
     const int st = S.st[ax];
-    int fi = 0;
-#pragma unroll
-    for (int k = 0; k < D; ++k) fi += idx[k] * S.fst[ax][k];
-    const CSL_G double *__restrict__ F = gbl(S.F[ax]);
-    in.fb[ax] = F[fi];
-    in.fa[ax] = F[fi + S.fst[ax][ax]];
-    in.b[ax] = idx[ax] > 0 ? ldg(u + (p - st)) : make_double2(0.0, 0.0);
-    in.a[ax] = idx[ax] < S.n[ax] - 1 ? ldg(u + (p + st)) : make_double2(0.0, 0.0);
+    const bool lo = idx[ax] > 0, hi = idx[ax] < S.n[ax] - 1;
+    in.inb |= (lo ? 1u : 0u) << ax;
+    in.ina |= (hi ? 1u : 0u) << ax;
+    in.b[ax] = lo ? ldg(u + (p - st)) : make_double2(0.0, 0.0);
+    in.a[ax] = hi ? ldg(u + (p + st)) : make_double2(0.0, 0.0);
+    in.ab[ax] = lo ? A[p - st] : 0.0;
+    in.aa[ax] = hi ? A[p + st] : 0.0;
   }
   return in;
 }
 
+// c_e / h^2 of the face between nodes with samples lo (lower index) and hi,
+// or of a boundary face next to a node with sample ap
+__device__ __forceinline__ double face_coef(bool inside, double lo, double hi, double ap, double h2) {
+  const double c = inside ? 2.0 * lo * hi / (lo + hi) : ap;
+  return c * h2;
+}
+
 template <int D>
-__device__ __forceinline__ double2 stencil_apply(const StencilIn<D> &in) {
+__device__ __forceinline__ double2 stencil_apply(const SysDesc &S, const StencilIn<D> &in) {
   double rx = 0.0, ry = 0.0;
 #pragma unroll
   for (int ax = 0; ax < D; ++ax) {
-    rx += in.fb[ax] * (in.c.x - in.b[ax].x) + in.fa[ax] * (in.c.x - in.a[ax].x);
-    ry += in.fb[ax] * (in.c.y - in.b[ax].y) + in.fa[ax] * (in.c.y - in.a[ax].y);
+    const double h2 = S.h2[ax];
+    const double fb = face_coef((in.inb >> ax) & 1u, in.ab[ax], in.ap, in.ap, h2);
+    const double fa = face_coef((in.ina >> ax) & 1u, in.ap, in.aa[ax], in.ap, h2);
+    rx += fb * (in.c.x - in.b[ax].x) + fa * (in.c.x - in.a[ax].x);
+    ry += fb * (in.c.y - in.b[ax].y) + fa * (in.c.y - in.a[ax].y);
   }
   return make_double2(rx, ry);
 }
@@ -629,7 +646,7 @@ __device__ __forceinline__ double2 stencil_apply(const StencilIn<D> &in) {
 template <int D>
 __device__ __forceinline__ double2 stencil_K(const SysDesc &S, const CSL_G double2 *__restrict__ u,
                                              int p, const int (&idx)[3]) {
-  return stencil_apply<D>(stencil_load<D>(S, u, p, idx));
+  return stencil_apply<D>(S, stencil_load<D>(S, u, p, idx));
 }
 
 

@@ -69,7 +69,7 @@ __device__ __forceinline__ void tile_X(const SysDesc &S, const IOPtr &io, int it
             return stencil_load<D>(S, zj, p, idx);
           },
           [&](int, int, int, const StencilIn<D> &in) {
-            const double2 kz = stencil_apply<D>(in);
+            const double2 kz = stencil_apply<D>(S, in);
             const double2 zz = in.c;
             const double qx = kz.x + al * zz.x + be * zz.y;
             const double qy = -(kz.y + al * zz.y - be * zz.x);
@@ -786,22 +786,36 @@ __global__ void init_kernel(const SysDesc *__restrict__ sys, int nsys, Glob *G) 
 // ---------------------------------------------------------------------------
 // Stand-alone operators.
 // ---------------------------------------------------------------------------
+// y = A x over the whole grid.  The points are split into 8 contiguous
+// slabs, one per XCD (workgroup b runs on XCD b mod 8), and the workgroups
+// of one XCD sweep their slab in steps of NT points, so the neighbouring
+// rows and planes a point needs were read moments before into the same L2:
+// x and a come from HBM about once, y goes back once (the model's 40 bytes
+// per point).
 template <int D>
 __global__ __launch_bounds__(NT) void apply_A_kernel(const SysDesc *__restrict__ sys,
                                                      const double2 *__restrict__ x,
                                                      double2 *__restrict__ y) {
   const SysDesc &S = *sys;
   const int nlast = S.n[D - 1];
-  for (int p = blockIdx.x * NT + threadIdx.x; p < S.M; p += gridDim.x * NT) {
+  const int nxcd = 8;
+  const int slab = blockIdx.x % nxcd, w = blockIdx.x / nxcd, nw = gridDim.x / nxcd;
+  const int p0 = (int)((long long)S.M * slab / nxcd);
+  const int p1 = (int)((long long)S.M * (slab + 1) / nxcd);
+  const CSL_G double2 *__restrict__ xg = gbl(x);
+  CSL_G double2 *__restrict__ yg = gbl(y);
+  const double al = S.alpha, be = S.beta;
+  for (int p = p0 + w * NT + (int)threadIdx.x; p < p1; p += nw * NT) {
     const int row = p / nlast;
     int idx[3];
     row_index<D>(S, row, p - row * nlast, idx);
-    const double2 kx = stencil_K<D>(S, gbl(x), p, idx);
-    const double2 xv = x[p];
+    const StencilIn<D> in = stencil_load<D>(S, xg, p, idx);
+    const double2 kx = stencil_apply<D>(S, in);
+    const double2 xv = in.c;
     // y = (K + lambda I) conj(x) = conj(K x + conj(lambda) x)
-    const double ux = kx.x + S.alpha * xv.x + S.beta * xv.y;
-    const double uy = kx.y + S.alpha * xv.y - S.beta * xv.x;
-    y[p] = make_double2(ux, -uy);
+    const double ux = kx.x + al * xv.x + be * xv.y;
+    const double uy = kx.y + al * xv.y - be * xv.x;
+    st_nt(yg + p, ux, -uy);
   }
 }
 
@@ -813,40 +827,6 @@ __global__ __launch_bounds__(NT) void pinv_pass_kernel(const SysDesc *__restrict
   const int ax = (pass == 0 || pass == 4) ? D - 1 : (pass == 2 ? 0 : 1);
   if (S.gemm[ax]) tile_pinv<R, D, LDSB, GemmEng<R, LDSB>>(S, pass, x, y, blockIdx.x, smem);
   else tile_pinv<R, D, LDSB, FftEng<R, LDSB>>(S, pass, x, y, blockIdx.x, smem);
-}
-
-// Face coefficients of axis ax divided by h_ax^2: harmonic mean of the two
-// neighbouring nodal samples inside, the adjacent sample on the boundary.
-template <int D>
-__global__ __launch_bounds__(NT) void faces_kernel(const SysDesc *__restrict__ sys, int ax,
-                                                   double *__restrict__ F) {
-  const SysDesc &S = *sys;
-  const double *__restrict__ a = S.a;
-  int fn[3];
-  for (int k = 0; k < 3; ++k) fn[k] = (k < D) ? S.n[k] + (k == ax ? 1 : 0) : 1;
-  const int total = fn[0] * fn[1] * (D == 3 ? fn[2] : 1);
-  for (int e = blockIdx.x * NT + threadIdx.x; e < total; e += gridDim.x * NT) {
-    int idx[3];
-    int rem = e;
-    for (int k = D - 1; k >= 0; --k) {
-      idx[k] = rem % fn[k];
-      rem /= fn[k];
-    }
-    // nodes below (i_ax - 1) and above (i_ax) the face
-    int pa = 0;
-    for (int k = 0; k < D; ++k) pa += (k == ax ? min(idx[k], S.n[ax] - 1) : idx[k]) * S.st[k];
-    double c;
-    if (idx[ax] == 0) {
-      c = a[pa];
-    } else if (idx[ax] == S.n[ax]) {
-      c = a[pa];
-    } else {
-      const double lo = a[pa - S.st[ax]];
-      const double hi = a[pa];
-      c = 2.0 * lo * hi / (lo + hi);
-    }
-    F[e] = c * S.h2[ax];
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1071,7 +1051,9 @@ hipError_t launch_init(const SysDesc *dsys, int nsys, Glob *G, hipStream_t s) {
 
 hipError_t launch_apply_A(const SysDesc *dsys, int d, int M, const double2 *x, double2 *y,
                           hipStream_t s) {
-  const int grid = (M + NT - 1) / NT < 4096 ? (M + NT - 1) / NT : 4096;
+  // 8 slabs (one per XCD), up to 256 workgroups sweeping each
+  const int per = (M / 8 + NT - 1) / NT;
+  const int grid = 8 * (per < 1 ? 1 : (per > 256 ? 256 : per));
   if (d == 3) hipLaunchKernelGGL(apply_A_kernel<3>, dim3(grid), dim3(NT), 0, s, dsys, x, y);
   else hipLaunchKernelGGL(apply_A_kernel<2>, dim3(grid), dim3(NT), 0, s, dsys, x, y);
   return hipGetLastError();
@@ -1097,13 +1079,6 @@ hipError_t launch_pinv_pass(const SysDesc *dsys, int d, int prec, int pass, int 
                             const double2 *x, double2 *y, hipStream_t s) {
   if (smem <= 32768) pinv_launch<32768>(dsys, d, prec, pass, ntile, 32768 + tw_lds_bytes(32768), x, y, s);
   else pinv_launch<65536>(dsys, d, prec, pass, ntile, 65536 + tw_lds_bytes(65536), x, y, s);
-  return hipGetLastError();
-}
-
-hipError_t launch_faces(const SysDesc *dsys, int d, int ax, int nfaces, double *F, hipStream_t s) {
-  const int grid = (nfaces + NT - 1) / NT < 4096 ? (nfaces + NT - 1) / NT : 4096;
-  if (d == 3) hipLaunchKernelGGL(faces_kernel<3>, dim3(grid), dim3(NT), 0, s, dsys, ax, F);
-  else hipLaunchKernelGGL(faces_kernel<2>, dim3(grid), dim3(NT), 0, s, dsys, ax, F);
   return hipGetLastError();
 }
 

@@ -21,7 +21,6 @@ hipError_t launch_apply_A(const SysDesc *dsys, int d, int M, const double2 *x, d
                           hipStream_t s);
 hipError_t launch_pinv_pass(const SysDesc *dsys, int d, int prec, int pass, int ntile, size_t smem,
                             const double2 *x, double2 *y, hipStream_t s);
-hipError_t launch_faces(const SysDesc *dsys, int d, int ax, int nfaces, double *F, hipStream_t s);
 hipError_t launch_adjoint(const SysDesc *dsys, int d, int M, const double2 *ytil,
                           const double2 *z, double2 *gf, double *ga, double *part, int nblk,
                           double *galpha, double *gbeta, hipStream_t s);

@@ -555,14 +555,6 @@ csl_status create_problem(const csl_grid *grid, const double *a_nodal, double al
   const size_t vecb = align256(sizeof(double2) * Mb);
   const size_t tsz = align256(Mb * (h.prec ? 8 : 16));
   const int nmu = h.n[0] + h.n[1] + h.n[2];
-  int nfaces[3] = {0, 0, 0};
-  for (int ax = 0; ax < h.d; ++ax) {
-    int fn[3];
-    for (int k = 0; k < 3; ++k) fn[k] = k < h.d ? h.n[k] + (k == ax ? 1 : 0) : 1;
-    nfaces[ax] = fn[0] * fn[1] * fn[2];
-    h.fst[ax][h.d - 1] = 1;
-    for (int k = h.d - 2; k >= 0; --k) h.fst[ax][k] = h.fst[ax][k + 1] * fn[k + 1];
-  }
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o2 = off;
@@ -570,8 +562,6 @@ csl_status create_problem(const csl_grid *grid, const double *a_nodal, double al
     return o2;
   };
   const size_t o_a = take(sizeof(double) * h.M);
-  size_t o_f[3] = {0, 0, 0};
-  for (int ax = 0; ax < h.d; ++ax) o_f[ax] = take(sizeof(double) * nfaces[ax]);
   const size_t o_mu = take(sizeof(double) * nmu);
   const size_t o_muf = take(sizeof(float) * nmu);
   size_t o_v[7];
@@ -607,7 +597,6 @@ csl_status create_problem(const csl_grid *grid, const double *a_nodal, double al
   double *d_mu = (double *)(base + o_mu);
   float *d_muf = (float *)(base + o_muf);
   h.a = d_a;
-  for (int ax = 0; ax < 3; ++ax) h.F[ax] = ax < h.d ? (const double *)(base + o_f[ax]) : nullptr;
   h.Tq = (double2 *)(base + o_v[0]);
   h.Tv[0] = (double2 *)(base + o_v[1]);
   h.Tv[1] = (double2 *)(base + o_v[2]);
@@ -674,8 +663,6 @@ csl_status create_problem(const csl_grid *grid, const double *a_nodal, double al
   }
   PCHK(hipMemcpyAsync(p->d_desc, &h, sizeof(SysDesc), hipMemcpyHostToDevice, s));
   PCHK(wg256::launch_coef_stats(p->d_desc, h.d, h.M, p->stats_part, p->stats_nblk, p->stats, s));
-  for (int ax = 0; ax < h.d; ++ax)
-    PCHK(wg256::launch_faces(p->d_desc, h.d, ax, nfaces[ax], (double *)h.F[ax], s));
   PCHK(hipMemcpyAsync(st4, p->stats, sizeof(st4), hipMemcpyDeviceToHost, s));
   PCHK(hipStreamSynchronize(s));
   if (st4[3] != 0.0) {
