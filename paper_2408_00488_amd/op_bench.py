@@ -13,7 +13,7 @@ gaps included); under rocprofv3 --kernel-trace the per-kernel durations of
 the same run give the kernels alone.  3-D n = 255 has vectors of 265 MB,
 larger than the 256 MB Infinity Cache, so its rate is an HBM rate.
 
-  python -m paper_2408_00488_amd.op_bench [--cases 3d255,3d127,2d1023] [--reps 20]
+  python -m paper_2408_00488_amd.op_bench [--cases 3d255,3d127,2d1023] [--reps 20] [--lds 65536]
 """
 from __future__ import annotations
 
@@ -38,6 +38,8 @@ def main():
     ap.add_argument("--cases", default="3d255,3d127,2d1023")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--ops", default="A,P64,P32")
+    ap.add_argument("--lds", type=int, default=0,
+                    help="LDS line budget of the problems' schedule (0 = default, 65536)")
     args = ap.parse_args()
     import torch
     import paper_2408_00488_amd as C
@@ -57,6 +59,8 @@ def main():
         for op in ops:
             fp32 = op == "P32"
             p = C.Problem(a, 10.0, 100.0, pinv_fp32=fp32, dst="fft")
+            if args.lds:
+                p.set_schedule(0, args.lds)
             fn = (lambda: C.apply_A(p, x, y)) if op == "A" else (lambda: C.apply_Pinv(p, x, y))
             for _ in range(3):
                 fn()
@@ -70,7 +74,8 @@ def main():
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / args.reps
             bpp = 40.0 if op == "A" else pinv_bytes(len(shape), fp32)
-            print(json.dumps({"case": name, "op": op, "points": M, "ms": round(ms, 4),
+            print(json.dumps({"case": name, "op": op, "lds": p.schedule["lds_bytes"],
+                              "points": M, "ms": round(ms, 4),
                               "model_bytes_per_point": bpp,
                               "model_GBps": round(bpp * M / ms / 1e6, 1),
                               "frac_of_8TBps": round(bpp * M / ms / 1e6 / 8000.0, 3)}),
