@@ -786,6 +786,120 @@ __global__ void init_kernel(const SysDesc *__restrict__ sys, int nsys, Glob *G) 
 // ---------------------------------------------------------------------------
 // Stand-alone operators.
 // ---------------------------------------------------------------------------
+// y = A x on a 3-D grid, marching.  Every wave owns a strip of up to 64
+// points along the contiguous axis (i2) at one i1 and walks a slab of
+// planes along axis 0, keeping x and a of the planes i0 - 1, i0, i0 + 1 in
+// registers: each value comes from HBM once, as the next plane, the face
+// coefficient between two planes is formed once and carried to the next
+// step, and the neighbours and faces along i2 come from the adjacent lanes.
+// The arithmetic is that of stencil_apply: the same face expressions, then
+// the sum over the axes in order.
+// Strips are numbered slab-major, then i1, then the i2 block, and each XCD
+// (workgroup b runs on XCD b mod 8) takes one eighth of that order, so the
+// strips at i1 +- 1 that a strip reads sit in the same L2.
+__device__ __forceinline__ double harm_face(double lo, double hi, double h2) {
+  return (2.0 * lo * hi / (lo + hi)) * h2;
+}
+
+__device__ __forceinline__ double2 shfl2(double2 v, int src) {
+  return make_double2(__shfl(v.x, src, 64), __shfl(v.y, src, 64));
+}
+
+__global__ __launch_bounds__(NT) void apply_A_march3_kernel(const SysDesc *__restrict__ sys,
+                                                            const double2 *__restrict__ x,
+                                                            double2 *__restrict__ y, int nslab) {
+  const SysDesc &S = *sys;
+  const int n0 = S.n[0], n1 = S.n[1], n2 = S.n[2];
+  const int st0 = S.st[0], st1 = S.st[1];
+  const int lane = threadIdx.x & 63;
+  const int xb = (n2 + 63) >> 6;            // strips per line along i2
+  const int per_slab = n1 * xb;
+  const int total = nslab * per_slab;
+  // wave -> strip: XCD k walks strips [k total / 8, (k + 1) total / 8)
+  const int nxcd = 8;
+  const int xcd = blockIdx.x % nxcd, wg = blockIdx.x / nxcd;
+  const int w = wg * (NT / 64) + ((int)threadIdx.x >> 6);
+  const int lo_s = (int)((long long)total * xcd / nxcd);
+  const int hi_s = (int)((long long)total * (xcd + 1) / nxcd);
+  const int strip = lo_s + w;
+  if (strip >= hi_s) return;                // whole waves leave together
+  const int slab = strip / per_slab;
+  const int rem = strip - slab * per_slab;
+  const int i1 = rem / xb;
+  const int i2 = (rem - i1 * xb) * 64 + lane;
+  const bool valid = i2 < n2;
+  const int s0 = (int)((long long)n0 * slab / nslab);
+  const int s1 = (int)((long long)n0 * (slab + 1) / nslab);
+  const CSL_G double2 *__restrict__ xg = gbl(x);
+  const CSL_G double *__restrict__ A = gbl(S.a);
+  CSL_G double2 *__restrict__ yg = gbl(y);
+  const double h0 = S.h2[0], h1 = S.h2[1], h2 = S.h2[2];
+  const double al = S.alpha, be = S.beta;
+  const double2 zero = make_double2(0.0, 0.0);
+  const bool lo1 = i1 > 0, hi1 = i1 < n1 - 1;
+  const bool lo2 = valid && i2 > 0, hi2 = valid && i2 < n2 - 1;
+  const int q = i1 * st1 + (valid ? i2 : 0);
+  int p = s0 * st0 + q;
+  double2 xc = valid ? ldg(xg + p) : zero;
+  double ac = valid ? A[p] : 1.0;
+  double2 xm = zero;
+  double fb0;
+  if (s0 > 0) {
+    xm = valid ? ldg(xg + (p - st0)) : zero;
+    const double am = valid ? A[p - st0] : 1.0;
+    fb0 = harm_face(am, ac, h0);
+  } else {
+    fb0 = ac * h0;
+  }
+  for (int i0 = s0; i0 < s1; ++i0, p += st0) {
+    const bool up0 = i0 < n0 - 1;
+    const double2 xp = (valid && up0) ? ldg(xg + (p + st0)) : zero;
+    const double ap = (valid && up0) ? A[p + st0] : 1.0;
+    // axis 1: the strips at i1 +- 1
+    const double2 xb1 = (valid && lo1) ? ldg(xg + (p - st1)) : zero;
+    const double2 xa1 = (valid && hi1) ? ldg(xg + (p + st1)) : zero;
+    const double ab1 = (valid && lo1) ? A[p - st1] : 1.0;
+    const double aa1 = (valid && hi1) ? A[p + st1] : 1.0;
+    // axis 2: neighbours from the adjacent lanes, the strip ends from memory
+    double2 xb2 = shfl2(xc, lane > 0 ? lane - 1 : 0);
+    double ab2 = __shfl(ac, lane > 0 ? lane - 1 : 0, 64);
+    if (lane == 0 && lo2) {
+      xb2 = ldg(xg + (p - 1));
+      ab2 = A[p - 1];
+    }
+    double2 xa2 = shfl2(xc, lane < 63 ? lane + 1 : 63);
+    if (lane == 63 && hi2) xa2 = ldg(xg + (p + 1));
+    // faces: axis 0 below is carried, above formed now; axis 2 above is the
+    // lower face of the next lane
+    const double fa0 = up0 ? harm_face(ac, ap, h0) : ac * h0;
+    const double fb1 = lo1 ? harm_face(ab1, ac, h1) : ac * h1;
+    const double fa1 = hi1 ? harm_face(ac, aa1, h1) : ac * h1;
+    const double fb2 = lo2 ? harm_face(ab2, ac, h2) : ac * h2;
+    double fa2 = __shfl(fb2, lane < 63 ? lane + 1 : 63, 64);
+    if (lane == 63 && hi2) fa2 = harm_face(ac, A[p + 1], h2);
+    if (!hi2) fa2 = ac * h2;
+    const double2 cb0 = (i0 > 0) ? xm : zero;
+    const double2 ca0 = xp;
+    const double2 cb2 = lo2 ? xb2 : zero;
+    const double2 ca2 = hi2 ? xa2 : zero;
+    double rx = 0.0, ry = 0.0;
+    rx += fb0 * (xc.x - cb0.x) + fa0 * (xc.x - ca0.x);
+    ry += fb0 * (xc.y - cb0.y) + fa0 * (xc.y - ca0.y);
+    rx += fb1 * (xc.x - xb1.x) + fa1 * (xc.x - xa1.x);
+    ry += fb1 * (xc.y - xb1.y) + fa1 * (xc.y - xa1.y);
+    rx += fb2 * (xc.x - cb2.x) + fa2 * (xc.x - ca2.x);
+    ry += fb2 * (xc.y - cb2.y) + fa2 * (xc.y - ca2.y);
+    // y = (K + lambda I) conj(x) = conj(K x + conj(lambda) x)
+    const double ux = rx + al * xc.x + be * xc.y;
+    const double uy = ry + al * xc.y - be * xc.x;
+    if (valid) st_nt(yg + p, ux, -uy);
+    xm = xc;
+    xc = xp;
+    ac = ap;
+    fb0 = fa0;
+  }
+}
+
 // y = A x over the whole grid.  The points are split into 8 contiguous
 // slabs, one per XCD (workgroup b runs on XCD b mod 8), and the workgroups
 // of one XCD sweep their slab in steps of NT points, so the neighbouring
@@ -1049,8 +1163,26 @@ hipError_t launch_init(const SysDesc *dsys, int nsys, Glob *G, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_apply_A(const SysDesc *dsys, int d, int M, const double2 *x, double2 *y,
-                          hipStream_t s) {
+// 3-D grids with at least 16 planes march (about 16K waves, slabs of at least
+// 8 planes); other grids use the point-wise kernel.
+static hipError_t launch_apply_A3(const SysDesc *dsys, const int n[3], const double2 *x,
+                                  double2 *y, hipStream_t s) {
+  const int xb = (n[2] + 63) / 64;
+  const int per_slab = n[1] * xb;
+  int nslab = 16384 / (per_slab > 0 ? per_slab : 1);
+  const int maxslab = n[0] / 8 > 0 ? n[0] / 8 : 1;
+  nslab = nslab < 1 ? 1 : (nslab > maxslab ? maxslab : nslab);
+  const int waves = nslab * per_slab;
+  const int per_xcd_waves = (waves + 7) / 8;
+  const int wgs_per_xcd = (per_xcd_waves + NT / 64 - 1) / (NT / 64);
+  hipLaunchKernelGGL(apply_A_march3_kernel, dim3(8 * wgs_per_xcd), dim3(NT), 0, s, dsys, x, y,
+                     nslab);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_A(const SysDesc *dsys, int d, const int n[3], int M, const double2 *x,
+                          double2 *y, hipStream_t s) {
+  if (d == 3 && n[0] >= 16) return launch_apply_A3(dsys, n, x, y, s);
   // 8 slabs (one per XCD), up to 256 workgroups sweeping each
   const int per = (M / 8 + NT - 1) / NT;
   const int grid = 8 * (per < 1 ? 1 : (per > 256 ? 256 : per));

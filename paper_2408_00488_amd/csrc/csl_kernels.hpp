@@ -17,8 +17,9 @@ hipError_t launch_init(const SysDesc *dsys, int nsys, Glob *G, hipStream_t s);
 hipError_t launch_solve(const SysDesc *dsys, const IOPtr *dio, IOPtr io0, int nsys,
                         const SolveParams &P, Glob *G, int grid, size_t smem, hipStream_t s);
 hipError_t solve_occupancy(size_t smem, int *blocks_per_cu);
-hipError_t launch_apply_A(const SysDesc *dsys, int d, int M, const double2 *x, double2 *y,
-                          hipStream_t s);
+// y = A x; 3-D grids with at least 16 planes take the marching kernel.
+hipError_t launch_apply_A(const SysDesc *dsys, int d, const int n[3], int M, const double2 *x,
+                          double2 *y, hipStream_t s);
 hipError_t launch_pinv_pass(const SysDesc *dsys, int d, int prec, int pass, int ntile, size_t smem,
                             const double2 *x, double2 *y, hipStream_t s);
 hipError_t launch_adjoint(const SysDesc *dsys, int d, int M, const double2 *ytil,

@@ -770,7 +770,8 @@ csl_status problem_dst_engines(csl_problem p, int engines[3]) {
 csl_status apply_A(csl_problem p, const double *x, double *y, hipStream_t s) {
   if (!p || !x || !y) return fail(CSL_ERR_ARG, "NULL argument");
   if (x == y) return fail(CSL_ERR_ARG, "apply_A: x and y must not alias");
-  HIPCHK(wg256::launch_apply_A(p->d_desc, p->h.d, p->h.M, (const double2 *)x, (double2 *)y, s));
+  HIPCHK(wg256::launch_apply_A(p->d_desc, p->h.d, p->h.n, p->h.M, (const double2 *)x,
+                               (double2 *)y, s));
   return CSL_OK;
 }
 
