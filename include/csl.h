@@ -151,7 +151,7 @@ csl_status problem_info(csl_problem p, double *abar, double *a_min,
  * workgroup and phase, which lets a single solve fill the device; 1 = one
  * LDS chunk per tile), the LDS line budget (0 or 32768 = default, 65536
  * = 64 KiB) and the workgroup size of the persistent solver, block_threads:
- * 0 = 512 where allowed, else 256; 256; or 512, which is allowed for 2-D
+ * 0 = 512 where allowed, else 256; 256; or 512, which is allowed for
  * problems whose sine transforms all run on the FFT (CSL_ERR_ARG otherwise).
  * Batches keep their own schedule.  Synchronises s. */
 csl_status problem_set_schedule(csl_problem p, int tile_points, int lds_bytes,
@@ -212,8 +212,8 @@ typedef struct csl_batch_opts {
                                64), 65536 = 64 KiB for every problem (twice
                                the lines per strided tile); 32768 = 0      */
     int block_threads;      /* workgroup size of the persistent solver: 0 =
-                               512 if every problem allows it (2-D, FFT on
-                               both axes), else 256; 256; 512 (CSL_ERR_ARG
+                               512 if every problem allows it (the FFT on
+                               every axis), else 256; 256; 512 (CSL_ERR_ARG
                                unless every problem allows it)             */
 } csl_batch_opts;
 

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libcsl.so")
-SOURCES = ["csl_kernels.hip", "csl_kernels_wg512.hip", "csl_runtime.hip"]
+SOURCES = ["csl_kernels.hip", "csl_kernels_wg512.hip", "csl_kernels_wg512x.hip", "csl_runtime.hip"]
 
 
 def hipcc() -> str:

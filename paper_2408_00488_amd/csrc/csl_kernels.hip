@@ -4,10 +4,11 @@
 // adjoint reduction and the coefficient set-up reductions.
 //
 // This file is the 256-thread instance (namespace csl::wg256).  It is also
-// compiled, through csl_kernels_wg512.hip, as a 512-thread instance of the
-// persistent solver alone (CSL_SOLVE_ONLY) for 2-D systems whose transforms
-// all run on the LDS FFT (CSL_2D_FFT_ONLY): eight waves per workgroup at 128
-// registers keep twice the waves per CU in flight on those paths.
+// compiled as two 512-thread instances of the persistent solver alone
+// (CSL_SOLVE_ONLY) for systems whose transforms all run on the LDS FFT:
+// csl_kernels_wg512.hip for 2-D ones (CSL_2D_FFT_ONLY) and
+// csl_kernels_wg512x.hip for either dimension (CSL_FFT_ONLY).  Eight waves
+// per workgroup at 128 registers keep twice the waves per CU in flight.
 #include <math.h>
 
 #include "csl_device.hpp"
@@ -18,6 +19,9 @@
 #endif
 #ifndef CSL_2D_FFT_ONLY
 #define CSL_2D_FFT_ONLY 0
+#endif
+#ifndef CSL_FFT_ONLY
+#define CSL_FFT_ONLY 0
 #endif
 
 namespace csl {
@@ -347,6 +351,9 @@ __device__ __forceinline__ void process_tile(const SysDesc &S, const IOPtr &io, 
                              char *smem, double *red) {
 #if CSL_2D_FFT_ONLY
   const bool d3 = false;
+  const bool g = false;
+#elif CSL_FFT_ONLY
+  const bool d3 = (S.d == 3);
   const bool g = false;
 #else
   const bool d3 = (S.d == 3);

@@ -1,7 +1,8 @@
 // Host-callable launch wrappers of the gfx950 kernels.  The device code is
-// built twice: csl::wg256 (256-thread workgroups; every kernel) and
+// built three times: csl::wg256 (256-thread workgroups; every kernel),
 // csl::wg512 (512-thread workgroups; the persistent solver for 2-D systems
-// whose transforms all run on the LDS FFT).
+// whose transforms all run on the LDS FFT) and csl::wg512x (the same for
+// FFT systems of either dimension).
 #pragma once
 #include "csl_common.hpp"
 
@@ -39,5 +40,14 @@ hipError_t launch_solve(const SysDesc *dsys, const IOPtr *dio, IOPtr io0, int ns
 hipError_t solve_occupancy(size_t smem, int *blocks_per_cu);
 
 }  // namespace wg512
+
+namespace wg512x {
+
+hipError_t upload_twiddles(const double2 *tw64, const float2 *tw32);
+hipError_t launch_solve(const SysDesc *dsys, const IOPtr *dio, IOPtr io0, int nsys,
+                        const SolveParams &P, Glob *G, int grid, size_t smem, hipStream_t s);
+hipError_t solve_occupancy(size_t smem, int *blocks_per_cu);
+
+}  // namespace wg512x
 
 }  // namespace csl

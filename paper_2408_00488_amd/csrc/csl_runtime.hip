@@ -53,6 +53,7 @@ csl_status ensure_twiddles(int dev) {
   }
   HIPCHK(wg256::upload_twiddles(t64.data(), t32.data()));
   HIPCHK(wg512::upload_twiddles(t64.data(), t32.data()));
+  HIPCHK(wg512x::upload_twiddles(t64.data(), t32.data()));
   g_tw_ready[dev] = true;
   return CSL_OK;
 }
@@ -91,17 +92,23 @@ void sine_matrix(int n, int np, std::vector<double> &W) {
     }
 }
 
-// The persistent solver instance of a workgroup size: 512 threads (2-D
-// systems with the FFT on both axes only) or 256.
-hipError_t solve_launch(int wg, const SysDesc *dsys, const IOPtr *dio, IOPtr io0, int nsys,
-                        const SolveParams &P, Glob *G, int grid, size_t smem, hipStream_t s) {
-  return wg == 512 ? wg512::launch_solve(dsys, dio, io0, nsys, P, G, grid, smem, s)
-                   : wg256::launch_solve(dsys, dio, io0, nsys, P, G, grid, smem, s);
+// The persistent solver instance of a workgroup size: 512 threads for
+// systems with the FFT on every axis (csl::wg512 when every system is 2-D,
+// csl::wg512x otherwise) or 256.
+hipError_t solve_launch(int wg, bool all2d, const SysDesc *dsys, const IOPtr *dio, IOPtr io0,
+                        int nsys, const SolveParams &P, Glob *G, int grid, size_t smem,
+                        hipStream_t s) {
+  if (wg != 512) return wg256::launch_solve(dsys, dio, io0, nsys, P, G, grid, smem, s);
+  return all2d ? wg512::launch_solve(dsys, dio, io0, nsys, P, G, grid, smem, s)
+               : wg512x::launch_solve(dsys, dio, io0, nsys, P, G, grid, smem, s);
 }
-hipError_t solve_occupancy_wg(int wg, size_t smem, int *blocks_per_cu) {
-  return wg == 512 ? wg512::solve_occupancy(smem, blocks_per_cu)
-                   : wg256::solve_occupancy(smem, blocks_per_cu);
+hipError_t solve_occupancy_wg(int wg, bool all2d, size_t smem, int *blocks_per_cu) {
+  if (wg != 512) return wg256::solve_occupancy(smem, blocks_per_cu);
+  return all2d ? wg512::solve_occupancy(smem, blocks_per_cu)
+               : wg512x::solve_occupancy(smem, blocks_per_cu);
 }
+// The 512-thread solver applies: the FFT on every axis.
+bool fft_everywhere(const SysDesc &h) { return !h.gemm[0] && !h.gemm[1] && !h.gemm[2]; }
 // Workgroup size for a request (0 = the larger one where allowed).
 int resolve_wg(int block_threads, bool wg512_ok) {
   if (block_threads == 256) return 256;
@@ -142,7 +149,7 @@ struct csl_problem_s {
   int tile_points = 0;   // current schedule of the problem's own solves
   int lds_bytes = 0;
   int block_threads = 256;
-  bool wg512_ok = false; // 2-D with the FFT on both axes: the 512-thread solver applies
+  bool wg512_ok = false; // the FFT on every axis: the 512-thread solver applies
 };
 
 struct csl_batch_s {
@@ -168,6 +175,7 @@ struct csl_batch_s {
   int lds_bytes = 0;
   int block_threads = 256;
   bool wg512_ok = false; // every problem allows the 512-thread solver
+  bool all2d = true;     // every problem is 2-D (the 2-D-only 512-thread instance)
 };
 
 namespace {
@@ -321,7 +329,7 @@ csl_status configure_single(csl_problem p, int tile_points, int lds_bytes, int b
   if (lds_bytes > 32768 && p->smem0 <= 32768) choose_tiles(h, p->tile_elems, lds_bytes, &sm);
   const int wg = resolve_wg(block_threads, p->wg512_ok);
   int bpc = 0;
-  HIPCHK(solve_occupancy_wg(wg, sm, &bpc));
+  HIPCHK(solve_occupancy_wg(wg, p->h0.d == 2, sm, &bpc));
   const int cap = std::max(1, bpc) * p->cus;
   const int tp = tile_points > 0 ? tile_points : (int)std::min<long long>(1 << 30, h.M / cap);
   set_tile_points(h, tp);
@@ -373,14 +381,15 @@ csl_status tune_engines(csl_problem p, int elig, hipStream_t s, int *best_mask) 
     p->h = h;
     p->h0 = h;
     p->smem0 = smem_in;
-    p->wg512_ok = h.d == 2 && !h.gemm[0] && !h.gemm[1];
+    p->wg512_ok = fft_everywhere(h);
     st = configure_single(p, 0, 0, 0, s);
     if (st != CSL_OK) break;
     for (int r = 0; r <= reps && err == hipSuccess; ++r) {
       if (r == 1) err = hipEventRecord(e0, s);   // the first solve is a warm-up
       if (err == hipSuccess) err = wg256::launch_init(p->d_desc, 1, p->glob, s);
       if (err == hipSuccess)
-        err = solve_launch(p->block_threads, p->d_desc, nullptr, io0, 1, P, p->glob, p->grid1,
+        err = solve_launch(p->block_threads, h.d == 2, p->d_desc, nullptr, io0, 1, P, p->glob,
+                           p->grid1,
                            p->smem, s);
     }
     if (err == hipSuccess) err = hipEventRecord(e1, s);
@@ -432,7 +441,7 @@ csl_status configure_batch(csl_batch b, int tile_points, int lds_bytes, int bloc
   b->lds_bytes = smem <= 32768 ? 32768 : 65536;
   b->block_threads = resolve_wg(block_threads, b->wg512_ok);
   int bpc = 0;
-  HIPCHK(solve_occupancy_wg(b->block_threads, smem, &bpc));
+  HIPCHK(solve_occupancy_wg(b->block_threads, b->all2d, smem, &bpc));
   // tiles are claimed dynamically, so a full-occupancy grid keeps every CU
   // busy whatever the mix of systems
   const int cap = std::max(1, bpc) * b->probs[0]->cus;
@@ -444,7 +453,8 @@ csl_status configure_batch(csl_batch b, int tile_points, int lds_bytes, int bloc
   if (ok) {
     ok = wg256::launch_init(b->d_desc, b->count, b->glob, cs) == hipSuccess;
     IOPtr none{nullptr, nullptr};
-    ok = ok && solve_launch(b->block_threads, b->d_desc, b->d_io, none, b->count, b->params,
+    ok = ok && solve_launch(b->block_threads, b->all2d, b->d_desc, b->d_io, none, b->count,
+                            b->params,
                             b->glob, b->grid, b->smem, cs) == hipSuccess;
     hipGraph_t g = nullptr;
     const bool ended = hipStreamEndCapture(cs, &g) == hipSuccess;
@@ -734,7 +744,7 @@ csl_status create_problem(const csl_grid *grid, const double *a_nodal, double al
   PCHK(hipStreamSynchronize(s));
   p->h0 = p->h;
   p->smem0 = p->smem;
-  p->wg512_ok = h.d == 2 && !p->h.gemm[0] && !p->h.gemm[1];
+  p->wg512_ok = fft_everywhere(p->h);
   {
     const csl_status st = configure_single(p, 0, 0, 0, s);
     if (st != CSL_OK) {
@@ -785,7 +795,8 @@ static csl_status run_single(csl_problem p, const double2 *f, double2 *x, const 
                              hipStream_t s) {
   HIPCHK(wg256::launch_init(p->d_desc, 1, p->glob, s));
   IOPtr io0{f, x};
-  HIPCHK(solve_launch(p->block_threads, p->d_desc, nullptr, io0, 1, P, p->glob, p->grid1, p->smem,
+  HIPCHK(solve_launch(p->block_threads, p->h.d == 2, p->d_desc, nullptr, io0, 1, P, p->glob,
+                      p->grid1, p->smem,
                       s));
   return CSL_OK;
 }
@@ -829,7 +840,7 @@ csl_status problem_set_schedule(csl_problem p, int tile_points, int lds_bytes, i
   if (!valid_block_threads(block_threads))
     return fail(CSL_ERR_ARG, "block_threads must be 0, 256 or 512");
   if (block_threads == 512 && !p->wg512_ok)
-    return fail(CSL_ERR_ARG, "block_threads 512 needs a 2-D problem with the FFT on both axes");
+    return fail(CSL_ERR_ARG, "block_threads 512 needs the FFT engine on every axis");
   return configure_single(p, tile_points, lds_bytes, block_threads, s);
 }
 
@@ -999,9 +1010,13 @@ csl_status batch_create(const csl_problem *problems, int count, const csl_batch_
   if (!valid_block_threads(o.block_threads))
     return cleanup(CSL_ERR_ARG, "block_threads must be 0, 256 or 512");
   b->wg512_ok = true;
-  for (int i = 0; i < count; ++i) b->wg512_ok = b->wg512_ok && problems[i]->wg512_ok;
+  b->all2d = true;
+  for (int i = 0; i < count; ++i) {
+    b->wg512_ok = b->wg512_ok && problems[i]->wg512_ok;
+    b->all2d = b->all2d && problems[i]->h.d == 2;
+  }
   if (o.block_threads == 512 && !b->wg512_ok)
-    return cleanup(CSL_ERR_ARG, "block_threads 512 needs 2-D problems with the FFT on both axes");
+    return cleanup(CSL_ERR_ARG, "block_threads 512 needs the FFT engine on every axis of every problem");
   const csl_status st = configure_batch(b, o.tile_points > 0 ? o.tile_points : 8192,
                                         o.lds_bytes, o.block_threads, b->use_graph);
   if (st != CSL_OK) {
@@ -1038,8 +1053,8 @@ csl_status batch_solve(csl_batch b, const double *const *f, double *const *z,
   } else {
     HIPCHK(wg256::launch_init(b->d_desc, b->count, b->glob, s));
     IOPtr none{nullptr, nullptr};
-    HIPCHK(solve_launch(b->block_threads, b->d_desc, b->d_io, none, b->count, b->params, b->glob,
-                        b->grid, b->smem, s));
+    HIPCHK(solve_launch(b->block_threads, b->all2d, b->d_desc, b->d_io, none, b->count, b->params,
+                        b->glob, b->grid, b->smem, s));
   }
   if (!infos) return CSL_OK;
   std::vector<DevInfo> di(b->count);

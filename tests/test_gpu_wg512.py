@@ -1,7 +1,7 @@
-"""GPU parity of the persistent solver's 512-thread instance (eight waves per
-workgroup, for 2-D systems whose sine transforms all run on the FFT) against
-the CPU oracle and against the 256-thread instance, and the rules that
-choose between them.
+"""GPU parity of the persistent solver's 512-thread instances (eight waves per
+workgroup, for systems whose sine transforms all run on the FFT: one for
+batches of 2-D systems, one for any dimension) against the CPU oracle and
+against the 256-thread instance, and the rules that choose between them.
 
 Tolerances (relative 2-norm), as for the 256-thread solver:
   MINRES iterates against the FP64 oracle at a matched iteration count:
@@ -82,16 +82,19 @@ def test_selection_rules(csl):
     a2 = cuda(_coef((63, 63), 1))
     a3 = cuda(_coef((7, 15, 31), 2))
     p2 = csl.Problem(a2, -40.0, 3.0, dst="fft")
-    p3 = csl.Problem(a3, -40.0, 3.0)
+    p3 = csl.Problem(a3, -40.0, 3.0, dst="fft")
+    p3g = csl.Problem(a3, -40.0, 3.0, dst="gemm")
     pg = csl.Problem(a2, -40.0, 3.0, dst="gemm")
     assert pg.dst_engines == ("gemm", "gemm")
+    assert p3g.dst_engines == ("fft", "gemm", "gemm")
     assert p2.schedule["block_threads"] == 512
-    assert p3.schedule["block_threads"] == 256
+    assert p3.schedule["block_threads"] == 512
     assert pg.schedule["block_threads"] == 256
+    assert p3g.schedule["block_threads"] == 256
     # a GEMM axis next to an FFT one also keeps the 256-thread solver
     pm = csl.Problem(cuda(_coef((127, 511), 3)), 5.0, 5.0, dst="gemm")
     assert pm.dst_engines == ("gemm", "fft") and pm.schedule["block_threads"] == 256
-    for p in (p3, pg, pm):
+    for p in (p3g, pg, pm):
         with pytest.raises(csl.CSLError):
             p.set_schedule(0, 0, 512)
     p2.set_schedule(0, 0, 256)
@@ -101,9 +104,11 @@ def test_selection_rules(csl):
     b = csl.Batch([p2, csl.Problem(a2, 10.0, -3.0, pinv_fp32=True, dst="fft")])
     assert b.schedule["block_threads"] == 512
     assert csl.Batch([p2], block_threads=256).schedule["block_threads"] == 256
-    assert csl.Batch([p2, p3]).schedule["block_threads"] == 256
+    # 2-D and 3-D FFT systems together: the any-dimension 512-thread instance
+    assert csl.Batch([p2, p3]).schedule["block_threads"] == 512
+    assert csl.Batch([p2, p3g]).schedule["block_threads"] == 256
     with pytest.raises(csl.CSLError):
-        csl.Batch([p2, p3], block_threads=512)
+        csl.Batch([p2, p3g], block_threads=512)
     with pytest.raises(csl.CSLError):
         csl.Batch([p2], block_threads=128)
 
@@ -141,6 +146,67 @@ def test_single_solve_both_instances(csl, shape, lengths, fp32):
         assert abs(out[512][1]["iters"] - out[256][1]["iters"]) <= 1
         if out[512][1]["iters"] == out[256][1]["iters"]:
             assert rel(out[512][0], out[256][0]) <= 1e-10
+
+
+SHAPES3 = [((7, 15, 31), [0.5, 1.0, 2.0]), ((15, 15, 15), None), ((31, 31, 31), None),
+           ((3, 63, 7), None)]
+
+
+@pytest.mark.parametrize("shape,lengths", SHAPES3)
+@pytest.mark.parametrize("fp32", [False, True])
+def test_single_solve_3d_both_instances(csl, shape, lengths, fp32):
+    _say("wg512x single", shape, lengths, fp32)
+    a = _coef(shape, 31, 1.0, 3.0)
+    f = _crand(shape, 32)
+    lam = 10.0 + 100.0j
+    p = csl.Problem(cuda(a), lam.real, lam.imag, pinv_fp32=fp32, lengths=lengths, dst="fft")
+    po = O.Problem(a, lam.real, lam.imag, abar_rule="given", abar=p.abar, lengths=lengths)
+    zo, io = po.solve(f, tol=1e-8)
+    out = {}
+    for bt in (512, 256):
+        p.set_schedule(0, 0, bt)
+        assert p.schedule["block_threads"] == bt
+        z, info = csl.minres_solve(p, cuda(f), raise_on_error=False, timeout_ms=30000)
+        zg = z.cpu().numpy()
+        _say(" ", bt, info, io["iters"])
+        assert info["status"] == 0 and info["relres_true"] <= 1e-8
+        if fp32:
+            assert _oracle_relres(po, lam, f, zg) <= 1.01e-8
+        else:
+            assert _vs_oracle(po, f, zg, info, zo, io) <= 1e-10
+        out[bt] = (zg, info)
+    if not fp32 and out[512][1]["iters"] == out[256][1]["iters"]:
+        assert rel(out[512][0], out[256][0]) <= 1e-10
+
+
+def test_batch_2d_and_3d_on_512(csl):
+    # the any-dimension instance carries 2-D and 3-D systems in one launch
+    cases = [((31, 31, 31), 10 + 100j, False), ((63, 63), -50 + 20j, False),
+             ((15, 31, 15), 5 + 50j, True), ((127, 63), 30 - 40j, True)]
+    probs, fs, ref = [], [], []
+    for k, (shape, lam, fp32) in enumerate(cases):
+        a = _coef(shape, 40 + k, 1.0, 3.0)
+        f = _crand(shape, 50 + k)
+        p = csl.Problem(cuda(a), lam.real, lam.imag, pinv_fp32=fp32, dst="fft")
+        probs.append(p)
+        fs.append(cuda(f))
+        ref.append((a, f, lam, fp32, O.Problem(a, lam.real, lam.imag, abar_rule="given", abar=p.abar)))
+    b = csl.Batch(probs, timeout_ms=30000)
+    assert b.schedule["block_threads"] == 512
+    zs, infos = b.solve(fs)
+    _say("wg512x batch", [i["iters"] for i in infos])
+    for (a, f, lam, fp32, po), z, info in zip(ref, zs, infos):
+        assert info["status"] == 0 and info["relres_true"] <= 1e-8
+        zg = z.cpu().numpy()
+        if fp32:
+            assert _oracle_relres(po, lam, f, zg) <= 1.01e-8
+        else:
+            zo, io = po.solve(f, tol=1e-8)
+            assert _vs_oracle(po, f, zg, info, zo, io) <= 1e-10
+    zs2, infos2 = b.solve(fs)
+    assert infos2 == infos
+    for z1, z2 in zip(zs, zs2):
+        assert torch.equal(z1, z2)
 
 
 @pytest.mark.parametrize("fp32", [False, True])
