@@ -21,7 +21,7 @@
  * interior grid node in C order (last axis contiguous).  The real block
  * vector [x1; x2] is stored as x1 + i x2.  The nodal coefficient is a DEVICE
  * array of M doubles in the same order.  Grid axis k has n[k] interior
- * points with n[k] + 1 a power of two, 2 <= n[k] + 1 <= 1024 (n in
+ * points with n[k] + 1 a power of two, 4 <= n[k] + 1 <= 1024 (n in
  * {3, 7, ..., 1023}), mesh width h_k = length[k] / (n[k] + 1).
  *
  * Ownership.  The caller owns every vector and coefficient buffer and keeps
@@ -118,7 +118,10 @@ typedef struct csl_solve_opts {
     int maxit;              /* iteration limit (default 1000 when <= 0)         */
     int check_true_residual;/* 1: also require ||f - (K+lambda I) z|| / ||f||
                                <= tol once the recurrence estimate passed      */
-    int timeout_ms;         /* kernel time limit (default 60000 when <= 0)      */
+    int timeout_ms;         /* kernel time limit (default 60000 when <= 0): past
+                               it no further phase is started, the launch
+                               returns within one phase and an unfinished
+                               solve reports CSL_ERR_TIMEOUT                */
     int reserved[3];
 } csl_solve_opts;
 
@@ -242,7 +245,8 @@ csl_status batch_create(const csl_problem *problems, int count,
  * system j (host arrays of `count` pointers).  One (graph) launch.  If
  * infos != NULL (host array of `count`), synchronises `s`, fills the infos
  * and returns CSL_OK only if every system converged (else the first
- * non-OK status). */
+ * non-OK status).  At the time limit, systems already finished keep their
+ * status and solution; the others report CSL_ERR_TIMEOUT. */
 csl_status batch_solve(csl_batch b, const double *const *f, double *const *z,
                        csl_solve_info *infos, hipStream_t s);
 

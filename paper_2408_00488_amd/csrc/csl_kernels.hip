@@ -663,7 +663,9 @@ __device__ __forceinline__ void epilogue(const SysDesc &S, const SolveParams &P,
 // system has one ready, processes it, and the workgroup that completes a
 // phase runs its epilogue.  A workgroup never waits while holding a tile,
 // so progress does not depend on which workgroups are resident.  Idle
-// workgroups exit when every system is done or the time limit passes.
+// workgroups exit when every system is done or the time limit passes; past
+// the limit no phase is published any more, so a system stops where it is
+// (status left unset) instead of running on in the workgroups still busy.
 // ---------------------------------------------------------------------------
 template <int LDSB>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) void solve_kernel(
@@ -757,8 +759,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         const unsigned old = __hip_atomic_fetch_add(&S.ctl->done, 1u, __ATOMIC_RELAXED,
                                                      __HIP_MEMORY_SCOPE_AGENT);
-        const int last = (old + 1 == (unsigned)S.ntile[kind]);
-        if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        int last = (old + 1 == (unsigned)S.ntile[kind]);
+        if (last) {
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          // past the time limit the next phase is not published: every
+          // system stops within one phase and the idle workgroups exit
+          if (wall_clock64() - t0 > P.timeout_ticks) {
+            __hip_atomic_fetch_or(&G->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            last = 0;
+          }
+        }
         sh_last = last;
       }
       __syncthreads();

@@ -271,25 +271,32 @@ void set_tile_points(SysDesc &h, int points) {
     if (h.d == 3) cpts[K_Y1] = cpts[K_Y1I] = per(h.lpt_s[1] * h.n[1]);
     cpts[K_PR] = per(h.rpt * nlast);
   }
-  int mx = 0;
+  // ntile <= nchunk, so the partials buffer sized by the chunk counts (maxtile)
+  // holds every tile's partial
   for (int k = 0; k < K_NKINDS; ++k) {
     h.cpt[k] = cpts[k];
     h.ntile[k] = h.nchunk[k] > 0 ? (h.nchunk[k] + cpts[k] - 1) / cpts[k] : 0;
-    mx = std::max(mx, h.ntile[k]);
   }
-  h.maxtile = std::max(h.maxtile, 0);
-  (void)mx;
 }
 
-csl_status info_from_device(const DevInfo &di, int glob_error, csl_solve_info *info) {
+// A system whose status is still unset when the kernel returns was stopped
+// by the time limit; one that finished keeps its own status (its solution
+// is complete even when another system of the batch timed out).
+csl_status info_from_device(const DevInfo &di, csl_solve_info *info) {
   csl_solve_info r;
   r.status = di.status;
   r.iters = di.iters;
   r.relres_est = di.relres_est;
   r.relres_true = di.relres_true;
-  if (glob_error || di.status < 0) r.status = CSL_ERR_TIMEOUT;
+  if (di.status < 0) r.status = CSL_ERR_TIMEOUT;
   if (info) *info = r;
   return (csl_status)r.status;
+}
+
+const char *status_name(csl_status st) {
+  static const char *names[] = {"ok", "bad argument", "singular", "not converged",
+                                "breakdown", "non-finite", "hip", "oom", "timeout"};
+  return st >= 0 && st <= 8 ? names[st] : "?";
 }
 
 void free_problem(csl_problem p) {
@@ -803,16 +810,10 @@ static csl_status run_single(csl_problem p, const double2 *f, double2 *x, const 
 
 static csl_status fetch_single_info(csl_problem p, csl_solve_info *info, hipStream_t s) {
   DevInfo di;
-  Glob g;
   HIPCHK(hipMemcpyAsync(&di, p->h.info, sizeof(di), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(&g, p->glob, sizeof(g), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  const csl_status st = info_from_device(di, g.error, info);
-  if (st != CSL_OK) {
-    static const char *names[] = {"ok", "bad argument", "singular", "not converged",
-                                  "breakdown", "non-finite", "hip", "oom", "timeout"};
-    g_err = std::string("solve ended with status: ") + (st >= 0 && st <= 8 ? names[st] : "?");
-  }
+  const csl_status st = info_from_device(di, info);
+  if (st != CSL_OK) g_err = std::string("solve ended with status: ") + status_name(st);
   return st;
 }
 
@@ -1058,16 +1059,18 @@ csl_status batch_solve(csl_batch b, const double *const *f, double *const *z,
   }
   if (!infos) return CSL_OK;
   std::vector<DevInfo> di(b->count);
-  Glob g;
   HIPCHK(hipMemcpyAsync(di.data(), b->d_info, sizeof(DevInfo) * b->count, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(&g, b->glob, sizeof(g), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   csl_status first = CSL_OK;
+  int nbad = 0;
   for (int i = 0; i < b->count; ++i) {
-    const csl_status st = info_from_device(di[i], g.error, &infos[i]);
+    const csl_status st = info_from_device(di[i], &infos[i]);
     if (st != CSL_OK && first == CSL_OK) first = st;
+    nbad += st != CSL_OK;
   }
-  if (first != CSL_OK) g_err = "batch: at least one system did not converge";
+  if (first != CSL_OK)
+    g_err = "batch: " + std::to_string(nbad) + " system(s) ended without convergence, the first"
+            " with status: " + status_name(first);
   return first;
 }
 
