@@ -18,10 +18,10 @@ inner product of two block vectors is then Re(p^H q).
 
 Pins.  Every function is pinned by tests against something other than
 itself (closed forms, dense linear algebra, the paper's theorems and tables,
-brute force on tiny grids); see tests/test_oracle_pins.py.  The exact
-iteration count of the paper's Example 2 (Table 2(a)) is *parity unpinned*:
-the paper does not state its domain, so only the n-independence of the count
-is checked.
+brute force on tiny grids); see tests/test_oracle_pins.py.  The paper does
+not state the domain of its Example 2; on the unit square the iteration
+count of Table 2(a) (14 for every listed shift) is reproduced at n = 63 and
+n = 255, and checked there together with its independence of n.
 """
 from __future__ import annotations
 

@@ -15,6 +15,8 @@ errors of O(1e-16 ||f||)); finite differences: relative 1e-5 (central
 difference truncation, of order step^2, and the solve noise 1e-12 / step,
 about 1e-6 relative at a relative step of 1e-6).
 """
+import json
+import os
 import sys
 
 import numpy as np
@@ -26,6 +28,8 @@ from oracle import csl_oracle as O
 from paper_2408_00488_amd import workloads as WL
 
 pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
 
 def _say(*a):
@@ -161,3 +165,53 @@ def test_c5_full_size_adjoint_directional_fd(csl):
     anf = float(np.real(np.vdot(gf[j].cpu().numpy(), df)))
     _say("dL/df . d", fdf, anf)
     assert anf == pytest.approx(fdf, rel=1e-5)
+
+
+def _crand(shape, seed):
+    g = np.random.default_rng(seed)
+    return g.standard_normal(shape) + 1j * g.standard_normal(shape)
+
+
+def test_iterations_flat_in_n_table2a(csl):
+    # Theorem 4 at the sizes of Table 2(a) that the grid rules admit (n = 63,
+    # 255, 1023), Example 2's coefficient on the unit square and the
+    # geometric-mean abar: for each of the table's shifts the GPU count is the
+    # printed 14 at every n, every solution meets the tolerance under the
+    # oracle's K, and at n = 63 the count equals the oracle's within one step.
+    gold = json.load(open(os.path.join(GOLD, "table2a_iterations.json")))
+    for alpha, beta in gold["shifts_alpha_beta"]:
+        lam = complex(alpha, beta)
+        its = []
+        for n in (63, 255, 1023):
+            a = WL.coef_paper_ex2(n)
+            f = _crand((n, n), 7)
+            p = csl.Problem(cuda(a), alpha, beta, abar_rule="geomean")
+            z, info = csl.minres_solve(p, cuda(f), timeout_ms=60000)
+            zc = z.cpu().numpy()
+            rr = _oracle_relres(O.build_K(a), lam, f, zc)
+            _say("table 2(a)", lam, n, info["iters"], rr)
+            assert info["status"] == 0 and rr <= 1e-8
+            if n == 63:
+                _, io = O.Problem(a, alpha, beta, abar_rule="given", abar=p.abar).solve(f)
+                assert abs(io["iters"] - info["iters"]) <= 1, (io["iters"], info)
+            its.append(info["iters"])
+            p.close()
+        assert its == [gold["iterations"]] * 3, (lam, its)
+
+
+def test_iterations_flat_in_n_3d(csl):
+    # the same property in 3-D on the c3 coefficient and shift, n = 15 .. 127,
+    # with the FP32 preconditioner
+    lam = complex(10.0, 100.0)
+    its = []
+    for n in (15, 31, 63, 127):
+        a = WL.coef_c3(n)
+        f = _crand((n, n, n), 9)
+        p = csl.Problem(cuda(a), lam.real, lam.imag, pinv_fp32=True)
+        z, info = csl.minres_solve(p, cuda(f), timeout_ms=60000)
+        rr = _oracle_relres(O.build_K(a), lam, f, z.cpu().numpy())
+        _say("3-D", n, info["iters"], rr)
+        assert info["status"] == 0 and rr <= 1e-8
+        its.append(info["iters"])
+        p.close()
+    assert max(its) - min(its) <= 2, its

@@ -314,17 +314,19 @@ def test_lemma1_bound_holds():
 
 
 def test_theorem4_iterations_flat_in_n():
-    # Theorem 4 / Table 2(a): the count does not grow with n.  The exact
-    # value 14 is parity unpinned (the paper's domain is not stated).
+    # Theorem 4 / Table 2(a): the count does not grow with n, and at the
+    # table's sizes n = 63 and 255 (unit square, the reading of the unstated
+    # domain) it is the printed 14 for every shift.
     gold = json.load(open(os.path.join(GOLD, "table2a_iterations.json")))
-    for alpha, beta in gold["shifts_alpha_beta"][:4]:
-        its = []
-        for n in (15, 31, 63):
+    for alpha, beta in gold["shifts_alpha_beta"]:
+        its = {}
+        for n in (15, 31, 63, 255):
             prob = O.Problem(WL.coef_paper_ex2(n), alpha, beta, abar_rule="geomean")
             _, info = prob.solve(_crand((n, n), 7), tol=1e-8)
-            its.append(info["iters"])
-        assert max(its) - min(its) <= 2, its
-        assert max(its) <= gold["iterations"] + 4
+            assert info["status"] == O.STATUS_OK
+            its[n] = info["iters"]
+        assert max(its.values()) - min(its.values()) <= 2, its
+        assert its[63] == gold["iterations"] and its[255] == gold["iterations"], its
 
 
 def test_minres_status_paths():
