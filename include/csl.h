@@ -242,7 +242,8 @@ csl_status batch_create(const csl_problem *problems, int count,
                         const csl_batch_opts *opts, csl_batch *out);
 
 /* Solve every system of the batch: f[j], z[j] are device pointers for
- * system j (host arrays of `count` pointers).  One (graph) launch.  If
+ * system j (host arrays of `count` pointers).  The z[j] are distinct and
+ * none is any f[i] (CSL_ERR_ARG otherwise).  One (graph) launch.  If
  * infos != NULL (host array of `count`), synchronises `s`, fills the infos
  * and returns CSL_OK only if every system converged (else the first
  * non-OK status).  At the time limit, systems already finished keep their

@@ -817,14 +817,19 @@ static csl_status fetch_single_info(csl_problem p, csl_solve_info *info, hipStre
   return st;
 }
 
+static csl_status check_solve_opts(const csl_solve_opts &o) {
+  if (o.maxit > 16000000) return fail(CSL_ERR_ARG, "maxit too large");
+  if (!std::isfinite(o.tol)) return fail(CSL_ERR_ARG, "tol must be finite");
+  return CSL_OK;
+}
+
 csl_status minres_solve(csl_problem p, const double *f, double *z, const csl_solve_opts *opts,
                         csl_solve_info *info, hipStream_t s) {
   if (!p || !f || !z) return fail(CSL_ERR_ARG, "NULL argument");
   if (f == z) return fail(CSL_ERR_ARG, "minres_solve: f and z must not alias");
   csl_solve_opts o{};
   if (opts) o = *opts;
-  if (o.maxit > 16000000) return fail(CSL_ERR_ARG, "maxit too large");
-  if (opts && !(std::isfinite(o.tol))) return fail(CSL_ERR_ARG, "tol must be finite");
+  if (check_solve_opts(o) != CSL_OK) return CSL_ERR_ARG;
   const SolveParams P = make_params(o.tol, o.maxit, o.check_true_residual, o.timeout_ms, p->wall_khz);
   csl_status st = run_single(p, (const double2 *)f, (double2 *)z, P, s);
   if (st != CSL_OK) return st;
@@ -934,8 +939,10 @@ csl_status minres_adjoint(csl_problem p, const double *z, const double *gz, doub
                           double *galpha, double *gbeta, double *ga, const csl_solve_opts *opts,
                           csl_solve_info *info, hipStream_t s) {
   if (!p || !z || !gz) return fail(CSL_ERR_ARG, "NULL argument");
+  if ((const double *)gf == z) return fail(CSL_ERR_ARG, "minres_adjoint: gf and z must not alias");
   csl_solve_opts o{};
   if (opts) o = *opts;
+  if (check_solve_opts(o) != CSL_OK) return CSL_ERR_ARG;
   const SolveParams P = make_params(o.tol, o.maxit, o.check_true_residual, o.timeout_ms, p->wall_khz);
   const int M = p->h.M;
   // y = (K + conj(lambda) I)^{-1} G  <=>  A (block) u = conj(G) with u = y;
@@ -1001,6 +1008,9 @@ csl_status batch_create(const csl_problem *problems, int count, const csl_batch_
     return cleanup(CSL_ERR_HIP, "hipHostMalloc failed");
   if (hipEventCreateWithFlags(&b->copy_done, hipEventDisableTiming) != hipSuccess)
     return cleanup(CSL_ERR_HIP, "hipEventCreate failed");
+  if (o.maxit > 16000000) return cleanup(CSL_ERR_ARG, "maxit too large");
+  if (!std::isfinite(o.tol)) return cleanup(CSL_ERR_ARG, "tol must be finite");
+  if (o.grid_size < 0) return cleanup(CSL_ERR_ARG, "grid_size must be >= 0");
   b->grid_opt = o.grid_size;
   b->params = make_params(o.tol, o.maxit, o.check_true_residual, o.timeout_ms,
                           problems[0]->wall_khz);
@@ -1034,12 +1044,19 @@ csl_status batch_solve(csl_batch b, const double *const *f, double *const *z,
   bool same = b->io_valid;
   for (int i = 0; i < b->count; ++i) {
     if (!f[i] || !z[i]) return fail(CSL_ERR_ARG, "NULL vector in batch");
-    if ((const void *)f[i] == (const void *)z[i])
-      return fail(CSL_ERR_ARG, "batch_solve: f and z must not alias");
     if (same && (b->h_io[i].f != (const double2 *)f[i] || b->h_io[i].x != (double2 *)z[i]))
       same = false;
   }
   if (!same) {
+    // every solution vector is written by its own system while the others
+    // read their right-hand sides: no z may be another z or any f
+    std::vector<const void *> zs(z, z + b->count);
+    std::sort(zs.begin(), zs.end());
+    if (std::adjacent_find(zs.begin(), zs.end()) != zs.end())
+      return fail(CSL_ERR_ARG, "batch_solve: two systems share a solution vector");
+    for (int i = 0; i < b->count; ++i)
+      if (std::binary_search(zs.begin(), zs.end(), (const void *)f[i]))
+        return fail(CSL_ERR_ARG, "batch_solve: a right-hand side is also a solution vector");
     HIPCHK(hipEventSynchronize(b->copy_done));
     for (int i = 0; i < b->count; ++i) {
       b->h_io[i].f = (const double2 *)f[i];

@@ -174,3 +174,48 @@ def test_time_limit_batch(csl):
     b.close()
     for p in probs:
         p.close()
+
+
+def test_batch_rejects_shared_vectors(csl):
+    shape = (15, 15)
+    probs = [csl.Problem(cuda(_coef(shape, 30 + j)), 5.0 + j, 2.0, dst="fft") for j in range(3)]
+    fs = [cuda(_crand(shape, 40 + j)) for j in range(3)]
+    zs = [torch.empty_like(f) for f in fs]
+    b = csl.Batch(probs, timeout_ms=30000)
+    for bad_z in ([zs[0], zs[0], zs[2]],      # two systems, one solution vector
+                  [zs[0], fs[0], zs[2]],      # a solution vector is another system's f
+                  [fs[0], zs[1], zs[2]]):     # f and z of one system alias
+        with pytest.raises(csl.CSLError, match="ERR_ARG"):
+            b.solve(fs, zs=bad_z)
+    out, infos = b.solve(fs, zs=zs)
+    assert all(i["status"] == 0 for i in infos)
+    b.close()
+    for p in probs:
+        p.close()
+
+
+def test_option_and_alias_checks(csl):
+    import ctypes
+    from paper_2408_00488_amd import _ptr, _stream
+    shape = (15, 15)
+    p = csl.Problem(cuda(_coef(shape, 50)), 5.0, 2.0, dst="fft")
+    f = cuda(_crand(shape, 51))
+    z, _ = csl.minres_solve(p, f)
+    L = csl.load_library()
+    # the adjoint's gradient in f must not overwrite the forward solution
+    st = L.minres_adjoint(p.handle, _ptr(z), _ptr(f), _ptr(z), None, None, None, None, None,
+                          _stream(p.device))
+    assert st == 1 and "alias" in L.csl_last_error().decode()
+    for bad in (dict(tol=float("nan")), dict(maxit=20000000)):
+        with pytest.raises(csl.CSLError, match="ERR_ARG"):
+            csl.minres_solve(p, f, **bad)
+        with pytest.raises(csl.CSLError, match="ERR_ARG"):
+            csl.minres_adjoint(p, z, f, **bad)
+        with pytest.raises(csl.CSLError, match="ERR_ARG"):
+            csl.Batch([p], **bad)
+    with pytest.raises(csl.CSLError, match="ERR_ARG"):
+        csl.Batch([p], grid_size=-1)
+    # nothing above changed the problem: the solve repeats bitwise
+    z2, _ = csl.minres_solve(p, f)
+    assert torch.equal(z, z2)
+    p.close()
