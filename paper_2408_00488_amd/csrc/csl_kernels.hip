@@ -413,7 +413,11 @@ template <typename R, int D, int LDSB, class E>
 __device__ __forceinline__ void tile_pinv(const SysDesc &S, int pass, const double2 *x, double2 *y, int tile,
                           char *smem) {
   Cx<R> *buf = reinterpret_cast<Cx<R> *>(smem);
-  Cx<R> *T = reinterpret_cast<Cx<R> *>(S.T);
+  // global views: the descriptor's generic pointer would compile to flat
+  // accesses, which also count against the LDS wait counter
+  CSL_G Cx<R> *T = gbl(reinterpret_cast<Cx<R> *>(S.T));
+  const CSL_G double2 *X = gbl(x);
+  CSL_G double2 *Y = gbl(y);
   // pass: 0 rows forward, 1 axis-1 forward, 2 axis-0 mid, 3 axis-1 inverse, 4 rows inverse
   const int ax = (pass == 0 || pass == 4) ? D - 1 : (pass == 2 ? 0 : 1);
   const int lp = (ax == D - 1) ? S.lpt_z : S.lpt_s[ax];
@@ -424,9 +428,9 @@ __device__ __forceinline__ void tile_pinv(const SysDesc &S, int pass, const doub
                                  : reinterpret_cast<const R *>(S.Wmf[ax]);
   // T is column-blocked: the row passes reach it in blocked order, the
   // strided passes through their tile addressing
-  if (pass == 0) E::template fill<4>(buf, t, [&](int, int, int p) { return to_cx<R>(x[p]); });
-  else if (pass == 4) E::template fill_blk<4>(buf, t, [&](int, int, int q) { return T[q]; });
-  else E::template fill<4>(buf, t, [&](int, int, int p) { return T[p]; });
+  if (pass == 0) E::template fill<4>(buf, t, [&](int, int, int p) { return to_cx<R>(ldg(X + p)); });
+  else if (pass == 4) E::template fill_blk<4>(buf, t, [&](int, int, int q) { return ldg(T + q); });
+  else E::template fill<4>(buf, t, [&](int, int, int p) { return ldg(T + p); });
   Cx<R> *o = E::transform(buf, t, twl, Wm);
   if (pass == 2) {
     const R ab = (sizeof(R) == 8) ? (R)S.abar : (R)S.abar_f;
@@ -455,14 +459,13 @@ __device__ __forceinline__ void tile_pinv(const SysDesc &S, int pass, const doub
       return (R)1 / sqrt(sh * sh + be * be);
     }, &o);
   }
+  // the next pass reads these in other workgroups: stream them past the L2
   if (pass == 4) {
-    E::store(o, t, [&](int, int, int p, Cx<R> v) {
-      y[p] = make_double2((double)v.x, (double)v.y);
-    });
+    E::store(o, t, [&](int, int, int p, Cx<R> v) { st_nt(Y + p, (double)v.x, (double)v.y); });
   } else if (pass == 0) {
-    E::store_blk(o, t, [&](int, int, int q, Cx<R> v) { T[q] = v; });
+    E::store_blk(o, t, [&](int, int, int q, Cx<R> v) { st_nt(T + q, v); });
   } else {
-    E::store(o, t, [&](int, int, int p, Cx<R> v) { T[p] = v; });
+    E::store(o, t, [&](int, int, int p, Cx<R> v) { st_nt(T + p, v); });
   }
 }
 
@@ -811,9 +814,11 @@ __global__ void init_kernel(const SysDesc *__restrict__ sys, int nsys, Glob *G) 
 // step, and the neighbours and faces along i2 come from the adjacent lanes.
 // The arithmetic is that of stencil_apply: the same face expressions, then
 // the sum over the axes in order.
-// Strips are numbered slab-major, then i1, then the i2 block, and each XCD
-// (workgroup b runs on XCD b mod 8) takes one eighth of that order, so the
-// strips at i1 +- 1 that a strip reads sit in the same L2.
+// Strips are numbered slab-major, then the i2 block, then i1, and each XCD
+// (workgroup b runs on XCD b mod 8) takes one eighth of that order: the
+// waves of a workgroup march over consecutive i1 rows of one block in step,
+// so half of the strips at i1 +- 1 that they read were just loaded by a
+// sibling wave, and the others sit in the same L2.
 __device__ __forceinline__ double harm_face(double lo, double hi, double h2) {
   return (2.0 * lo * hi / (lo + hi)) * h2;
 }
@@ -842,8 +847,9 @@ __global__ __launch_bounds__(NT) void apply_A_march3_kernel(const SysDesc *__res
   if (strip >= hi_s) return;                // whole waves leave together
   const int slab = strip / per_slab;
   const int rem = strip - slab * per_slab;
-  const int i1 = rem / xb;
-  const int i2 = (rem - i1 * xb) * 64 + lane;
+  const int blk = rem / n1;
+  const int i1 = rem - blk * n1;
+  const int i2 = blk * 64 + lane;
   const bool valid = i2 < n2;
   const int s0 = (int)((long long)n0 * slab / nslab);
   const int s1 = (int)((long long)n0 * (slab + 1) / nslab);
