@@ -814,11 +814,9 @@ __global__ void init_kernel(const SysDesc *__restrict__ sys, int nsys, Glob *G) 
 // step, and the neighbours and faces along i2 come from the adjacent lanes.
 // The arithmetic is that of stencil_apply: the same face expressions, then
 // the sum over the axes in order.
-// Strips are numbered slab-major, then the i2 block, then i1, and each XCD
-// (workgroup b runs on XCD b mod 8) takes one eighth of that order: the
-// waves of a workgroup march over consecutive i1 rows of one block in step,
-// so half of the strips at i1 +- 1 that they read were just loaded by a
-// sibling wave, and the others sit in the same L2.
+// Strips are numbered slab-major, then i1, then the i2 block, and each XCD
+// (workgroup b runs on XCD b mod 8) takes one eighth of that order, so the
+// strips at i1 +- 1 that a strip reads sit in the same L2.
 __device__ __forceinline__ double harm_face(double lo, double hi, double h2) {
   return (2.0 * lo * hi / (lo + hi)) * h2;
 }
@@ -847,9 +845,8 @@ __global__ __launch_bounds__(NT) void apply_A_march3_kernel(const SysDesc *__res
   if (strip >= hi_s) return;                // whole waves leave together
   const int slab = strip / per_slab;
   const int rem = strip - slab * per_slab;
-  const int blk = rem / n1;
-  const int i1 = rem - blk * n1;
-  const int i2 = blk * 64 + lane;
+  const int i1 = rem / xb;
+  const int i2 = (rem - i1 * xb) * 64 + lane;
   const bool valid = i2 < n2;
   const int s0 = (int)((long long)n0 * slab / nslab);
   const int s1 = (int)((long long)n0 * (slab + 1) / nslab);
