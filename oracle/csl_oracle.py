@@ -541,3 +541,93 @@ def theorem3_bounds(a_min, a_max, c0, alpha, beta):
     mt0 = math.sqrt(2.0) * (c0 * a_max + ab - alpha) / (c0 * gam + ab + alpha)
     mt1 = math.sqrt(2.0) * (c0 * a_min + ab + alpha) / (2.0 * (c0 * gam + ab - alpha))
     return min(1.0 / mu0, mt1), max(mu0, mt0)
+
+
+# --------------------------------------------------------------------------
+# The alpha-circulant all-at-once layer  (Section 1: evolutionary problems
+# whose time-stepping matrix is replaced by an alpha-circulant one become,
+# after block diagonalisation, one complex-shifted system per eigenvalue)
+#
+# Reading (the paper describes the setting, not its matrices): implicit Euler
+# with step tau for u' + K u = g over L steps gives the time factor
+# B = (I - Z_0)/tau, Z_0 the down-shift; the alpha-circulant factor is
+# C = (I - Z_alpha)/tau, where Z_alpha also carries alpha in its top-right
+# corner.  The time-space matrix is kron(C, I) + kron(I, K); a right-hand
+# side or solution is an array (L, *grid), step index first.
+# --------------------------------------------------------------------------
+
+
+def alpha_circulant(L, tau, alpha_c):
+    """Dense C = (I - Z_alpha)/tau."""
+    Z = np.zeros((L, L))
+    Z[np.arange(1, L), np.arange(L - 1)] = 1.0
+    Z[0, L - 1] = alpha_c
+    return (np.eye(L) - Z) / tau
+
+
+def alpha_circulant_shifts(L, tau, alpha_c):
+    """Eigenvalues of C in the order of the forward transform below:
+    D_j = (1 - alpha^(1/L) exp(-2 pi i j / L)) / tau, j = 0..L-1.  With
+    Gamma = diag(alpha^(k/L)), Gamma Z_alpha Gamma^-1 = alpha^(1/L) times the
+    cyclic shift, which the DFT F (exp(-2 pi i j k / L)) diagonalises."""
+    j = np.arange(L)
+    return (1.0 - alpha_c ** (1.0 / L) * np.exp(-2j * np.pi * j / L)) / tau
+
+
+def all_at_once_matrix(K, L, tau, alpha_c):
+    """kron(C, I_M) + kron(I_L, K), sparse complex (reference only)."""
+    M = K.shape[0]
+    C = sp.csr_matrix(alpha_circulant(L, tau, alpha_c))
+    return (sp.kron(C, sp.identity(M)) + sp.kron(sp.identity(L), K)).tocsc().astype(np.complex128)
+
+
+def paradiag_forward(R, alpha_c):
+    """(F Gamma (x) I) R: step k scaled by alpha^(k/L), then the DFT over steps."""
+    R = np.asarray(R, dtype=np.complex128)
+    L = R.shape[0]
+    g = alpha_c ** (np.arange(L) / L)
+    return np.fft.fft(R * g.reshape((L,) + (1,) * (R.ndim - 1)), axis=0)
+
+
+def paradiag_inverse(U, alpha_c):
+    """(Gamma^-1 F^-1 (x) I) U: inverse DFT over steps, then alpha^(-k/L)."""
+    U = np.asarray(U, dtype=np.complex128)
+    L = U.shape[0]
+    g = alpha_c ** (-np.arange(L) / L)
+    return np.fft.ifft(U, axis=0) * g.reshape((L,) + (1,) * (U.ndim - 1))
+
+
+def paradiag_solve(a, L, tau, alpha_c, R, direct=True, tol=1e-8, maxit=1000,
+                   abar_rule="mean", lengths=None):
+    """Solve (kron(C, I) + kron(I, K)) U = R through the diagonalisation:
+    transform R, solve (K + D_j I) Ut_j = Rt_j for every step mode j (a direct
+    solve, or MINRES with the averaged preconditioner), transform back.
+    Returns (U, infos) with one info dict per mode (None for direct)."""
+    D = alpha_circulant_shifts(L, tau, alpha_c)
+    Rt = paradiag_forward(R, alpha_c)
+    Ut = np.empty_like(Rt)
+    infos = []
+    for j in range(L):
+        prob = Problem(a, D[j].real, D[j].imag, abar_rule=abar_rule, lengths=lengths)
+        if direct:
+            Ut[j] = prob.direct(Rt[j])
+            infos.append(None)
+        else:
+            Ut[j], info = prob.solve(Rt[j], tol=tol, maxit=maxit)
+            infos.append(info)
+    return paradiag_inverse(Ut, alpha_c), infos
+
+
+def implicit_euler(a, L, tau, R, lengths=None):
+    """Step-by-step implicit Euler for u' + K u = g from u_0 = 0:
+    (I/tau + K) u_k = u_{k-1}/tau + g_k, with R[k] = g_k; the system that
+    the alpha-circulant factor approximates (reference only)."""
+    K = build_K(np.asarray(a, dtype=np.float64), lengths)
+    M = K.shape[0]
+    Ak = (K + sp.identity(M) / tau).tocsc().astype(np.complex128)
+    U = np.empty((L,) + np.shape(a), dtype=np.complex128)
+    prev = np.zeros(M, dtype=np.complex128)
+    for k in range(L):
+        prev = spla.spsolve(Ak, prev / tau + np.ravel(R[k]))
+        U[k] = prev.reshape(np.shape(a))
+    return U

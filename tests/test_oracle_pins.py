@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 import scipy.linalg as sla
 import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 from oracle import csl_oracle as O
 from paper_2408_00488_amd import workloads as WL
@@ -440,3 +441,62 @@ def test_adjoint_minres_matches_direct():
     y_it, info = O.adjoint_solve(prob, G, tol=1e-12)
     y_d, _ = O.adjoint_solve(prob, G, direct=True)
     assert np.linalg.norm(y_it - y_d) / np.linalg.norm(y_d) < 1e-10
+
+
+# ---- the alpha-circulant all-at-once layer --------------------------------
+
+@pytest.mark.parametrize("L,alpha_c", [(8, 0.1), (16, 1e-2), (8, 1.0)])
+def test_alpha_circulant_shifts_are_its_eigenvalues(L, alpha_c):
+    tau = 0.05
+    C = O.alpha_circulant(L, tau, alpha_c)
+    D = O.alpha_circulant_shifts(L, tau, alpha_c)
+    ev = np.linalg.eigvals(C)
+    scale = np.abs(D).max()
+    # every closed-form shift is an eigenvalue, and they are L distinct ones
+    assert max(np.abs(ev - d).min() for d in D) <= 1e-12 * scale
+    assert min(abs(D[i] - D[j]) for i in range(L) for j in range(i)) > 1e-6 * scale
+
+
+@pytest.mark.parametrize("alpha_c", [0.1, 1e-3])
+def test_paradiag_transforms_diagonalise_the_alpha_circulant(alpha_c):
+    # inverse(D * forward(X)) = C X fixes the order of the shifts, the sign of
+    # the DFT and the direction of the alpha^(k/L) scaling
+    L, tau = 16, 0.02
+    C = O.alpha_circulant(L, tau, alpha_c)
+    D = O.alpha_circulant_shifts(L, tau, alpha_c)
+    X = _crand((L, 5), 11)
+    Y = O.paradiag_inverse(D[:, None] * O.paradiag_forward(X, alpha_c), alpha_c)
+    assert np.abs(Y - C @ X).max() <= 1e-10 * np.abs(C @ X).max()
+    # forward and inverse are each other's inverse
+    assert np.abs(O.paradiag_inverse(O.paradiag_forward(X, alpha_c), alpha_c) - X).max() <= 1e-12
+
+
+@pytest.mark.parametrize("shape", [(7, 7), (7, 3, 7)])
+def test_paradiag_solve_matches_all_at_once_direct_solve(shape):
+    L, tau, alpha_c = 8, 0.1, 0.1
+    a = np.random.default_rng(3).uniform(0.5, 2.0, shape)
+    R = _crand((L,) + shape, 4)
+    U, _ = O.paradiag_solve(a, L, tau, alpha_c, R)
+    A = O.all_at_once_matrix(O.build_K(a), L, tau, alpha_c)
+    Ud = spla.spsolve(A, R.ravel()).reshape(R.shape)
+    assert np.linalg.norm(U - Ud) <= 1e-11 * np.linalg.norm(Ud)
+    # with MINRES on each mode (tol 1e-10) the result stays within the
+    # modes' tolerance times the conditioning of the alpha scaling
+    Um, infos = O.paradiag_solve(a, L, tau, alpha_c, R, direct=False, tol=1e-10)
+    assert all(i["status"] == O.STATUS_OK for i in infos)
+    assert np.linalg.norm(Um - Ud) <= 1e-8 * np.linalg.norm(Ud)
+
+
+def test_paradiag_small_alpha_approaches_implicit_euler():
+    # alpha -> 0 turns the alpha-circulant factor into implicit Euler's
+    # bidiagonal one: the all-at-once solution approaches the step-by-step
+    # solution at O(alpha)
+    L, tau, n = 8, 0.1, 7
+    a = np.random.default_rng(3).uniform(0.5, 2.0, (n, n))
+    R = _crand((L, n, n), 6)
+    Ue = O.implicit_euler(a, L, tau, R)
+    errs = []
+    for alpha_c in (1e-3, 1e-5):
+        U, _ = O.paradiag_solve(a, L, tau, alpha_c, R)
+        errs.append(np.linalg.norm(U - Ue) / np.linalg.norm(Ue))
+    assert errs[1] <= 1e-4 and errs[1] < errs[0] / 50, errs
