@@ -64,6 +64,7 @@ typedef enum csl_status {
 
 typedef struct csl_problem_s *csl_problem;
 typedef struct csl_batch_s *csl_batch;
+typedef struct csl_paradiag_s *csl_paradiag;
 
 /* Grid of the rectangular domain (Section 1): dim in {2, 3}; n[k] interior
  * points along axis k (axis dim-1 contiguous); length[k] > 0 the side
@@ -273,6 +274,53 @@ csl_status problem_schedule(csl_problem p, csl_batch_tuning *out);
 csl_status batch_schedule(csl_batch b, csl_batch_tuning *out);
 
 csl_status batch_destroy(csl_batch b);
+
+/* ---- The alpha-circulant all-at-once layer (Section 1) ------------------
+ * The setting the paper's introduction gives for complex-shifted systems:
+ * implicit Euler with step tau for u' + K u = g over L steps, with the
+ * bidiagonal time factor (I - Z)/tau replaced by the alpha-circulant
+ * C = (I - Z_alpha)/tau (Z_alpha: the down-shift with alpha in its
+ * top-right corner).  paradiag_solve applies (kron(C, I) + kron(I, K))^-1:
+ *   Rt = (F Gamma (x) I) r,  Gamma = diag(alpha^(k/L)), F the DFT over steps;
+ *   (K + D_j I) Ut_j = Rt_j for every mode j, one batched persistent solve,
+ *     D_j = (1 - alpha^(1/L) exp(-2 pi i j / L)) / tau;
+ *   u = (Gamma^-1 F^-1 (x) I) Ut.
+ * All-at-once vectors are DEVICE arrays of L * M complex values, step-major
+ * (step k occupies entries [k M, (k + 1) M), each in the grid layout above). */
+
+/* Create the layer: one problem per mode (shift D_j; grid, coefficient and
+ * popts as create_problem, which each of them copies) and one batch over
+ * them (bopts as batch_create; NULL for the defaults), plus two all-at-once
+ * work vectors.  steps = L, a power of two in [8, 1024]; tau > 0;
+ * 0 < alpha_c <= 1.  Synchronises s. */
+csl_status paradiag_create(const csl_grid *grid, const double *a_nodal, int steps, double tau,
+                           double alpha_c, const csl_problem_opts *popts,
+                           const csl_batch_opts *bopts, hipStream_t s, csl_paradiag *out);
+
+/* Shift D_j = alpha + i beta of mode j (host). */
+csl_status paradiag_shift(csl_paradiag pd, int j, double *alpha, double *beta);
+
+/* The step transform alone: y = (F Gamma (x) I) x (inverse = 0) or
+ * y = (Gamma^-1 F^-1 (x) I) x (inverse = 1).  x, y: device, L * M complex,
+ * must not alias. */
+csl_status paradiag_transform(csl_paradiag pd, const double *x, double *y, int inverse,
+                              hipStream_t s);
+
+/* u = (kron(C, I) + kron(I, K))^-1 r.  r, u: device, L * M complex, must
+ * not alias.  infos: NULL, or a host array of L solve records (mode j in
+ * infos[j]); with infos the call synchronises s and returns CSL_OK only if
+ * every mode converged (u is written in any case). */
+csl_status paradiag_solve(csl_paradiag pd, const double *r, double *u, csl_solve_info *infos,
+                          hipStream_t s);
+
+/* Autotuner of the mode batch (batch_tune) on the modes of the right-hand
+ * side r (device, L * M complex).  Blocks until done; out may be NULL. */
+csl_status paradiag_tune(csl_paradiag pd, const double *r, csl_batch_tuning *out, hipStream_t s);
+
+/* The batch over the modes, owned by pd (for batch_schedule). */
+csl_status paradiag_batch(csl_paradiag pd, csl_batch *out);
+
+csl_status paradiag_destroy(csl_paradiag pd);
 
 /* Thread-local message describing the last non-OK status of this thread. */
 const char *csl_last_error(void);

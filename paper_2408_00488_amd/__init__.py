@@ -122,13 +122,24 @@ def load_library():
     L.batch_destroy.argtypes = [vp]
     L.batch_tune.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp),
                              ctypes.POINTER(_BatchTuning), vp]
+    L.paradiag_create.argtypes = [ctypes.POINTER(_Grid), vp, ip, ctypes.c_double,
+                                  ctypes.c_double, ctypes.POINTER(_ProblemOpts),
+                                  ctypes.POINTER(_BatchOpts), vp, ctypes.POINTER(vp)]
+    L.paradiag_shift.argtypes = [vp, ip, dp, dp]
+    L.paradiag_transform.argtypes = [vp, vp, vp, ip, vp]
+    L.paradiag_solve.argtypes = [vp, vp, vp, ctypes.POINTER(_SolveInfo), vp]
+    L.paradiag_tune.argtypes = [vp, vp, ctypes.POINTER(_BatchTuning), vp]
+    L.paradiag_batch.argtypes = [vp, ctypes.POINTER(vp)]
+    L.paradiag_destroy.argtypes = [vp]
     L.csl_last_error.restype = ctypes.c_char_p
     L.csl_version.restype = ctypes.c_int
     for fn in ("create_problem", "destroy_problem", "problem_info", "problem_dst_engines",
                "problem_set_schedule", "problem_tune", "problem_schedule", "batch_schedule",
                "apply_A", "apply_Pinv",
                "minres_solve", "minres_adjoint", "batch_create", "batch_solve",
-               "batch_tune", "batch_destroy"):
+               "batch_tune", "batch_destroy", "paradiag_create", "paradiag_shift",
+               "paradiag_transform", "paradiag_solve", "paradiag_tune", "paradiag_batch",
+               "paradiag_destroy"):
         getattr(L, fn).restype = ctypes.c_int
     _lib = L
     return L
@@ -419,6 +430,119 @@ class Batch:
         """Schedule in use for this batch."""
         t = _BatchTuning()
         _check(load_library().batch_schedule(self._h, ctypes.byref(t)))
+        return _tuning_dict(t)
+
+
+class ParaDiag:
+    """All-at-once solve of implicit Euler (step tau, L steps) for u' + K u = g
+    with the alpha-circulant time factor: u = (kron(C, I) + kron(I, K))^-1 r
+    through the step transform and one batched solve of the L shifted
+    systems (see paradiag_create).  All-at-once vectors are complex128 CUDA
+    tensors of shape (L,) + grid shape."""
+
+    def __init__(self, a, steps: int, tau: float, alpha_c: float, lengths=None,
+                 abar_rule: str = "mean", pinv_fp32: bool = False, dst: str = "auto",
+                 tol=1e-8, maxit=1000, check_true=True, timeout_ms=0, use_graph=True,
+                 tile_points=0, lds_bytes=0, block_threads=0):
+        torch = _torch()
+        if not (isinstance(a, torch.Tensor) and a.is_cuda and a.dtype == torch.float64):
+            raise TypeError("a must be a float64 CUDA tensor")
+        if a.dim() not in (2, 3):
+            raise ValueError("a must be 2-D or 3-D")
+        self.a = a.contiguous()
+        self.shape = tuple(self.a.shape)
+        self.device = self.a.device
+        self.steps = int(steps)
+        g = _Grid()
+        g.dim = self.a.dim()
+        for k in range(3):
+            g.n[k] = self.shape[k] if k < g.dim else 0
+            g.length[k] = float(lengths[k]) if (lengths is not None and k < g.dim) else 1.0
+        po = _ProblemOpts()
+        po.abar_rule = _ABAR[abar_rule]
+        po.pinv_prec = 1 if pinv_fp32 else 0
+        po.dst_engine = _DST[dst]
+        bo = _BatchOpts()
+        bo.tol = float(tol)
+        bo.maxit = int(maxit)
+        bo.check_true_residual = 1 if check_true else 0
+        bo.timeout_ms = int(timeout_ms)
+        bo.use_graph = 1 if use_graph else 0
+        bo.tile_points = int(tile_points)
+        bo.lds_bytes = int(lds_bytes)
+        bo.block_threads = int(block_threads)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(load_library().paradiag_create(
+                ctypes.byref(g), _ptr(self.a), self.steps, float(tau), float(alpha_c),
+                ctypes.byref(po), ctypes.byref(bo), _stream(self.device), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            load_library().paradiag_destroy(self._h)
+            self._h = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _vec(self, x, name):
+        torch = _torch()
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.complex128
+                and x.is_contiguous() and x.device == self.device
+                and tuple(x.shape) == (self.steps,) + self.shape):
+            raise ValueError(f"{name} must be a contiguous complex128 CUDA tensor of shape "
+                             f"{(self.steps,) + self.shape} on {self.device}")
+
+    @property
+    def shifts(self) -> list:
+        out = []
+        for j in range(self.steps):
+            re, im = ctypes.c_double(), ctypes.c_double()
+            _check(load_library().paradiag_shift(self._h, j, ctypes.byref(re), ctypes.byref(im)))
+            out.append(complex(re.value, im.value))
+        return out
+
+    def transform(self, x, y=None, inverse=False):
+        torch = _torch()
+        self._vec(x, "x")
+        if y is None:
+            y = torch.empty_like(x)
+        self._vec(y, "y")
+        _check(load_library().paradiag_transform(self._h, _ptr(x), _ptr(y), 1 if inverse else 0,
+                                                 _stream(self.device)))
+        return y
+
+    def solve(self, r, u=None, want_info=True, raise_on_error=True):
+        torch = _torch()
+        self._vec(r, "r")
+        if u is None:
+            u = torch.empty_like(r)
+        self._vec(u, "u")
+        infos = (_SolveInfo * self.steps)()
+        st = load_library().paradiag_solve(self._h, _ptr(r), _ptr(u),
+                                           infos if want_info else None, _stream(self.device))
+        d = [_info_dict(i) for i in infos] if want_info else None
+        if raise_on_error and st != 0:
+            _check(st, d)
+        return u, d
+
+    def tune(self, r) -> dict:
+        self._vec(r, "r")
+        t = _BatchTuning()
+        _check(load_library().paradiag_tune(self._h, _ptr(r), ctypes.byref(t),
+                                            _stream(self.device)))
+        return _tuning_dict(t)
+
+    @property
+    def schedule(self) -> dict:
+        b = ctypes.c_void_p()
+        _check(load_library().paradiag_batch(self._h, ctypes.byref(b)))
+        t = _BatchTuning()
+        _check(load_library().batch_schedule(b, ctypes.byref(t)))
         return _tuning_dict(t)
 
 

@@ -1052,6 +1052,66 @@ __global__ __launch_bounds__(NT) void conj_kernel(const double2 *__restrict__ x,
 }
 
 // ---------------------------------------------------------------------------
+// Transform over the L = 2^lg steps of an all-at-once vector (L vectors of M
+// complex values, step-major) that block-diagonalises the alpha-circulant
+// time factor:
+//   forward: y_j = sum_k exp(-2 pi i j k / L) alpha^(k/L) x_k
+//   inverse: y_k = alpha^(-k/L) / L sum_j exp(2 pi i j k / L) x_j
+// (the inverse as the conjugate of the forward DFT of the conjugate).  A
+// workgroup takes P = MAXE / L consecutive grid points, reads their L values
+// step by step (P consecutive points per step: coalesced), transforms the P
+// lines of length L in LDS and writes them back the same way.  ln_alpha_l is
+// ln(alpha) / L.
+// ---------------------------------------------------------------------------
+template <int LDSB>
+__global__ __launch_bounds__(NT) void step_transform_kernel(const double2 *__restrict__ x,
+                                                            double2 *__restrict__ y, int M,
+                                                            int lg, double ln_alpha_l,
+                                                            int inverse) {
+  extern __shared__ __align__(16) char smem[];
+  constexpr int MAXE = MaxElts<double, LDSB>::value;
+  Cx<double> *buf = reinterpret_cast<Cx<double> *>(smem);
+  Cx<double> *twl = reinterpret_cast<Cx<double> *>(smem + LDSB);
+  const int L = 1 << lg;
+  const int lgp = ilog2i(MAXE) - lg;   // log2 of the points per workgroup
+  const int P = 1 << lgp;
+  const long long p0 = (long long)blockIdx.x * P;
+  const CSL_G double2 *__restrict__ X = gbl(x);
+  CSL_G double2 *__restrict__ Y = gbl(y);
+  load_twiddles<double>(twl, lg);
+  for (int e = threadIdx.x; e < L * P; e += NT) {
+    const int k = e >> lgp, pl = e & (P - 1);
+    const long long p = p0 + pl;
+    Cx<double> v = {0.0, 0.0};
+    if (p < M) {
+      const double2 u = ldg(X + (long long)k * M + p);
+      if (inverse) {
+        v = {u.x, -u.y};
+      } else {
+        const double g = exp(ln_alpha_l * k);
+        v = {u.x * g, u.y * g};
+      }
+    }
+    buf[pl * L + k] = v;
+  }
+  __syncthreads();
+  fft_lines<double, LDSB>(buf, P, lg, twl);
+  for (int e = threadIdx.x; e < L * P; e += NT) {
+    const int k = e >> lgp, pl = e & (P - 1);
+    const long long p = p0 + pl;
+    if (p < M) {
+      const Cx<double> v = buf[pl * L + k];
+      if (inverse) {
+        const double g = exp(-ln_alpha_l * k) / L;
+        st_nt(Y + (long long)k * M + p, v.x * g, -v.y * g);
+      } else {
+        st_nt(Y + (long long)k * M + p, v.x, v.y);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Coefficient set-up: sum of the nodal samples, min / max over all face
 // coefficients (harmonic means inside, a_p on boundary faces), and a count
 // of samples that are not finite and positive.
@@ -1244,6 +1304,17 @@ hipError_t launch_adjoint(const SysDesc *dsys, int d, int M, const double2 *ytil
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(adjoint_final_kernel, dim3(1), dim3(NT), 0, s, part, nblk, galpha, gbeta);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_transform(const double2 *x, double2 *y, int M, int lg, double alpha_c,
+                                 int inverse, hipStream_t s) {
+  constexpr int LDSB = 32768;
+  const int P = MaxElts<double, LDSB>::value >> lg;
+  const long long nblk = ((long long)M + P - 1) / P;
+  hipLaunchKernelGGL(step_transform_kernel<LDSB>, dim3((unsigned)nblk), dim3(NT),
+                     LDSB + tw_lds_bytes(LDSB), s, x, y, M, lg, log(alpha_c) / (1 << lg),
+                     inverse);
   return hipGetLastError();
 }
 

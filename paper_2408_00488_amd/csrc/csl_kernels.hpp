@@ -27,6 +27,11 @@ hipError_t launch_adjoint(const SysDesc *dsys, int d, int M, const double2 *ytil
                           const double2 *z, double2 *gf, double *ga, double *part, int nblk,
                           double *galpha, double *gbeta, hipStream_t s);
 hipError_t launch_conj(const double2 *x, double2 *y, int M, hipStream_t s);
+// Step transform of an all-at-once vector (L = 2^lg steps of M points, 8 <= L
+// <= 1024): forward = DFT over the steps after the alpha^(k/L) scaling,
+// inverse = its inverse.
+hipError_t launch_step_transform(const double2 *x, double2 *y, int M, int lg, double alpha_c,
+                                 int inverse, hipStream_t s);
 hipError_t launch_coef_stats(const SysDesc *dsys, int d, int M, double *part, int nblk,
                              double *out, hipStream_t s);
 

@@ -178,6 +178,20 @@ struct csl_batch_s {
   bool all2d = true;     // every problem is 2-D (the 2-D-only 512-thread instance)
 };
 
+struct csl_paradiag_s {
+  int device = 0;
+  int L = 0, lg = 0;
+  int M = 0;
+  double tau = 0.0, alpha_c = 0.0;
+  std::vector<csl_problem> probs;   // mode j: shift D_j
+  std::vector<double> dre, dim;     // D_j
+  csl_batch batch = nullptr;
+  void *mem = nullptr;              // Rt, Ut: L * M complex each
+  double2 *rt = nullptr, *ut = nullptr;
+  std::vector<const double *> fptr; // per-mode slices of rt / ut
+  std::vector<double *> zptr;
+};
+
 namespace {
 
 SolveParams make_params(double tol, int maxit, int check_true, int timeout_ms, double wall_khz) {
@@ -1173,6 +1187,118 @@ csl_status batch_schedule(csl_batch b, csl_batch_tuning *out) {
   out->lds_bytes = b->lds_bytes;
   out->grid_size = b->grid;
   out->block_threads = b->block_threads;
+  return CSL_OK;
+}
+
+static void free_paradiag(csl_paradiag pd) {
+  if (!pd) return;
+  if (pd->batch) (void)batch_destroy(pd->batch);
+  for (csl_problem p : pd->probs) free_problem(p);
+  if (pd->mem) (void)hipFree(pd->mem);
+  delete pd;
+}
+
+csl_status paradiag_create(const csl_grid *grid, const double *a_nodal, int steps, double tau,
+                           double alpha_c, const csl_problem_opts *popts,
+                           const csl_batch_opts *bopts, hipStream_t s, csl_paradiag *out) {
+  if (!out) return fail(CSL_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (steps < 8 || steps > 1024 || (steps & (steps - 1)) != 0)
+    return fail(CSL_ERR_ARG, "steps must be a power of two between 8 and 1024");
+  if (!(tau > 0.0) || !std::isfinite(tau)) return fail(CSL_ERR_ARG, "tau must be finite and > 0");
+  if (!(alpha_c > 0.0 && alpha_c <= 1.0)) return fail(CSL_ERR_ARG, "alpha_c must be in (0, 1]");
+  csl_paradiag pd = new csl_paradiag_s();
+  pd->L = steps;
+  pd->lg = ilog2(steps);
+  pd->tau = tau;
+  pd->alpha_c = alpha_c;
+  const double r = std::pow(alpha_c, 1.0 / steps);
+  for (int j = 0; j < steps; ++j) {
+    // D_j = (1 - alpha^(1/L) exp(-2 pi i j / L)) / tau
+    const double th = 2.0 * M_PI * j / steps;
+    const double re = (1.0 - r * std::cos(th)) / tau, im = r * std::sin(th) / tau;
+    pd->dre.push_back(re);
+    pd->dim.push_back(im);
+    csl_problem p = nullptr;
+    const csl_status st = create_problem(grid, a_nodal, re, im, popts, s, &p);
+    if (st != CSL_OK) {
+      const std::string msg = g_err;
+      free_paradiag(pd);
+      return fail(st, "paradiag mode " + std::to_string(j) + ": " + msg);
+    }
+    pd->probs.push_back(p);
+  }
+  pd->device = pd->probs[0]->device;
+  pd->M = pd->probs[0]->h.M;
+  const size_t vec = align256(sizeof(double2) * (size_t)pd->M * steps);
+  hipError_t e = hipMalloc(&pd->mem, 2 * vec);
+  if (e != hipSuccess) {
+    free_paradiag(pd);
+    return fail(CSL_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  pd->rt = (double2 *)pd->mem;
+  pd->ut = (double2 *)((char *)pd->mem + vec);
+  for (int j = 0; j < steps; ++j) {
+    pd->fptr.push_back((const double *)(pd->rt + (size_t)j * pd->M));
+    pd->zptr.push_back((double *)(pd->ut + (size_t)j * pd->M));
+  }
+  const csl_status st = batch_create(pd->probs.data(), steps, bopts, &pd->batch);
+  if (st != CSL_OK) {
+    const std::string msg = g_err;
+    free_paradiag(pd);
+    return fail(st, msg);
+  }
+  *out = pd;
+  return CSL_OK;
+}
+
+csl_status paradiag_shift(csl_paradiag pd, int j, double *alpha, double *beta) {
+  if (!pd || !alpha || !beta) return fail(CSL_ERR_ARG, "NULL argument");
+  if (j < 0 || j >= pd->L) return fail(CSL_ERR_ARG, "mode index out of range");
+  *alpha = pd->dre[j];
+  *beta = pd->dim[j];
+  return CSL_OK;
+}
+
+csl_status paradiag_transform(csl_paradiag pd, const double *x, double *y, int inverse,
+                              hipStream_t s) {
+  if (!pd || !x || !y) return fail(CSL_ERR_ARG, "NULL argument");
+  if (x == y) return fail(CSL_ERR_ARG, "paradiag_transform: x and y must not alias");
+  HIPCHK(wg256::launch_step_transform((const double2 *)x, (double2 *)y, pd->M, pd->lg,
+                                      pd->alpha_c, inverse ? 1 : 0, s));
+  return CSL_OK;
+}
+
+csl_status paradiag_solve(csl_paradiag pd, const double *r, double *u, csl_solve_info *infos,
+                          hipStream_t s) {
+  if (!pd || !r || !u) return fail(CSL_ERR_ARG, "NULL argument");
+  if (r == u) return fail(CSL_ERR_ARG, "paradiag_solve: r and u must not alias");
+  HIPCHK(wg256::launch_step_transform((const double2 *)r, pd->rt, pd->M, pd->lg, pd->alpha_c, 0, s));
+  const csl_status st = batch_solve(pd->batch, pd->fptr.data(), pd->zptr.data(), infos, s);
+  if (st != CSL_OK && st != CSL_ERR_NOT_CONVERGED && st != CSL_ERR_BREAKDOWN &&
+      st != CSL_ERR_NONFINITE && st != CSL_ERR_TIMEOUT)
+    return st;
+  const std::string msg = g_err;
+  HIPCHK(wg256::launch_step_transform(pd->ut, (double2 *)u, pd->M, pd->lg, pd->alpha_c, 1, s));
+  if (st != CSL_OK) g_err = msg;
+  return st;
+}
+
+csl_status paradiag_tune(csl_paradiag pd, const double *r, csl_batch_tuning *out, hipStream_t s) {
+  if (!pd || !r) return fail(CSL_ERR_ARG, "NULL argument");
+  HIPCHK(wg256::launch_step_transform((const double2 *)r, pd->rt, pd->M, pd->lg, pd->alpha_c, 0, s));
+  return batch_tune(pd->batch, pd->fptr.data(), pd->zptr.data(), out, s);
+}
+
+csl_status paradiag_batch(csl_paradiag pd, csl_batch *out) {
+  if (!pd || !out) return fail(CSL_ERR_ARG, "NULL argument");
+  *out = pd->batch;
+  return CSL_OK;
+}
+
+csl_status paradiag_destroy(csl_paradiag pd) {
+  if (!pd) return fail(CSL_ERR_ARG, "paradiag is NULL");
+  free_paradiag(pd);
   return CSL_OK;
 }
 
