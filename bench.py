@@ -207,6 +207,53 @@ def other_configs(C, WL, dev):
     out["c5_adjoint"] = {"systems": len(w.systems), "points_each": int(w.systems[0].a.size),
                          "ms_forward_plus_adjoint_all": (time.perf_counter() - t0) * 1e3,
                          "max_relres": worst}
+    out["paradiag"] = paradiag_config(C, WL, dev)
+    return out
+
+
+def paradiag_config(C, WL, dev, n=255, steps=64, tau=1.0 / 64, alpha_c=1e-2):
+    """The alpha-circulant all-at-once layer: 64 implicit-Euler steps on a
+    2-D n = 255 grid (a as c1, FP32 preconditioner, tol 1e-8): one solve =
+    step transform, batched solve of the 64 shifted systems, inverse
+    transform.  The step transform's rate is from HIP events around 20
+    forward + inverse pairs (32 bytes per point and step each)."""
+    import torch
+    a = torch.from_numpy(WL.coef_c1(n)).to(dev)
+    R = torch.from_numpy(WL.complex_normal(WL.rng(6), (steps, n, n))).to(dev)
+    pd = C.ParaDiag(a, steps, tau, alpha_c, pinv_fp32=True)
+    sched = pd.tune(R)
+    U = torch.empty_like(R)
+    _, infos = pd.solve(R, U)
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        pd.solve(R, U, want_info=False)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    Y = torch.empty_like(R)
+    pd.transform(R, Y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        pd.transform(R, Y)
+        pd.transform(Y, U, inverse=True)
+    e1.record()
+    torch.cuda.synchronize()
+    tms = e0.elapsed_time(e1) / 40
+    M = n * n
+    its = [i["iters"] for i in infos]
+    out = {"steps": steps, "points_per_step": M, "tau": tau, "alpha_c": alpha_c,
+           "ms_per_all_at_once_solve": ms, "mode_solves_per_s": steps / ms * 1e3,
+           "iters_min": min(its), "iters_max": max(its),
+           "all_converged": all(i["status"] == 0 for i in infos),
+           "max_relres_true": max(i["relres_true"] for i in infos),
+           "step_transform_ms": tms,
+           "step_transform_GBps": steps * M * 32.0 / tms / 1e6,
+           "step_transform_frac_of_8TBps": steps * M * 32.0 / tms / 1e6 / 8000.0,
+           "schedule": {"tile_points": sched["tile_points"], "lds_bytes": sched["lds_bytes"],
+                        "block_threads": sched["block_threads"]}}
+    pd.close()
     return out
 
 

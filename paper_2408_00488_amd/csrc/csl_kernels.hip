@@ -1079,24 +1079,34 @@ __global__ __launch_bounds__(NT) void step_transform_kernel(const double2 *__res
   const CSL_G double2 *__restrict__ X = gbl(x);
   CSL_G double2 *__restrict__ Y = gbl(y);
   load_twiddles<double>(twl, lg);
-  for (int e = threadIdx.x; e < L * P; e += NT) {
+  // L P = MAXE: every thread moves MAXE / NT values each way; all loads are
+  // issued before the first LDS write
+  constexpr int U = MAXE / NT;
+  double2 u[U];
+#pragma unroll
+  for (int i = 0; i < U; ++i) {
+    const int e = threadIdx.x + i * NT;
+    const long long p = p0 + (e & (P - 1));
+    u[i] = p < M ? ldg(X + (long long)(e >> lgp) * M + p) : make_double2(0.0, 0.0);
+  }
+#pragma unroll
+  for (int i = 0; i < U; ++i) {
+    const int e = threadIdx.x + i * NT;
     const int k = e >> lgp, pl = e & (P - 1);
-    const long long p = p0 + pl;
-    Cx<double> v = {0.0, 0.0};
-    if (p < M) {
-      const double2 u = ldg(X + (long long)k * M + p);
-      if (inverse) {
-        v = {u.x, -u.y};
-      } else {
-        const double g = exp(ln_alpha_l * k);
-        v = {u.x * g, u.y * g};
-      }
+    Cx<double> v;
+    if (inverse) {
+      v = {u[i].x, -u[i].y};
+    } else {
+      const double g = exp(ln_alpha_l * k);
+      v = {u[i].x * g, u[i].y * g};
     }
     buf[pl * L + k] = v;
   }
   __syncthreads();
   fft_lines<double, LDSB>(buf, P, lg, twl);
-  for (int e = threadIdx.x; e < L * P; e += NT) {
+#pragma unroll
+  for (int i = 0; i < U; ++i) {
+    const int e = threadIdx.x + i * NT;
     const int k = e >> lgp, pl = e & (P - 1);
     const long long p = p0 + pl;
     if (p < M) {
