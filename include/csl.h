@@ -21,8 +21,10 @@
  * interior grid node in C order (last axis contiguous).  The real block
  * vector [x1; x2] is stored as x1 + i x2.  The nodal coefficient is a DEVICE
  * array of M doubles in the same order.  Grid axis k has n[k] interior
- * points with n[k] + 1 a power of two, 4 <= n[k] + 1 <= 1024 (n in
- * {3, 7, ..., 1023}), mesh width h_k = length[k] / (n[k] + 1).
+ * points, mesh width h_k = length[k] / (n[k] + 1): n[k] + 1 a power of two
+ * with 4 <= n[k] + 1 <= 1024 (n in {3, 7, ..., 1023}; the sine transform
+ * along the axis by the LDS FFT or the dense sine matrix), or any
+ * 3 <= n[k] <= 127 (the dense sine matrix on the matrix cores only).
  *
  * Ownership.  The caller owns every vector and coefficient buffer and keeps
  * it alive while work that uses it is queued.  A problem handle owns a copy
@@ -95,11 +97,15 @@ enum {
 enum {
     CSL_DST_AUTO = 0,       /* per axis, the faster of FFT and GEMM, timed on
                                this device the first time a grid shape and
-                               precision is seen in the process            */
-    CSL_DST_FFT = 1,        /* FFT of the odd extension, staged in LDS      */
+                               precision is seen in the process (GEMM on
+                               every axis with n + 1 not a power of two)   */
+    CSL_DST_FFT = 1,        /* FFT of the odd extension, staged in LDS
+                               (CSL_ERR_ARG if an axis has n + 1 not a
+                               power of two)                               */
     CSL_DST_GEMM = 2        /* product with the dense n x n sine matrix on
                                the matrix cores, for axes with
-                               15 <= n <= 127; FFT on the other axes        */
+                               15 <= n <= 127 or n + 1 not a power of two;
+                               FFT on the other axes                       */
 };
 
 typedef struct csl_problem_opts {

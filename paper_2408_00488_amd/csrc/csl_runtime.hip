@@ -73,11 +73,18 @@ int ilog2(int v) {
 }
 
 // Axes whose sine transform may run as a dense matrix product on the matrix
-// cores: the padded length np = n + 1 keeps the two LDS operands of a chunk
-// (2 lp np elements) inside the FFT's lp L budget, L = 2(n + 1), and
-// n <= 127 keeps the n^2 products per line within reach of the FFT's cost.
-bool gemm_eligible(int n) { return n >= 15 && n <= 127; }
+// cores: n <= 127 keeps the n^2 products per line within reach of the FFT's
+// cost.  With n + 1 a power of two (n >= 15) the padded length np = n + 1
+// keeps the two LDS operands of a chunk (2 lp np elements) inside the FFT's
+// lp L budget, L = 2(n + 1).  An axis with n + 1 not a power of two has no
+// FFT here and must take the matrix product (3 <= n <= 127).
+bool pow2_axis(int n) { return ((n + 1) & n) == 0; }
+bool gemm_required(int n) { return !pow2_axis(n); }
+bool gemm_eligible(int n) { return (n >= 15 && n <= 127) || (gemm_required(n) && n <= 127); }
 int gemm_pad(int n) { return (n + 15) & ~15; }
+// LDS elements a line of an axis takes: the FFT's odd extension 2(n + 1),
+// or both GEMM operands 2 np where that is larger (n + 1 not a power of two)
+int line_elems(int n) { return pow2_axis(n) ? 2 * (n + 1) : 2 * std::max(n + 1, gemm_pad(n)); }
 
 // Orthonormal DST-I matrix sqrt(2/(n+1)) sin(pi (m+1)(k+1)/(n+1)), zero
 // padded to np x np; the angle is reduced exactly in integers first.
@@ -212,7 +219,7 @@ void choose_tiles(SysDesc &h, int tile_elems, int ldsb_min, size_t *smem_out) {
   // LDS budget per workgroup: 32 KiB unless a line of 2048 (n = 1023) needs
   // 64, or the caller asks for 64 (twice the lines per strided tile)
   int Lmax = 0;
-  for (int ax = 0; ax < h.d; ++ax) Lmax = std::max(Lmax, 2 * (h.n[ax] + 1));
+  for (int ax = 0; ax < h.d; ++ax) Lmax = std::max(Lmax, line_elems(h.n[ax]));
   const int ldsb = (Lmax > 1024 || ldsb_min > 32768) ? 65536 : 32768;
   const int eltR = h.prec ? 8 : 16;
   const int maxeR = ldsb / eltR;
@@ -221,7 +228,7 @@ void choose_tiles(SysDesc &h, int tile_elems, int ldsb_min, size_t *smem_out) {
   const int tgtR = tile_elems > 0 ? std::min(tile_elems, maxeR) : maxeR;
   const int dl = h.d - 1;
   const int nlast = h.n[dl];
-  const int Ll = 2 * (nlast + 1);
+  const int Ll = line_elems(nlast);
   auto rows_lp = [&](int tgt, int maxe) {
     const int cap = std::max(1, std::min(64, maxe / Ll));
     return pow2floor(std::max(1, std::min(tgt / Ll, cap)));
@@ -234,7 +241,7 @@ void choose_tiles(SysDesc &h, int tile_elems, int ldsb_min, size_t *smem_out) {
       h.lpt_s[ax] = 1;
       continue;
     }
-    const int L = 2 * (h.n[ax] + 1);
+    const int L = line_elems(h.n[ax]);
     const int cap = std::max(1, std::min(64, maxeR / L));
     int want = std::max(4, tgtR / L);
     int lp = pow2floor(std::min(want, cap));
@@ -370,7 +377,8 @@ csl_status configure_single(csl_problem p, int tile_points, int lds_bytes, int b
 
 // Choose the matrix-core axes by timing the problem's own solve: a few
 // MINRES iterations (fixed count, constant right-hand side) of the
-// persistent solver with every admissible subset of the eligible axes, each
+// persistent solver with every admissible subset of the eligible axes (one
+// that holds every axis without an FFT, n + 1 not a power of two), each
 // with its default single-solve schedule and the workgroup size it allows
 // (the 512-thread solver needs the FFT on both axes of a 2-D grid); the
 // fastest is kept, the FFT winning anything within 2%.  Timing the solver
@@ -378,8 +386,8 @@ csl_status configure_single(csl_problem p, int tile_points, int lds_bytes, int b
 // the iteration (transform, staging, occupancy) rather than in stand-alone
 // transform passes.  Runs on p's workspaces; the caller then sets the
 // chosen engines and rewrites p's descriptor and schedule.
-csl_status tune_engines(csl_problem p, int elig, hipStream_t s, int *best_mask) {
-  *best_mask = 0;
+csl_status tune_engines(csl_problem p, int elig, int req, hipStream_t s, int *best_mask) {
+  *best_mask = req;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -396,7 +404,7 @@ csl_status tune_engines(csl_problem p, int elig, hipStream_t s, int *best_mask) 
   float best = INFINITY;
   csl_status st = CSL_OK;
   for (int mask = 0; mask < 8 && err == hipSuccess && st == CSL_OK; ++mask) {
-    if (mask & ~elig) continue;
+    if ((mask & ~elig) || (mask & req) != req) continue;
     SysDesc h = h_in;
     for (int ax = 0; ax < 3; ++ax) h.gemm[ax] = (mask >> ax) & 1;
     p->h = h;
@@ -417,7 +425,7 @@ csl_status tune_engines(csl_problem p, int elig, hipStream_t s, int *best_mask) 
     if (err == hipSuccess) err = hipEventSynchronize(e1);
     float ms = 0.f;
     if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-    if (err == hipSuccess && (mask == 0 ? ms < best : ms < 0.98f * best)) {
+    if (err == hipSuccess && (mask == req ? ms < best : ms < 0.98f * best)) {
       best = ms;
       *best_mask = mask;
     }
@@ -520,9 +528,9 @@ csl_status create_problem(const csl_grid *grid, const double *a_nodal, double al
   for (int ax = 0; ax < 3; ++ax) {
     if (ax < h.d) {
       const int n = grid->n[ax];
-      if (n < 3 || n > TWN / 2 - 1 || ((n + 1) & n) != 0)
+      if (n < 3 || n > TWN / 2 - 1 || (!pow2_axis(n) && n > 127))
         return fail(CSL_ERR_ARG, "n[" + std::to_string(ax) +
-                                     "] + 1 must be a power of two between 4 and 1024");
+                                     "] must be between 3 and 127, or n + 1 a power of two up to 1024");
       const double len = grid->length[ax] > 0 ? grid->length[ax] : 1.0;
       if (!std::isfinite(len)) return fail(CSL_ERR_ARG, "length must be finite");
       const double hh = len / (n + 1);
@@ -609,10 +617,11 @@ csl_status create_problem(const csl_grid *grid, const double *a_nodal, double al
   const size_t o_gtmp = take(vec);
   const size_t o_apart = take(sizeof(double) * 2 * p->adj_nblk);
   size_t o_w[3] = {0, 0, 0}, o_wf[3] = {0, 0, 0};
-  int elig = 0;
+  int elig = 0, req = 0;
   for (int ax = 0; ax < h.d; ++ax) {
     if (!gemm_eligible(h.n[ax])) continue;
     elig |= 1 << ax;
+    if (gemm_required(h.n[ax])) req |= 1 << ax;
     const size_t np2 = (size_t)gemm_pad(h.n[ax]) * gemm_pad(h.n[ax]);
     o_w[ax] = take(sizeof(double) * np2);
     o_wf[ax] = take(sizeof(float) * np2);
@@ -736,10 +745,15 @@ csl_status create_problem(const csl_grid *grid, const double *a_nodal, double al
     free_problem(p);
     return fail(CSL_ERR_ARG, "unknown sine-transform engine");
   }
-  int mask = 0;
+  if (o.dst_engine == CSL_DST_FFT && req) {
+    free_problem(p);
+    return fail(CSL_ERR_ARG, "an axis with n + 1 not a power of two needs the dense sine-matrix "
+                             "transform (dst_engine auto or gemm)");
+  }
+  int mask = req;
   if (o.dst_engine == CSL_DST_GEMM) {
     mask = elig;
-  } else if (o.dst_engine == CSL_DST_AUTO && elig) {
+  } else if (o.dst_engine == CSL_DST_AUTO && elig != req) {
     const ShapeKey key{dev, h.d, h.n[0], h.n[1], h.n[2], h.prec};
     bool have = false;
     {
@@ -751,7 +765,7 @@ csl_status create_problem(const csl_grid *grid, const double *a_nodal, double al
       }
     }
     if (!have) {
-      const csl_status st = tune_engines(p, elig, s, &mask);
+      const csl_status st = tune_engines(p, elig, req, s, &mask);
       if (st != CSL_OK) {
         free_problem(p);
         return st;

@@ -29,7 +29,7 @@ def _crand(shape, seed):
 
 # ---------------------------------------------------------------- sine transform
 
-@pytest.mark.parametrize("n", [1, 3, 7, 15, 31])
+@pytest.mark.parametrize("n", [1, 3, 7, 15, 31, 12, 100])
 def test_dst_equals_dense_sine_matrix(n):
     # Section 2.3: W is the real symmetric orthogonal DST matrix.
     j = np.arange(1, n + 1)
@@ -41,7 +41,7 @@ def test_dst_equals_dense_sine_matrix(n):
     assert np.allclose(W @ W, np.eye(n), atol=1e-13)
 
 
-@pytest.mark.parametrize("n", [3, 7, 16, 31])
+@pytest.mark.parametrize("n", [3, 7, 16, 31, 45])
 def test_mu_closed_form_and_diagonalisation(n):
     # Section 2.3: W L W = Lambda with positive diagonal.
     h = 1.0 / (n + 1)
