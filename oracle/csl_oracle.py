@@ -308,13 +308,14 @@ def minres(A, Pinv, b, tol=1e-8, maxit=1000, check_true=True,
     with P^{-1}; the initial P^{-1} b is not counted.
 
     fixed_iters: run exactly that many iterations (no stopping test).
-    Returns (x, info); info has iters, status, relres_est, relres_true and,
-    if record, the list of iterates x_k and of eta_k.
+    Returns (x, info); info has iters, status, relres_est, relres_true, the
+    Lanczos coefficients delta_1..delta_k and gamma_2..gamma_{k+1} (lists
+    "delta", "gamma") and, if record, the list of iterates x_k and of eta_k.
     """
     b = np.asarray(b)
     bnorm = math.sqrt(rdot(b, b))
     info = {"iters": 0, "status": STATUS_OK, "relres_est": 0.0,
-            "relres_true": 0.0, "history": [], "eta": []}
+            "relres_true": 0.0, "history": [], "eta": [], "delta": [], "gamma": []}
     x = np.zeros_like(b)
     if not np.isfinite(bnorm):
         info["status"] = STATUS_NONFINITE
@@ -368,6 +369,8 @@ def minres(A, Pinv, b, tol=1e-8, maxit=1000, check_true=True,
         x = x + (c_new * eta) * w_new
         eta = -s_new * eta
         info["iters"] = k
+        info["delta"].append(delta)
+        info["gamma"].append(gamma_new)
         est = abs(eta) / eta0
         info["relres_est"] = est
         if record:
@@ -631,3 +634,23 @@ def implicit_euler(a, L, tau, R, lengths=None):
         prev = spla.spsolve(Ak, prev / tau + np.ravel(R[k]))
         U[k] = prev.reshape(np.shape(a))
     return U
+
+
+# --------------------------------------------------------------------------
+# Ritz values of the preconditioned operator  (the Lanczos tridiagonal that
+# MINRES builds, Section 3; its extreme eigenvalues approach those bounded
+# by Theorem 3)
+# --------------------------------------------------------------------------
+
+
+def ritz_values(delta, gamma):
+    """Eigenvalues of T_k = tridiag(gamma_2..gamma_k; delta_1..delta_k;
+    gamma_2..gamma_k), ascending; delta and gamma as minres records them
+    (gamma[j] = gamma_{j+2}, the last entry couples to step k + 1)."""
+    import scipy.linalg as sla
+    d = np.asarray(delta, dtype=np.float64)
+    k = d.size
+    if k == 0:
+        return d
+    e = np.asarray(gamma, dtype=np.float64)[:k - 1]
+    return sla.eigvalsh_tridiagonal(d, e)

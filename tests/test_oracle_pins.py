@@ -500,3 +500,36 @@ def test_paradiag_small_alpha_approaches_implicit_euler():
         U, _ = O.paradiag_solve(a, L, tau, alpha_c, R)
         errs.append(np.linalg.norm(U - Ue) / np.linalg.norm(Ue))
     assert errs[1] <= 1e-4 and errs[1] < errs[0] / 50, errs
+
+
+# ---- Ritz values of the Lanczos tridiagonal --------------------------------
+
+def test_ritz_values_constant_coefficient_are_pm1():
+    # Theorem 1: with a constant, P^{-1} A has only the eigenvalues +-1; the
+    # two-step Lanczos tridiagonal reproduces them
+    n = 15
+    prob = O.Problem(np.full((n, n), 1.7), 30.0, 40.0)
+    _, info = prob.solve(_crand((n, n), 3), tol=1e-10)
+    assert info["iters"] == 2
+    th = O.ritz_values(info["delta"], info["gamma"])
+    assert np.allclose(th, [-1.0, 1.0], atol=1e-10)
+
+
+def test_ritz_values_interlace_and_converge_to_the_extremes():
+    # Ritz values of T_k lie between the extreme eigenvalues of P^{-1} A
+    # (from the dense generalised problem) and the outermost ones converge
+    # to them
+    n = 7
+    a = WL.coef_c1(n) * 1.5
+    alpha, beta = 20.0, 15.0
+    prob = O.Problem(a, alpha, beta)
+    B = O.block_matrix(prob.K, alpha, beta).toarray()
+    P = np.linalg.inv(O.dense_Pinv(a.shape, prob.abar, alpha, beta))
+    ev = sla.eigh(B, sla.block_diag(P, P), eigvals_only=True)
+    _, info = prob.solve(_crand((n, n), 4), fixed_iters=40)
+    th = O.ritz_values(info["delta"], info["gamma"])
+    assert th.min() >= ev.min() * (1 + 1e-10) - 1e-12 and th.max() <= ev.max() * (1 + 1e-10) + 1e-12
+    # the two largest |eigenvalues| nearly coincide (1.402769, 1.402816),
+    # so the outermost Ritz values approach them slowly: 5e-6 after 40 steps
+    assert abs(th.max() - ev.max()) <= 1e-4 * abs(ev.max())
+    assert abs(th.min() - ev.min()) <= 1e-4 * abs(ev.min())
