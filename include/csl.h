@@ -167,6 +167,24 @@ csl_status problem_info(csl_problem p, double *abar, double *a_min,
 csl_status problem_set_schedule(csl_problem p, int tile_points, int lds_bytes,
                                 int block_threads, hipStream_t s);
 
+/* Lanczos coefficients of the problem's last completed solve (its own
+ * minres_solve / minres_adjoint, or its system within a batch_solve):
+ * delta_1..delta_k, the diagonal of the tridiagonal T_k that MINRES builds
+ * for P^{-1} A (Section 3), and gamma_2..gamma_{k+1}, its off-diagonal
+ * (gamma_{k+1} couples step k to the next), k = the steps taken (at most
+ * 4096 recorded).  delta, gamma: host arrays of cap entries (the first
+ * min(cap, k) are written; may be NULL when cap = 0); *count = k.
+ * Synchronises s: call it on the stream of the solve. */
+csl_status problem_lanczos(csl_problem p, double *delta, double *gamma, int cap,
+                           int *count, hipStream_t s);
+
+/* Ritz values of P^{-1} A from the last completed solve: the eigenvalues of
+ * T_k, ascending (host bisection on Sturm counts, O(k^2) work).  Their
+ * extremes approach the extreme eigenvalues that Theorem 3 bounds; all of
+ * them lie between the smallest and largest eigenvalue.  theta: host array
+ * of cap entries; *count = k.  Synchronises s. */
+csl_status problem_ritz(csl_problem p, double *theta, int cap, int *count, hipStream_t s);
+
 /* Sine-transform engine in use along each axis (CSL_DST_FFT or
  * CSL_DST_GEMM; entries past the grid's dimension are CSL_DST_FFT). */
 csl_status problem_dst_engines(csl_problem p, int engines[3]);

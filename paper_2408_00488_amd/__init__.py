@@ -122,6 +122,8 @@ def load_library():
     L.batch_destroy.argtypes = [vp]
     L.batch_tune.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp),
                              ctypes.POINTER(_BatchTuning), vp]
+    L.problem_lanczos.argtypes = [vp, dp, dp, ip, ctypes.POINTER(ctypes.c_int), vp]
+    L.problem_ritz.argtypes = [vp, dp, ip, ctypes.POINTER(ctypes.c_int), vp]
     L.paradiag_create.argtypes = [ctypes.POINTER(_Grid), vp, ip, ctypes.c_double,
                                   ctypes.c_double, ctypes.POINTER(_ProblemOpts),
                                   ctypes.POINTER(_BatchOpts), vp, ctypes.POINTER(vp)]
@@ -137,7 +139,8 @@ def load_library():
                "problem_set_schedule", "problem_tune", "problem_schedule", "batch_schedule",
                "apply_A", "apply_Pinv",
                "minres_solve", "minres_adjoint", "batch_create", "batch_solve",
-               "batch_tune", "batch_destroy", "paradiag_create", "paradiag_shift",
+               "batch_tune", "batch_destroy", "problem_lanczos", "problem_ritz",
+               "paradiag_create", "paradiag_shift",
                "paradiag_transform", "paradiag_solve", "paradiag_tune", "paradiag_batch",
                "paradiag_destroy"):
         getattr(L, fn).restype = ctypes.c_int
@@ -235,6 +238,32 @@ class Problem:
         t = _BatchTuning()
         _check(load_library().problem_schedule(self.handle, ctypes.byref(t)))
         return _tuning_dict(t)
+
+    def lanczos(self):
+        """(delta, gamma) of the last completed solve as float64 NumPy arrays
+        (see problem_lanczos)."""
+        import numpy as np
+        L = load_library()
+        k = ctypes.c_int()
+        _check(L.problem_lanczos(self.handle, None, None, 0, ctypes.byref(k), _stream(self.device)))
+        d = np.empty(k.value)
+        g = np.empty(k.value)
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(L.problem_lanczos(self.handle, d.ctypes.data_as(dp), g.ctypes.data_as(dp), k.value,
+                                 ctypes.byref(k), _stream(self.device)))
+        return d, g
+
+    def ritz_values(self):
+        """Ritz values of P^{-1} A from the last completed solve, ascending
+        (see problem_ritz)."""
+        import numpy as np
+        L = load_library()
+        k = ctypes.c_int()
+        _check(L.problem_ritz(self.handle, None, 0, ctypes.byref(k), _stream(self.device)))
+        th = np.empty(k.value)
+        _check(L.problem_ritz(self.handle, th.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                              k.value, ctypes.byref(k), _stream(self.device)))
+        return th
 
     def tune(self, f, z=None) -> dict:
         """Time candidate schedules of minres_solve on f and keep the fastest."""

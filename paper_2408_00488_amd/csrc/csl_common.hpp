@@ -110,7 +110,13 @@ struct SysDesc {
   double *part;            // per-tile partial sums
   Ctl *ctl;
   DevInfo *info;
+  // Lanczos coefficients of the last solve: lz[2 (j - 1)] = delta_j,
+  // lz[2 (j - 1) + 1] = gamma_{j+1} for j <= kLanczosCap; lz[2 kLanczosCap]
+  // = the number of steps recorded
+  double *lz;
 };
+
+constexpr int kLanczosCap = 4096;
 
 // Right-hand side and output of one system for one solve.
 struct IOPtr {

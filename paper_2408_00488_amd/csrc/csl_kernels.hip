@@ -594,6 +594,11 @@ __device__ __forceinline__ void epilogue(const SysDesc &S, const SolveParams &P,
     // Givens rotations of column j of the Lanczos tridiagonal (step j)
     const double gn = sqrt(g2);
     const double dl = C->delta, g = C->gamma;
+    if (iter <= kLanczosCap) {
+      S.lz[2 * (iter - 1)] = dl;
+      S.lz[2 * (iter - 1) + 1] = gn;
+      S.lz[2 * kLanczosCap] = (double)iter;
+    }
     const double c = C->c, co = C->c_old, s = C->s, so = C->s_old, eta = C->eta;
     const double e0 = c * dl - co * s * g;
     const double e1 = hypot(e0, gn);
@@ -796,6 +801,7 @@ __global__ void init_kernel(const SysDesc *__restrict__ sys, int nsys, Glob *G) 
     I->iters = 0;
     I->relres_est = 0.0;
     I->relres_true = 0.0;
+    sys[s].lz[2 * kLanczosCap] = 0.0;
   }
   if (threadIdx.x == 0) {
     G->active = nsys;

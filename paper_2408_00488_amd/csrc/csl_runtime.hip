@@ -320,6 +320,77 @@ const char *status_name(csl_status st) {
   return st >= 0 && st <= 8 ? names[st] : "?";
 }
 
+// Eigenvalues of the symmetric tridiagonal matrix with diagonal d and
+// off-diagonal e (e[i] couples i and i + 1), ascending, by bisection on
+// Sturm counts: the number of eigenvalues below x is the number of negative
+// pivots of the LDL^T factorisation of T - x I.  Intervals are split until
+// they hold one eigenvalue and are as narrow as the rounding allows
+// (O(k^2) counts of O(k) work for k eigenvalues).
+int sturm_below(const std::vector<double> &d, const std::vector<double> &e2, double x) {
+  int c = 0;
+  double q = 1.0;
+  for (size_t i = 0; i < d.size(); ++i) {
+    q = d[i] - x - (i > 0 ? e2[i - 1] / q : 0.0);
+    if (q == 0.0) q = -1e-300;
+    c += q < 0.0;
+  }
+  return c;
+}
+
+void tridiag_eigenvalues(const std::vector<double> &d, const std::vector<double> &e,
+                         std::vector<double> &out) {
+  const int k = (int)d.size();
+  out.assign(k, 0.0);
+  if (k == 0) return;
+  std::vector<double> e2(e.size());
+  double lo = INFINITY, hi = -INFINITY;
+  for (int i = 0; i < k; ++i) {
+    const double r = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < k ? std::fabs(e[i]) : 0.0);
+    lo = std::min(lo, d[i] - r);
+    hi = std::max(hi, d[i] + r);
+  }
+  for (size_t i = 0; i < e.size(); ++i) e2[i] = e[i] * e[i];
+  const double span = std::max(std::fabs(lo), std::fabs(hi));
+  lo -= 1e-12 * span + 1e-300;
+  hi += 1e-12 * span + 1e-300;
+  struct Iv {
+    double lo, hi;
+    int clo, chi;
+  };
+  std::vector<Iv> stack{{lo, hi, 0, k}};
+  while (!stack.empty()) {
+    const Iv v = stack.back();
+    stack.pop_back();
+    if (v.chi <= v.clo) continue;
+    const double mid = 0.5 * (v.lo + v.hi);
+    const double tol = 4.0 * 2.220446049250313e-16 * std::max(std::fabs(v.lo), std::fabs(v.hi));
+    if (v.hi - v.lo <= tol || mid <= v.lo || mid >= v.hi) {
+      for (int i = v.clo; i < v.chi; ++i) out[i] = mid;
+      continue;
+    }
+    const int cm = std::min(std::max(sturm_below(d, e2, mid), v.clo), v.chi);
+    stack.push_back({v.lo, mid, v.clo, cm});
+    stack.push_back({mid, v.hi, cm, v.chi});
+  }
+}
+
+// Lanczos coefficients recorded by the last solve of p (its own or within a
+// batch): delta_1..delta_k, gamma_2..gamma_{k+1}.
+csl_status read_lanczos(csl_problem p, std::vector<double> &delta, std::vector<double> &gamma,
+                        hipStream_t s) {
+  std::vector<double> buf(2 * kLanczosCap + 1);
+  HIPCHK(hipMemcpyAsync(buf.data(), p->h.lz, sizeof(double) * buf.size(), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const int k = std::min(kLanczosCap, std::max(0, (int)buf[2 * kLanczosCap]));
+  delta.resize(k);
+  gamma.resize(k);
+  for (int j = 0; j < k; ++j) {
+    delta[j] = buf[2 * j];
+    gamma[j] = buf[2 * j + 1];
+  }
+  return CSL_OK;
+}
+
 void free_problem(csl_problem p) {
   if (!p) return;
   if (p->mem) (void)hipFree(p->mem);
@@ -616,6 +687,7 @@ csl_status create_problem(const csl_grid *grid, const double *a_nodal, double al
   const size_t o_ytmp = take(vec);
   const size_t o_gtmp = take(vec);
   const size_t o_apart = take(sizeof(double) * 2 * p->adj_nblk);
+  const size_t o_lz = take(sizeof(double) * (2 * kLanczosCap + 1));
   size_t o_w[3] = {0, 0, 0}, o_wf[3] = {0, 0, 0};
   int elig = 0, req = 0;
   for (int ax = 0; ax < h.d; ++ax) {
@@ -655,6 +727,7 @@ csl_status create_problem(const csl_grid *grid, const double *a_nodal, double al
   p->ytmp = (double2 *)(base + o_ytmp);
   p->gtmp = (double2 *)(base + o_gtmp);
   p->adj_part = (double *)(base + o_apart);
+  h.lz = (double *)(base + o_lz);
   for (int ax = 0; ax < 3; ++ax) {
     h.gemm[ax] = 0;
     h.Wm[ax] = (elig >> ax & 1) ? (const double *)(base + o_w[ax]) : nullptr;
@@ -686,6 +759,7 @@ csl_status create_problem(const csl_grid *grid, const double *a_nodal, double al
     }                                                                                \
   } while (0)
   PCHK(hipMemcpyAsync(d_a, a_nodal, sizeof(double) * h.M, hipMemcpyDeviceToDevice, s));
+  PCHK(hipMemsetAsync(h.lz, 0, sizeof(double) * (2 * kLanczosCap + 1), s));
   PCHK(hipMemcpyAsync(d_mu, mu.data(), sizeof(double) * nmu, hipMemcpyHostToDevice, s));
   PCHK(hipMemcpyAsync(d_muf, muf.data(), sizeof(float) * nmu, hipMemcpyHostToDevice, s));
   std::vector<double> Wt[3];
@@ -789,6 +863,34 @@ csl_status create_problem(const csl_grid *grid, const double *a_nodal, double al
   }
 #undef PCHK
   *out = p;
+  return CSL_OK;
+}
+
+csl_status problem_lanczos(csl_problem p, double *delta, double *gamma, int cap, int *count,
+                           hipStream_t s) {
+  if (!p || !count || cap < 0 || (cap > 0 && (!delta || !gamma)))
+    return fail(CSL_ERR_ARG, "NULL argument or negative capacity");
+  std::vector<double> d, g;
+  const csl_status st = read_lanczos(p, d, g, s);
+  if (st != CSL_OK) return st;
+  *count = (int)d.size();
+  for (int j = 0; j < std::min(cap, (int)d.size()); ++j) {
+    delta[j] = d[j];
+    gamma[j] = g[j];
+  }
+  return CSL_OK;
+}
+
+csl_status problem_ritz(csl_problem p, double *theta, int cap, int *count, hipStream_t s) {
+  if (!p || !count || cap < 0 || (cap > 0 && !theta))
+    return fail(CSL_ERR_ARG, "NULL argument or negative capacity");
+  std::vector<double> d, g, th;
+  const csl_status st = read_lanczos(p, d, g, s);
+  if (st != CSL_OK) return st;
+  if (!d.empty()) g.resize(d.size() - 1);   // the last gamma couples to step k + 1
+  tridiag_eigenvalues(d, g, th);
+  *count = (int)th.size();
+  for (int j = 0; j < std::min(cap, (int)th.size()); ++j) theta[j] = th[j];
   return CSL_OK;
 }
 

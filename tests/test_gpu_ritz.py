@@ -1,0 +1,137 @@
+"""GPU: the Lanczos coefficients the solver records and the Ritz values of
+P^{-1} A computed from them (problem_lanczos, problem_ritz).
+
+- delta_j, gamma_{j+1} against the oracle's MINRES on the same inputs:
+  relative 1e-10 (the iterates agree to that level); the library's
+  bisection against SciPy's tridiagonal eigensolver on the same
+  coefficients: 1e-12 of the largest |value|.
+- Theorem 1: a constant coefficient gives the two Ritz values -1 and +1.
+- Theorem 3 (i) at n = 511 and 1023 (Example 2's coefficient, geometric-mean
+  abar, alpha >= 0): every Ritz value lies within the spectrum, so
+  max |theta| <= mu0 = sqrt(2 a_max / a_min); the extremes for the mean
+  and the geometric-mean abar are printed side by side.
+"""
+import sys
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+torch = pytest.importorskip("torch")
+
+from oracle import csl_oracle as O
+from paper_2408_00488_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def csl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2408_00488_amd as C
+    C.load_library()
+    return C
+
+
+def _crand(shape, seed):
+    g = np.random.default_rng(seed)
+    return g.standard_normal(shape) + 1j * g.standard_normal(shape)
+
+
+def _coef(shape, seed, lo=0.5, hi=2.0):
+    return np.random.default_rng(seed).uniform(lo, hi, shape)
+
+
+def cuda(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+@pytest.mark.parametrize("shape", [(31, 31), (15, 15, 15), (20, 45)])
+def test_lanczos_and_ritz_match_oracle(csl, shape):
+    a = _coef(shape, 1)
+    f = _crand(shape, 2)
+    lam = complex(15.0, 35.0)
+    p = csl.Problem(cuda(a), lam.real, lam.imag)
+    _, info = csl.minres_solve(p, cuda(f), timeout_ms=30000)
+    d, g = p.lanczos()
+    assert d.size == info["iters"] and g.size == info["iters"]
+    po = O.Problem(a, lam.real, lam.imag, abar_rule="given", abar=p.abar)
+    _, io = po.solve(f)
+    k = min(d.size, len(io["delta"]))
+    _say(shape, "steps", d.size, len(io["delta"]))
+    assert abs(d.size - len(io["delta"])) <= 1
+    do, go = np.array(io["delta"][:k]), np.array(io["gamma"][:k])
+    assert np.abs(d[:k] - do).max() <= 1e-10 * np.abs(do).max()
+    assert np.abs(g[:k] - go).max() <= 1e-10 * np.abs(go).max()
+    th = p.ritz_values()
+    ref = sla.eigvalsh_tridiagonal(d, g[:-1])
+    assert th.size == d.size
+    assert np.abs(th - ref).max() <= 1e-12 * np.abs(ref).max()
+    tho = O.ritz_values(io["delta"][:k], io["gamma"][:k])
+    thk = sla.eigvalsh_tridiagonal(d[:k], g[:k - 1])
+    assert np.abs(thk - tho).max() <= 1e-9 * np.abs(tho).max()
+    p.close()
+
+
+def test_ritz_constant_coefficient(csl):
+    n = 63
+    p = csl.Problem(cuda(np.full((n, n), 2.5)), 30.0, -40.0)
+    _, info = csl.minres_solve(p, cuda(_crand((n, n), 3)), tol=1e-10)
+    assert info["iters"] == 2
+    assert np.allclose(p.ritz_values(), [-1.0, 1.0], atol=1e-10)
+    p.close()
+
+
+def test_recorded_in_a_batch(csl):
+    shapes = [(31, 31), (63, 63), (15, 31)]
+    probs = [csl.Problem(cuda(_coef(s, 10 + j)), 5.0 + j, 20.0) for j, s in enumerate(shapes)]
+    fs = [cuda(_crand(s, 20 + j)) for j, s in enumerate(shapes)]
+    b = csl.Batch(probs, timeout_ms=30000)
+    _, infos = b.solve(fs)
+    for p, f, info in zip(probs, fs, infos):
+        d, g = p.lanczos()
+        assert d.size == info["iters"]
+        th_b = p.ritz_values()
+        # the problem's own solve records the same recurrence (up to the
+        # order of the partial sums)
+        _, i1 = csl.minres_solve(p, f, timeout_ms=30000)
+        th_1 = p.ritz_values()
+        k = min(th_b.size, th_1.size)
+        assert abs(th_b.size - th_1.size) <= 1
+        if th_b.size == th_1.size:
+            assert np.abs(th_b - th_1).max() <= 1e-9 * np.abs(th_1).max()
+    b.close()
+    for p in probs:
+        p.close()
+
+
+@pytest.mark.parametrize("n", [511, 1023])
+def test_theorem3_bound_at_scale(csl, n):
+    a = WL.coef_paper_ex2(n)
+    amin, amax = O.coefficient_bounds(a)
+    mu0 = np.sqrt(2.0 * amax / amin)
+    f = cuda(_crand((n, n), 4))
+    rows = []
+    for alpha, beta in ((100.0, 100.0), (1.0, -100.0), (100.0, -25.0)):
+        out = {}
+        for rule in ("geomean", "mean"):
+            p = csl.Problem(cuda(a), alpha, beta, abar_rule=rule)
+            _, info = csl.minres_solve(p, f, timeout_ms=60000)
+            th = np.abs(p.ritz_values())
+            out[rule] = (info["iters"], th.min(), th.max())
+            if rule == "geomean":
+                # Theorem 3 (i): |eig(P^-1 A)| <= mu0, and Ritz values lie
+                # between the extreme eigenvalues
+                assert th.max() <= mu0 * (1 + 1e-9), (alpha, beta, th.max(), mu0)
+            p.close()
+        rows.append((alpha, beta, out))
+    for alpha, beta, out in rows:
+        _say(f"n={n} lambda={alpha}+{beta}i  bound [{1 / mu0:.4f}, {mu0:.4f}]  "
+             + "  ".join(f"{r}: {it} its, |theta| in [{lo:.4f}, {hi:.4f}]"
+                         for r, (it, lo, hi) in out.items()))
