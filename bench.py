@@ -208,6 +208,52 @@ def other_configs(C, WL, dev):
                          "ms_forward_plus_adjoint_all": (time.perf_counter() - t0) * 1e3,
                          "max_relres": worst}
     out["paradiag"] = paradiag_config(C, WL, dev)
+    out["many_rhs"] = many_rhs_config(C, WL, dev)
+    return out
+
+
+def many_rhs_config(C, WL, dev, n=255, count=64):
+    """64 right-hand sides of one shifted system (c1's coefficient and shift
+    on a 2-D n = 255 grid, FP64): one batch of the problem and 63 clones
+    against 64 single solves of the problem."""
+    import torch
+    s = WL.workload("c1", n_override=n).systems[0]
+    a = torch.from_numpy(s.a).to(dev)
+    g = WL.rng(7)
+    fs = [torch.from_numpy(WL.complex_normal(g, (n, n))).to(dev) for _ in range(count)]
+    zs = [torch.empty_like(f) for f in fs]
+    p = C.Problem(a, s.lam.real, s.lam.imag)
+    p.tune(fs[0], zs[0])
+    probs = [p] + [p.clone() for _ in range(count - 1)]
+    b = C.Batch(probs)
+    sched = b.tune(fs, zs)
+    _, infos = b.solve(fs, zs)
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.solve(fs, zs, want_info=False)
+    torch.cuda.synchronize()
+    ms_batch = (time.perf_counter() - t0) / reps * 1e3
+    for f, z in zip(fs, zs):
+        C.minres_solve(p, f, z, want_info=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for f, z in zip(fs, zs):
+        C.minres_solve(p, f, z, want_info=False)
+    torch.cuda.synchronize()
+    ms_single = (time.perf_counter() - t0) * 1e3
+    out = {"rhs": count, "points": n * n, "ms_batch": ms_batch, "ms_64_single_solves": ms_single,
+           "solves_per_s_batch": count / ms_batch * 1e3,
+           "solves_per_s_single": count / ms_single * 1e3,
+           "speedup": ms_single / ms_batch,
+           "iters_min": min(i["iters"] for i in infos), "iters_max": max(i["iters"] for i in infos),
+           "all_converged": all(i["status"] == 0 for i in infos),
+           "schedule": {"tile_points": sched["tile_points"], "lds_bytes": sched["lds_bytes"],
+                        "block_threads": sched["block_threads"]}}
+    b.close()
+    for q in probs:
+        q.close()
     return out
 
 

@@ -151,6 +151,13 @@ csl_status create_problem(const csl_grid *grid, const double *a_nodal,
 
 csl_status destroy_problem(csl_problem p);
 
+/* A second problem with p's grid, coefficient (copied from p's own copy),
+ * shift, abar, precision, sine-transform engines and schedule, and
+ * workspaces of its own, without timing the engines again: several
+ * right-hand sides of one shifted system are then solved together by
+ * batching p and its clones.  Synchronises s. */
+csl_status problem_clone(csl_problem p, hipStream_t s, csl_problem *out);
+
 /* Query: abar used by P, and the face-coefficient bounds a_min, a_max
  * (Lemma 3).  Any pointer may be NULL. */
 csl_status problem_info(csl_problem p, double *abar, double *a_min,

@@ -122,6 +122,7 @@ def load_library():
     L.batch_destroy.argtypes = [vp]
     L.batch_tune.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp),
                              ctypes.POINTER(_BatchTuning), vp]
+    L.problem_clone.argtypes = [vp, vp, ctypes.POINTER(vp)]
     L.problem_lanczos.argtypes = [vp, dp, dp, ip, ctypes.POINTER(ctypes.c_int), vp]
     L.problem_ritz.argtypes = [vp, dp, ip, ctypes.POINTER(ctypes.c_int), vp]
     L.paradiag_create.argtypes = [ctypes.POINTER(_Grid), vp, ip, ctypes.c_double,
@@ -139,7 +140,7 @@ def load_library():
                "problem_set_schedule", "problem_tune", "problem_schedule", "batch_schedule",
                "apply_A", "apply_Pinv",
                "minres_solve", "minres_adjoint", "batch_create", "batch_solve",
-               "batch_tune", "batch_destroy", "problem_lanczos", "problem_ritz",
+               "batch_tune", "batch_destroy", "problem_clone", "problem_lanczos", "problem_ritz",
                "paradiag_create", "paradiag_shift",
                "paradiag_transform", "paradiag_solve", "paradiag_tune", "paradiag_batch",
                "paradiag_destroy"):
@@ -226,6 +227,19 @@ class Problem:
         if self._h is None:
             raise RuntimeError("problem destroyed")
         return self._h
+
+    def clone(self) -> "Problem":
+        """A problem with the same set-up and workspaces of its own (see
+        problem_clone): batch it with this one to solve several right-hand
+        sides of the same shifted system in one launch."""
+        torch = _torch()
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(load_library().problem_clone(self.handle, _stream(self.device), ctypes.byref(h)))
+        q = Problem.__new__(Problem)
+        q.__dict__.update({k: v for k, v in self.__dict__.items() if k != "_h"})
+        q._h = h
+        return q
 
     def set_schedule(self, tile_points: int = 0, lds_bytes: int = 0, block_threads: int = 0):
         """Schedule of this problem's own solves (see problem_set_schedule)."""

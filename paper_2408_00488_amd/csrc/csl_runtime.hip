@@ -157,6 +157,8 @@ struct csl_problem_s {
   int lds_bytes = 0;
   int block_threads = 256;
   bool wg512_ok = false; // the FFT on every axis: the 512-thread solver applies
+  csl_grid grid{};       // creation arguments (for problem_clone)
+  csl_problem_opts opts{};
 };
 
 struct csl_batch_s {
@@ -575,8 +577,11 @@ int csl_version(void) { return 100; }
 
 const char *csl_last_error(void) { return g_err.c_str(); }
 
-csl_status create_problem(const csl_grid *grid, const double *a_nodal, double alpha, double beta,
-                          const csl_problem_opts *opts, hipStream_t s, csl_problem *out) {
+// forced_mask >= 0: the matrix-core axes are given (problem_clone), no
+// engine selection
+static csl_status create_problem_impl(const csl_grid *grid, const double *a_nodal, double alpha,
+                                      double beta, const csl_problem_opts *opts, hipStream_t s,
+                                      csl_problem *out, int forced_mask) {
   if (!out) return fail(CSL_ERR_ARG, "out is NULL");
   *out = nullptr;
   if (!grid || !a_nodal) return fail(CSL_ERR_ARG, "grid or coefficient is NULL");
@@ -825,7 +830,9 @@ csl_status create_problem(const csl_grid *grid, const double *a_nodal, double al
                              "transform (dst_engine auto or gemm)");
   }
   int mask = req;
-  if (o.dst_engine == CSL_DST_GEMM) {
+  if (forced_mask >= 0) {
+    mask = forced_mask & elig;
+  } else if (o.dst_engine == CSL_DST_GEMM) {
     mask = elig;
   } else if (o.dst_engine == CSL_DST_AUTO && elig != req) {
     const ShapeKey key{dev, h.d, h.n[0], h.n[1], h.n[2], h.prec};
@@ -862,7 +869,35 @@ csl_status create_problem(const csl_grid *grid, const double *a_nodal, double al
     }
   }
 #undef PCHK
+  p->grid = *grid;
+  p->opts = o;
   *out = p;
+  return CSL_OK;
+}
+
+csl_status create_problem(const csl_grid *grid, const double *a_nodal, double alpha, double beta,
+                          const csl_problem_opts *opts, hipStream_t s, csl_problem *out) {
+  return create_problem_impl(grid, a_nodal, alpha, beta, opts, s, out, -1);
+}
+
+csl_status problem_clone(csl_problem p, hipStream_t s, csl_problem *out) {
+  if (!out) return fail(CSL_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!p) return fail(CSL_ERR_ARG, "problem is NULL");
+  csl_problem_opts o = p->opts;
+  o.abar_rule = CSL_ABAR_GIVEN;   // the same abar, whichever rule produced it
+  o.abar = p->h.abar;
+  int mask = 0;
+  for (int ax = 0; ax < 3; ++ax) mask |= (p->h.gemm[ax] ? 1 : 0) << ax;
+  csl_problem q = nullptr;
+  csl_status st = create_problem_impl(&p->grid, p->h.a, p->h.alpha, p->h.beta, &o, s, &q, mask);
+  if (st != CSL_OK) return st;
+  st = configure_single(q, p->tile_points, p->lds_bytes, p->block_threads, s);
+  if (st != CSL_OK) {
+    free_problem(q);
+    return st;
+  }
+  *out = q;
   return CSL_OK;
 }
 
