@@ -78,7 +78,8 @@ def test_step_transform_and_shifts(csl, L, shape, alpha_c):
 
 @pytest.mark.parametrize("shape,L,alpha_c,fp32", [((15, 15), 8, 0.1, False),
                                                   ((7, 7, 7), 16, 0.05, False),
-                                                  ((31, 31), 32, 1e-2, True)])
+                                                  ((31, 31), 32, 1e-2, True),
+                                                  ((20, 31), 8, 0.1, False)])
 def test_paradiag_solve_against_all_at_once(csl, shape, L, alpha_c, fp32):
     _say("paradiag solve", shape, L, alpha_c, fp32)
     tau = 0.02
