@@ -573,7 +573,7 @@ csl_status configure_batch(csl_batch b, int tile_points, int lds_bytes, int bloc
 
 extern "C" {
 
-int csl_version(void) { return 100; }
+int csl_version(void) { return 200; }
 
 const char *csl_last_error(void) { return g_err.c_str(); }
 
