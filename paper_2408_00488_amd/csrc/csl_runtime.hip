@@ -39,10 +39,12 @@ csl_status fail(csl_status st, const std::string &msg) {
 
 constexpr int kMaxDevices = 64;
 bool g_tw_ready[kMaxDevices] = {false};
+std::mutex g_tw_mu;   // problems may be created from several threads
 
 // exp(-2 pi i m / TWN) in FP64 from the host sin/cos, rounded for FP32.
 csl_status ensure_twiddles(int dev) {
   if (dev < 0 || dev >= kMaxDevices) return fail(CSL_ERR_ARG, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_tw_mu);
   if (g_tw_ready[dev]) return CSL_OK;
   std::vector<double2> t64(TWN);
   std::vector<float2> t32(TWN);
