@@ -219,3 +219,41 @@ def test_option_and_alias_checks(csl):
     z2, _ = csl.minres_solve(p, f)
     assert torch.equal(z, z2)
     p.close()
+
+
+def test_problems_from_several_threads(csl):
+    # ctypes releases the GIL: four threads create problems and solve on
+    # streams of their own at the same time; every result equals the same
+    # solve done alone
+    import threading
+    shapes = [(31, 31), (63, 63), (15, 31, 15), (20, 45)]
+    data = [(_coef(s, 60 + j), _crand(s, 70 + j)) for j, s in enumerate(shapes)]
+    ref = []
+    for a, f in data:
+        p = csl.Problem(cuda(a), 8.0, 30.0)
+        z, info = csl.minres_solve(p, cuda(f))
+        ref.append((z.cpu(), info))
+        p.close()
+    out = [None] * len(data)
+    errors = []
+
+    def work(j):
+        try:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                a, f = data[j]
+                p = csl.Problem(cuda(a), 8.0, 30.0)
+                z, info = csl.minres_solve(p, cuda(f))
+                out[j] = (z.cpu(), info)
+                p.close()
+        except Exception as e:   # reported below
+            errors.append((j, repr(e)))
+
+    threads = [threading.Thread(target=work, args=(j,)) for j in range(len(data))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    for (zr, ir), (z, i) in zip(ref, out):
+        assert i == ir and torch.equal(z, zr)
