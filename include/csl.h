@@ -262,7 +262,9 @@ typedef struct csl_batch_tuning {
     double ms;              /* time of one solve with the chosen schedule       */
     double ms_default;      /* time with the creation-time schedule             */
     int block_threads;      /* workgroup size of the persistent solver          */
-    int reserved;
+    int tile_elems;         /* chunk size (LDS elements) of a problem's own
+                               solves, 0 = the creation-time tiling (always 0
+                               for batches, which keep that tiling)        */
 } csl_batch_tuning;
 
 /* Group `count` problems (any grids, shifts and precisions) into one
@@ -284,9 +286,10 @@ csl_status batch_solve(csl_batch b, const double *const *f, double *const *z,
                        csl_solve_info *infos, hipStream_t s);
 
 /* Autotuner of a problem's own schedule: solves (K + lambda I) z = f with
- * each candidate tile size, LDS budget and allowed workgroup size (tol
- * 1e-8), timing each on stream s, and keeps the fastest
- * (problem_set_schedule).  Blocks until done; out may be NULL (its
+ * each candidate tile size, LDS budget and allowed workgroup size, and on
+ * grids of at most 65536 points also chunks of 512 and 1024 elements (tol
+ * 1e-8), timing each on stream s, and keeps the fastest (the chunk size
+ * stays in force through later problem_set_schedule calls).  Blocks until done; out may be NULL (its
  * grid_size is the single-solve grid). */
 csl_status problem_tune(csl_problem p, const double *f, double *z,
                         csl_batch_tuning *out, hipStream_t s);

@@ -73,13 +73,14 @@ class _BatchTuning(ctypes.Structure):
     _fields_ = [("tile_points", ctypes.c_int), ("lds_bytes", ctypes.c_int),
                 ("grid_size", ctypes.c_int), ("candidates", ctypes.c_int),
                 ("ms", ctypes.c_double), ("ms_default", ctypes.c_double),
-                ("block_threads", ctypes.c_int), ("reserved", ctypes.c_int)]
+                ("block_threads", ctypes.c_int), ("tile_elems", ctypes.c_int)]
 
 
 def _tuning_dict(t: _BatchTuning) -> dict:
     return {"tile_points": t.tile_points, "lds_bytes": t.lds_bytes,
             "grid_size": t.grid_size, "block_threads": t.block_threads,
-            "candidates": t.candidates, "ms": t.ms, "ms_default": t.ms_default}
+            "candidates": t.candidates, "ms": t.ms, "ms_default": t.ms_default,
+            "tile_elems": t.tile_elems}
 
 
 _lib = None

@@ -161,7 +161,15 @@ struct csl_problem_s {
   bool wg512_ok = false; // the FFT on every axis: the 512-thread solver applies
   csl_grid grid{};       // creation arguments (for problem_clone)
   csl_problem_opts opts{};
+  int single_te = 0;     // chunk size of the problem's own solves (0 = creation tiling)
+  int part_cap = 1;      // per-tile partial-sum slots allocated
 };
+
+// Grids up to this many points may take smaller chunks for their own solves
+// (problem_tune tries 512 and 1024 elements): a small system has too few
+// full-size chunks to occupy the device.
+constexpr int kSmallChunkPoints = 65536;
+constexpr int kSmallChunkElems[2] = {512, 1024};
 
 struct csl_batch_s {
   int device = 0;
@@ -429,7 +437,10 @@ csl_status configure_single(csl_problem p, int tile_points, int lds_bytes, int b
                             hipStream_t s) {
   SysDesc h = p->h0;
   size_t sm = p->smem0;
-  if (lds_bytes > 32768 && p->smem0 <= 32768) choose_tiles(h, p->tile_elems, lds_bytes, &sm);
+  if (p->single_te > 0) choose_tiles(h, p->single_te, lds_bytes, &sm);
+  else if (lds_bytes > 32768 && p->smem0 <= 32768) choose_tiles(h, p->tile_elems, lds_bytes, &sm);
+  // every tile of every phase owns a partial-sum slot
+  if (h.maxtile > p->part_cap) return fail(CSL_ERR_ARG, "chunking exceeds the partial-sum slots");
   const int wg = resolve_wg(block_threads, p->wg512_ok);
   int bpc = 0;
   HIPCHK(solve_occupancy_wg(wg, p->h0.d == 2, sm, &bpc));
@@ -684,7 +695,16 @@ static csl_status create_problem_impl(const csl_grid *grid, const double *a_noda
   size_t o_v[7];
   for (int i = 0; i < 7; ++i) o_v[i] = take(i < 3 ? vecb : vec);   // Tq, Tv0, Tv1 blocked
   const size_t o_t = take(tsz);
-  const size_t o_part = take(sizeof(double) * std::max(1, h.maxtile));
+  // partial-sum slots: the creation-time chunking, and on small grids the
+  // smallest chunks problem_tune may choose for the problem's own solves
+  int part_cap = std::max(1, h.maxtile);
+  if (h.M <= kSmallChunkPoints) {
+    SysDesc t = h;
+    size_t sm_t = 0;
+    choose_tiles(t, kSmallChunkElems[0], 0, &sm_t);
+    part_cap = std::max(part_cap, t.maxtile);
+  }
+  const size_t o_part = take(sizeof(double) * part_cap);
   const size_t o_ctl = take(sizeof(Ctl));
   const size_t o_info = take(sizeof(DevInfo));
   const size_t o_glob = take(sizeof(Glob));
@@ -728,6 +748,7 @@ static csl_status create_problem_impl(const csl_grid *grid, const double *a_noda
   h.ctl = (Ctl *)(base + o_ctl);
   h.info = (DevInfo *)(base + o_info);
   p->glob = (Glob *)(base + o_glob);
+  p->part_cap = part_cap;
   p->d_desc = (SysDesc *)(base + o_desc);
   p->stats = (double *)(base + o_stats);
   p->stats_part = (double *)(base + o_spart);
@@ -894,6 +915,7 @@ csl_status problem_clone(csl_problem p, hipStream_t s, csl_problem *out) {
   csl_problem q = nullptr;
   csl_status st = create_problem_impl(&p->grid, p->h.a, p->h.alpha, p->h.beta, &o, s, &q, mask);
   if (st != CSL_OK) return st;
+  q->single_te = p->single_te;
   st = configure_single(q, p->tile_points, p->lds_bytes, p->block_threads, s);
   if (st != CSL_OK) {
     free_problem(q);
@@ -1024,6 +1046,7 @@ csl_status problem_schedule(csl_problem p, csl_batch_tuning *out) {
   out->lds_bytes = p->lds_bytes;
   out->grid_size = p->grid1;
   out->block_threads = p->block_threads;
+  out->tile_elems = p->single_te;
   return CSL_OK;
 }
 
@@ -1031,21 +1054,27 @@ csl_status problem_tune(csl_problem p, const double *f, double *z, csl_batch_tun
                         hipStream_t s) {
   if (!p || !f || !z) return fail(CSL_ERR_ARG, "NULL argument");
   if (f == z) return fail(CSL_ERR_ARG, "problem_tune: f and z must not alias");
-  const int tp0 = p->tile_points, lds0 = p->lds_bytes, wg0 = p->block_threads;
+  const int tp0 = p->tile_points, lds0 = p->lds_bytes, wg0 = p->block_threads,
+            te0 = p->single_te;
   const long long per_wg = std::max<long long>(1, p->h.M / std::max(1, p->cap));
   // candidates: the current schedule first, then tile sizes around one tile
-  // per workgroup with both LDS budgets and every allowed workgroup size
+  // per workgroup with both LDS budgets and every allowed workgroup size,
+  // and on small grids the smaller chunks as well
   struct Cand {
-    int tp, lds, wg;
+    int tp, lds, wg, te;
   };
   std::vector<Cand> cands;
-  cands.push_back({tp0, lds0, wg0});
+  cands.push_back({tp0, lds0, wg0, te0});
   for (int wg : {256, 512}) {
     if (wg == 512 && !p->wg512_ok) continue;
     for (int lds : {32768, 65536})
       for (long long tp : {0LL, 1LL, per_wg / 2, per_wg * 2, 8192LL})
-        if (tp >= 0 && !((int)tp == tp0 && lds == lds0 && wg == wg0))
-          cands.push_back({(int)tp, lds, wg});
+        if (tp >= 0 && !((int)tp == tp0 && lds == lds0 && wg == wg0 && te0 == 0))
+          cands.push_back({(int)tp, lds, wg, 0});
+    if (p->h.M <= kSmallChunkPoints)
+      for (int te : kSmallChunkElems)
+        for (long long tp : {0LL, 1LL, per_wg})
+          if (!((int)tp == tp0 && wg == wg0 && te == te0)) cands.push_back({(int)tp, 32768, wg, te});
   }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(hipEventCreate(&e0));
@@ -1055,10 +1084,15 @@ csl_status problem_tune(csl_problem p, const double *f, double *z, csl_batch_tun
   }
   const SolveParams P = make_params(0.0, 0, 1, 0, p->wall_khz);
   double best = INFINITY, first = INFINITY;
-  int best_tp = tp0, best_lds = lds0, best_wg = wg0, timed = 0;
+  int best_tp = tp0, best_lds = lds0, best_wg = wg0, best_te = te0, timed = 0;
   csl_status st = CSL_OK;
   for (size_t c = 0; c < cands.size() && st == CSL_OK; ++c) {
+    p->single_te = cands[c].te;
     st = configure_single(p, cands[c].tp, cands[c].lds, cands[c].wg, s);
+    if (st == CSL_ERR_ARG && cands[c].te > 0) {   // more chunks than partial-sum slots
+      st = CSL_OK;
+      continue;
+    }
     if (st != CSL_OK) break;
     if (c > 0 && p->lds_bytes != cands[c].lds) continue;   // budget not applicable
     st = run_single(p, (const double2 *)f, (double2 *)z, P, s);   // warm-up
@@ -1082,10 +1116,12 @@ csl_status problem_tune(csl_problem p, const double *f, double *z, csl_batch_tun
       best_tp = cands[c].tp;
       best_lds = p->lds_bytes;
       best_wg = p->block_threads;
+      best_te = cands[c].te;
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  p->single_te = best_te;
   const csl_status st2 = configure_single(p, best_tp, best_lds, best_wg, s);
   if (st != CSL_OK) return st;
   if (st2 != CSL_OK) return st2;
@@ -1098,6 +1134,7 @@ csl_status problem_tune(csl_problem p, const double *f, double *z, csl_batch_tun
     out->ms = best;
     out->ms_default = first;
     out->block_threads = p->block_threads;
+    out->tile_elems = p->single_te;
   }
   return CSL_OK;
 }
