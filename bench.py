@@ -387,7 +387,8 @@ def main():
     for p, f, z, s in zip(probs64, F, Z64, w.systems):
         if s.n not in plain_sched:
             t = p.tune(f, z)
-            plain_sched[s.n] = (t["tile_points"], t["lds_bytes"], t["block_threads"])
+            plain_sched[s.n] = (t["tile_points"], t["lds_bytes"], t["block_threads"],
+                                t["tile_elems"])
         else:
             p.set_schedule(*plain_sched[s.n])
     for p, f, z in zip(probs64, F, Z64):

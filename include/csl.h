@@ -169,10 +169,14 @@ csl_status problem_info(csl_problem p, double *abar, double *a_min,
  * LDS chunk per tile), the LDS line budget (0 or 32768 = default, 65536
  * = 64 KiB) and the workgroup size of the persistent solver, block_threads:
  * 0 = 512 where allowed, else 256; 256; or 512, which is allowed for
- * problems whose sine transforms all run on the FFT (CSL_ERR_ARG otherwise).
- * Batches keep their own schedule.  Synchronises s. */
+ * problems whose sine transforms all run on the FFT (CSL_ERR_ARG otherwise);
+ * tile_elems, the LDS elements of a chunk (0 = the creation-time tiling;
+ * chunks smaller than that are accepted while every tile keeps a partial-sum
+ * slot, on grids of at most 65536 points down to 512 elements; CSL_ERR_ARG
+ * otherwise, the previous schedule staying in force).  Batches keep their
+ * own schedule.  Synchronises s. */
 csl_status problem_set_schedule(csl_problem p, int tile_points, int lds_bytes,
-                                int block_threads, hipStream_t s);
+                                int block_threads, int tile_elems, hipStream_t s);
 
 /* Lanczos coefficients of the problem's last completed solve (its own
  * minres_solve / minres_adjoint, or its system within a batch_solve):
@@ -288,8 +292,8 @@ csl_status batch_solve(csl_batch b, const double *const *f, double *const *z,
 /* Autotuner of a problem's own schedule: solves (K + lambda I) z = f with
  * each candidate tile size, LDS budget and allowed workgroup size, and on
  * grids of at most 65536 points also chunks of 512 and 1024 elements (tol
- * 1e-8), timing each on stream s, and keeps the fastest (the chunk size
- * stays in force through later problem_set_schedule calls).  Blocks until done; out may be NULL (its
+ * 1e-8), timing each on stream s, and keeps the fastest
+ * (problem_set_schedule).  Blocks until done; out may be NULL (its
  * grid_size is the single-solve grid). */
 csl_status problem_tune(csl_problem p, const double *f, double *z,
                         csl_batch_tuning *out, hipStream_t s);

@@ -106,7 +106,8 @@ def load_library():
     L.destroy_problem.argtypes = [vp]
     L.problem_info.argtypes = [vp, dp, dp, dp]
     L.problem_dst_engines.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
-    L.problem_set_schedule.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]
+    L.problem_set_schedule.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                       vp]
     L.problem_schedule.argtypes = [vp, ctypes.POINTER(_BatchTuning)]
     L.batch_schedule.argtypes = [vp, ctypes.POINTER(_BatchTuning)]
     L.problem_tune.argtypes = [vp, vp, vp, ctypes.POINTER(_BatchTuning), vp]
@@ -242,10 +243,12 @@ class Problem:
         q._h = h
         return q
 
-    def set_schedule(self, tile_points: int = 0, lds_bytes: int = 0, block_threads: int = 0):
+    def set_schedule(self, tile_points: int = 0, lds_bytes: int = 0, block_threads: int = 0,
+                     tile_elems: int = 0):
         """Schedule of this problem's own solves (see problem_set_schedule)."""
         _check(load_library().problem_set_schedule(self.handle, int(tile_points), int(lds_bytes),
-                                                   int(block_threads), _stream(self.device)))
+                                                   int(block_threads), int(tile_elems),
+                                                   _stream(self.device)))
 
     @property
     def schedule(self) -> dict:

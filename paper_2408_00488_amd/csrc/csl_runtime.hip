@@ -1027,16 +1027,21 @@ csl_status minres_solve(csl_problem p, const double *f, double *z, const csl_sol
 }
 
 csl_status problem_set_schedule(csl_problem p, int tile_points, int lds_bytes, int block_threads,
-                                hipStream_t s) {
+                                int tile_elems, hipStream_t s) {
   if (!p) return fail(CSL_ERR_ARG, "problem is NULL");
   if (tile_points < 0) return fail(CSL_ERR_ARG, "tile_points must be >= 0");
+  if (tile_elems < 0) return fail(CSL_ERR_ARG, "tile_elems must be >= 0");
   if (lds_bytes != 0 && lds_bytes != 32768 && lds_bytes != 65536)
     return fail(CSL_ERR_ARG, "lds_bytes must be 0, 32768 or 65536");
   if (!valid_block_threads(block_threads))
     return fail(CSL_ERR_ARG, "block_threads must be 0, 256 or 512");
   if (block_threads == 512 && !p->wg512_ok)
     return fail(CSL_ERR_ARG, "block_threads 512 needs the FFT engine on every axis");
-  return configure_single(p, tile_points, lds_bytes, block_threads, s);
+  const int te0 = p->single_te;
+  p->single_te = tile_elems;
+  const csl_status st = configure_single(p, tile_points, lds_bytes, block_threads, s);
+  if (st != CSL_OK) p->single_te = te0;   // the previous schedule stays in force
+  return st;
 }
 
 csl_status problem_schedule(csl_problem p, csl_batch_tuning *out) {

@@ -257,3 +257,31 @@ def test_problems_from_several_threads(csl):
     assert not errors, errors
     for (zr, ir), (z, i) in zip(ref, out):
         assert i == ir and torch.equal(z, zr)
+
+
+def test_chunk_size_schedule(csl):
+    # small grids may run their own solves on 512- or 1024-element chunks;
+    # a chunking with more tiles than partial-sum slots is refused and the
+    # schedule in force stays
+    shape, lam = (63, 63), complex(12.0, 30.0)
+    a = _coef(shape, 80)
+    f = _crand(shape, 81)
+    p = csl.Problem(cuda(a), lam.real, lam.imag)
+    po = O.Problem(a, lam.real, lam.imag, abar_rule="given", abar=p.abar)
+    zo, io = po.solve(f)
+    for te in (512, 1024, 0):
+        p.set_schedule(0, 0, 0, te)
+        assert p.schedule["tile_elems"] == te
+        z, info = csl.minres_solve(p, cuda(f))
+        assert info["status"] == 0
+        assert _vs_oracle(po, lam, f, z.cpu().numpy(), info, zo, io) <= 1e-10
+    p.set_schedule(0, 0, 0, 512)
+    before = p.schedule
+    with pytest.raises(csl.CSLError, match="ERR_ARG"):
+        p.set_schedule(0, 0, 0, 16)
+    assert p.schedule == before
+    p.close()
+    big = csl.Problem(cuda(_coef((511, 511), 82)), 1.0, 1.0)
+    with pytest.raises(csl.CSLError, match="ERR_ARG"):
+        big.set_schedule(0, 0, 0, 512)
+    big.close()
