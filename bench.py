@@ -212,6 +212,34 @@ def other_configs(C, WL, dev):
                          "max_relres": worst}
     out["paradiag"] = paradiag_config(C, WL, dev)
     out["many_rhs"] = many_rhs_config(C, WL, dev)
+    out["paper_table2a"] = table2a_config(C, WL, dev)
+    return out
+
+
+# The paper's Octave times per solve for Example 2 at the shift -100 + 100i
+# (Table 2(a); GNU Octave 8.2 on two 16-core Xeon Gold 6246R, FP64): context
+# for the same workload here, not a target.
+PAPER_TABLE2A_S = {63: 0.028, 255: 0.25, 1023: 4.47}
+
+
+def table2a_config(C, WL, dev, alpha=-100.0, beta=100.0):
+    """Example 2 of the paper (a = (20 + x^2)(20 + y^2) on the unit square,
+    abar = sqrt(a_min a_max), FP64, tol 1e-8) at the sizes of Table 2(a)
+    that the grids admit: one tuned single solve each."""
+    import torch
+    out = {"shift": [alpha, beta], "paper_octave_s_per_solve": PAPER_TABLE2A_S}
+    g = WL.rng(8)
+    for n in (63, 255, 1023):
+        a = torch.from_numpy(WL.coef_paper_ex2(n)).to(dev)
+        f = torch.from_numpy(WL.complex_normal(g, (n, n))).to(dev)
+        z = torch.empty_like(f)
+        p = C.Problem(a, alpha, beta, abar_rule="geomean")
+        p.tune(f, z)
+        ms, info = time_solve(C, p, f, z, 10)
+        out[str(n)] = {"ms_per_solve": ms, "iters": info["iters"],
+                       "relres_true": info["relres_true"],
+                       "paper_time_over_gpu_time": PAPER_TABLE2A_S[n] * 1e3 / ms}
+        p.close()
     return out
 
 
