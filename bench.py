@@ -213,6 +213,32 @@ def other_configs(C, WL, dev):
     out["paradiag"] = paradiag_config(C, WL, dev)
     out["many_rhs"] = many_rhs_config(C, WL, dev)
     out["paper_table2a"] = table2a_config(C, WL, dev)
+    out["paper_table1a"] = table1a_config(C, WL, dev)
+    return out
+
+
+# The paper's Octave times per solve with a = 1 (the preconditioner is then
+# |A| itself, two steps) at the shift -100 + 100i (Table 1(a)): context.
+PAPER_TABLE1A_S = {63: 0.0073, 255: 0.054, 1023: 0.83}
+
+
+def table1a_config(C, WL, dev, alpha=-100.0, beta=100.0):
+    """Example 1 of the paper: a = 1, FP64, tol 1e-8, at the sizes of Table
+    1(a) that the grids admit: one tuned single solve each."""
+    import torch
+    out = {"shift": [alpha, beta], "paper_octave_s_per_solve": PAPER_TABLE1A_S}
+    g = WL.rng(9)
+    for n in (63, 255, 1023):
+        a = torch.ones((n, n), dtype=torch.float64, device=dev)
+        f = torch.from_numpy(WL.complex_normal(g, (n, n))).to(dev)
+        z = torch.empty_like(f)
+        p = C.Problem(a, alpha, beta)
+        p.tune(f, z)
+        ms, info = time_solve(C, p, f, z, 10)
+        out[str(n)] = {"ms_per_solve": ms, "iters": info["iters"],
+                       "relres_true": info["relres_true"],
+                       "paper_time_over_gpu_time": PAPER_TABLE1A_S[n] * 1e3 / ms}
+        p.close()
     return out
 
 
