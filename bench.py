@@ -364,8 +364,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this solver runs on one GPU only; multi-GPU runs are "
-                                   "not part of this build (shard by system across GPUs)"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; several GPUs would each "
+                                   "solve their own share of the batch, which is not implemented"}))
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
