@@ -285,3 +285,27 @@ def test_chunk_size_schedule(csl):
     with pytest.raises(csl.CSLError, match="ERR_ARG"):
         big.set_schedule(0, 0, 0, 512)
     big.close()
+
+
+def test_batch_isolates_degenerate_systems(csl):
+    # a zero right-hand side finishes at step 0, a NaN one with
+    # ERR_NONFINITE; the other systems of the same launch converge as alone
+    shapes = [(31, 31), (63, 63), (15, 15, 15), (31, 63)]
+    probs = [csl.Problem(cuda(_coef(s, 90 + j)), 9.0, 33.0) for j, s in enumerate(shapes)]
+    fs_h = [_crand(s, 95 + j) for j, s in enumerate(shapes)]
+    fs_h[1] = np.zeros(shapes[1], dtype=np.complex128)
+    fs_h[2] = fs_h[2].copy()
+    fs_h[2][3, 4, 5] = np.nan
+    b = csl.Batch(probs, timeout_ms=30000)
+    zs, infos = b.solve([cuda(f) for f in fs_h], raise_on_error=False)
+    assert infos[1]["status"] == 0 and infos[1]["iters"] == 0 and not zs[1].abs().sum().item()
+    assert infos[2]["status_name"] == "ERR_NONFINITE"
+    for j in (0, 3):
+        z1, i1 = csl.minres_solve(probs[j], cuda(fs_h[j]))
+        assert infos[j]["status"] == 0 and abs(infos[j]["iters"] - i1["iters"]) <= 1
+        assert float((zs[j] - z1).abs().max() / z1.abs().max()) <= 1e-9
+    with pytest.raises(csl.CSLError, match="ERR_NONFINITE"):
+        b.solve([cuda(f) for f in fs_h])
+    b.close()
+    for p in probs:
+        p.close()
