@@ -196,6 +196,12 @@ csl_status problem_lanczos(csl_problem p, double *delta, double *gamma, int cap,
  * of cap entries; *count = k.  Synchronises s. */
 csl_status problem_ritz(csl_problem p, double *theta, int cap, int *count, hipStream_t s);
 
+/* Host utility (no device work): the eigenvalues of the symmetric
+ * tridiagonal matrix with diagonal d[0..k-1] and off-diagonal e[0..k-2],
+ * ascending, into theta[0..k-1] (host arrays), by the bisection that
+ * problem_ritz uses.  k >= 0; pointers may be NULL when k = 0. */
+csl_status csl_tridiagonal_eigenvalues(const double *d, const double *e, int k, double *theta);
+
 /* Sine-transform engine in use along each axis (CSL_DST_FFT or
  * CSL_DST_GEMM; entries past the grid's dimension are CSL_DST_FFT). */
 csl_status problem_dst_engines(csl_problem p, int engines[3]);

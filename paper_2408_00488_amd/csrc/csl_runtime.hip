@@ -940,6 +940,19 @@ csl_status problem_lanczos(csl_problem p, double *delta, double *gamma, int cap,
   return CSL_OK;
 }
 
+csl_status csl_tridiagonal_eigenvalues(const double *d, const double *e, int k, double *theta) {
+  if (k < 0 || (k > 0 && (!d || !theta)) || (k > 1 && !e))
+    return fail(CSL_ERR_ARG, "NULL argument or negative size");
+  std::vector<double> dv(d, d + k), ev, th;
+  if (k > 1) ev.assign(e, e + (k - 1));
+  for (int i = 0; i < k; ++i)
+    if (!std::isfinite(dv[i]) || (i + 1 < k && !std::isfinite(ev[i])))
+      return fail(CSL_ERR_ARG, "entries must be finite");
+  tridiag_eigenvalues(dv, ev, th);
+  for (int i = 0; i < k; ++i) theta[i] = th[i];
+  return CSL_OK;
+}
+
 csl_status problem_ritz(csl_problem p, double *theta, int cap, int *count, hipStream_t s) {
   if (!p || !count || cap < 0 || (cap > 0 && !theta))
     return fail(CSL_ERR_ARG, "NULL argument or negative capacity");

@@ -82,3 +82,31 @@ def test_null_handles_rejected(lib):
     assert lib.destroy_problem(None) == 1
     assert lib.batch_destroy(None) == 1
     assert lib.batch_create(None, 0, None, ctypes.byref(ctypes.c_void_p())) == 1
+
+
+def test_tridiagonal_eigenvalues_against_scipy(lib):
+    # the host bisection behind problem_ritz, against SciPy's tridiagonal
+    # eigensolver: random, clustered and repeated spectra, the sizes 0 and 1
+    import numpy as np
+    import scipy.linalg as sla
+    dp = ctypes.POINTER(ctypes.c_double)
+    f = lib.csl_tridiagonal_eigenvalues
+    f.argtypes = [dp, dp, ctypes.c_int, dp]
+    f.restype = ctypes.c_int
+    g = np.random.default_rng(5)
+    cases = [(g.standard_normal(50), g.standard_normal(49)),
+             (np.ones(40) + 1e-9 * g.standard_normal(40), 1e-6 * g.standard_normal(39)),
+             (np.full(30, 2.0), np.zeros(29)),
+             (g.uniform(-1, 1, 400), g.uniform(0.5, 1.0, 399)),
+             (np.array([3.5]), np.zeros(0))]
+    for d, e in cases:
+        d = np.ascontiguousarray(d, dtype=np.float64)
+        e = np.ascontiguousarray(e, dtype=np.float64)
+        th = np.empty(d.size)
+        assert f(d.ctypes.data_as(dp), e.ctypes.data_as(dp), d.size, th.ctypes.data_as(dp)) == 0
+        ref = sla.eigvalsh_tridiagonal(d, e) if d.size > 1 else d
+        scale = max(1.0, np.abs(ref).max())
+        assert np.all(np.diff(th) >= 0)
+        assert np.abs(th - ref).max() <= 1e-13 * scale, (d.size, np.abs(th - ref).max())
+    assert f(None, None, 0, None) == 0
+    assert f(None, None, -1, None) == 1
