@@ -21,10 +21,10 @@
  * interior grid node in C order (last axis contiguous).  The real block
  * vector [x1; x2] is stored as x1 + i x2.  The nodal coefficient is a DEVICE
  * array of M doubles in the same order.  Grid axis k has n[k] interior
- * points, mesh width h_k = length[k] / (n[k] + 1): n[k] + 1 a power of two
- * with 4 <= n[k] + 1 <= 1024 (n in {3, 7, ..., 1023}; the sine transform
- * along the axis by the LDS FFT or the dense sine matrix), or any
- * 3 <= n[k] <= 127 (the dense sine matrix on the matrix cores only).
+ * points, mesh width h_k = length[k] / (n[k] + 1), 3 <= n[k] <= 1023.  With
+ * n[k] + 1 a power of two the sine transform along the axis runs as the LDS
+ * FFT or the dense sine matrix; any other n[k] takes the dense sine matrix
+ * on the matrix cores only, whose cost grows as n[k]^2 per line.
  *
  * Ownership.  The caller owns every vector and coefficient buffer and keeps
  * it alive while work that uses it is queued.  A problem handle owns a copy
@@ -104,8 +104,8 @@ enum {
                                power of two)                               */
     CSL_DST_GEMM = 2        /* product with the dense n x n sine matrix on
                                the matrix cores, for axes with
-                               15 <= n <= 127 or n + 1 not a power of two;
-                               FFT on the other axes                       */
+                               15 <= n <= 127 or n + 1 not a power of two
+                               (any n up to 1022); FFT on the other axes   */
 };
 
 typedef struct csl_problem_opts {

@@ -651,7 +651,7 @@ __device__ __forceinline__ double2 stencil_K(const SysDesc &S, const CSL_G doubl
 
 
 // ---------------------------------------------------------------------------
-// Dense sine-matrix transform on MFMA (lines of n <= 127 points).
+// Dense sine-matrix transform on MFMA (lines of up to 1022 points).
 // A chunk of lp complex lines is the real matrix X (np x 2 lp, np = n
 // rounded up to 16; column 2l = Re of line l, 2l+1 = Im) stored in LDS as
 // complex lines of np entries (rows n..np-1 zero).  Y = W X with W the

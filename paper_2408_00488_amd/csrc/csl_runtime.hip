@@ -75,14 +75,16 @@ int ilog2(int v) {
 }
 
 // Axes whose sine transform may run as a dense matrix product on the matrix
-// cores: n <= 127 keeps the n^2 products per line within reach of the FFT's
-// cost.  With n + 1 a power of two (n >= 15) the padded length np = n + 1
-// keeps the two LDS operands of a chunk (2 lp np elements) inside the FFT's
-// lp L budget, L = 2(n + 1).  An axis with n + 1 not a power of two has no
-// FFT here and must take the matrix product (3 <= n <= 127).
+// cores: with n + 1 a power of two, n <= 127 keeps the n^2 products per line
+// within reach of the FFT's cost, and the padded length np = n + 1 keeps the
+// two LDS operands of a chunk (2 lp np elements) inside the FFT's lp L
+// budget, L = 2(n + 1).  An axis with n + 1 not a power of two has no FFT
+// here and must take the matrix product, for any 3 <= n <= 1022: its two
+// operands take 2 np <= 2048 elements a line, the FFT's largest line, at a
+// cost that grows as n^2 per line.
 bool pow2_axis(int n) { return ((n + 1) & n) == 0; }
 bool gemm_required(int n) { return !pow2_axis(n); }
-bool gemm_eligible(int n) { return (n >= 15 && n <= 127) || (gemm_required(n) && n <= 127); }
+bool gemm_eligible(int n) { return (n >= 15 && n <= 127) || gemm_required(n); }
 int gemm_pad(int n) { return (n + 15) & ~15; }
 // LDS elements a line of an axis takes: the FFT's odd extension 2(n + 1),
 // or both GEMM operands 2 np where that is larger (n + 1 not a power of two)
@@ -617,9 +619,8 @@ static csl_status create_problem_impl(const csl_grid *grid, const double *a_noda
   for (int ax = 0; ax < 3; ++ax) {
     if (ax < h.d) {
       const int n = grid->n[ax];
-      if (n < 3 || n > TWN / 2 - 1 || (!pow2_axis(n) && n > 127))
-        return fail(CSL_ERR_ARG, "n[" + std::to_string(ax) +
-                                     "] must be between 3 and 127, or n + 1 a power of two up to 1024");
+      if (n < 3 || n > TWN / 2 - 1)
+        return fail(CSL_ERR_ARG, "n[" + std::to_string(ax) + "] must be between 3 and 1023");
       const double len = grid->length[ax] > 0 ? grid->length[ax] : 1.0;
       if (!std::isfinite(len)) return fail(CSL_ERR_ARG, "length must be finite");
       const double hh = len / (n + 1);

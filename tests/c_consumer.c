@@ -20,7 +20,7 @@ int main(void) {
     csl_problem p = NULL;
     if (create_problem(NULL, NULL, 1.0, 1.0, NULL, 0, &p) != CSL_ERR_ARG || p != NULL) return 4;
     if (strlen(csl_last_error()) == 0) return 5;
-    csl_grid g = {2, {7, 200, 0}, {1.0, 1.0, 0.0}};
+    csl_grid g = {2, {7, 1500, 0}, {1.0, 1.0, 0.0}};
     if (create_problem(&g, (const double *)0x1000, 1.0, 1.0, NULL, 0, &p) != CSL_ERR_ARG) return 6;
     printf("ok\n");
     return 0;

@@ -52,9 +52,10 @@ def _grid(dim, n, length=1.0):
     return g
 
 
-@pytest.mark.parametrize("dim,n,msg", [(4, (7, 7), "dim"), (2, (200, 7), "power of two"),
-                                       (2, (7, 2047), "power of two"), (3, (7, 7, 1), "power of two"),
-                                       (2, (2, 7), "power of two"), (2, (128, 7), "power of two")])
+@pytest.mark.parametrize("dim,n,msg", [(4, (7, 7), "dim"), (2, (1024, 7), "between 3 and 1023"),
+                                       (2, (7, 2047), "between 3 and 1023"),
+                                       (3, (7, 7, 1), "between 3 and 1023"),
+                                       (2, (2, 7), "between 3 and 1023"), (2, (7, 1500), "between 3 and 1023")])
 def test_create_problem_rejects_bad_grid(lib, dim, n, msg):
     h = ctypes.c_void_p()
     g = _grid(dim, n)
