@@ -654,11 +654,16 @@ __device__ __forceinline__ double2 stencil_K(const SysDesc &S, const CSL_G doubl
 // Dense sine-matrix transform on MFMA (lines of up to 1022 points).
 // A chunk of lp complex lines is the real matrix X (np x 2 lp, np = n
 // rounded up to 16; column 2l = Re of line l, 2l+1 = Im) stored in LDS as
-// complex lines of np entries (rows n..np-1 zero).  Y = W X with W the
-// padded orthonormal DST-I matrix (np x np, symmetric, in global memory),
-// on 16x16x4 MFMA tiles: lane l feeds A[l%16][l/16] and B[l/16][l%16];
-// the accumulator row of register r is 4r + l/16 (FP64) or 4(l/16) + r
-// (FP32), its column l%16.
+// complex lines of np entries.  Y = W X with W the orthonormal DST-I matrix,
+// which satisfies W[n-1-m][k] = (-1)^k W[m][k]: for the first h = ceil(n/2)
+// rows, E = sum over even k and O = sum over odd k give Y[m] = E + O and
+// Y[n-1-m] = E - O, half the products and half the matrix reads of the
+// plain product.  The matrix is stored as two hp x hp blocks (hp = h rounded
+// up to 16; global memory, zero padded): We[m][j] = W[m][2j] followed by
+// Wo[m][j] = W[m][2j+1].  16x16x4 MFMA tiles: lane l feeds A[l%16][l/16]
+// and B[l/16][l%16]; the accumulator row of register r is 4r + l/16 (FP64)
+// or 4(l/16) + r (FP32), its column l%16.  X rows n..np-1 are never read and
+// Y rows n..np-1 never written.
 // ---------------------------------------------------------------------------
 typedef double mfma_d4 __attribute__((ext_vector_type(4)));
 typedef float mfma_f4 __attribute__((ext_vector_type(4)));
@@ -679,18 +684,23 @@ template <> struct Mfma<float> {
   static __device__ __forceinline__ int row(int r, int lane) { return 4 * (lane >> 4) + r; }
 };
 
-// Y = W X for a chunk of lp lines of padded length np (X, Y in LDS).  The
-// real and imaginary parts of a line are two columns of X; each wave owns
-// 16 x 16 output blocks and streams the K dimension in steps of 4, taking
-// W from the cache hierarchy and X from LDS, so that only a handful of
-// registers are live beside the accumulator.
+__device__ __forceinline__ int gemm_np(int n) { return (n + 15) & ~15; }
+__device__ __forceinline__ int gemm_hp(int n) { return (((n + 1) >> 1) + 15) & ~15; }
+
+// Y = W X for a chunk of lp lines of n points, padded length np (X, Y in
+// LDS).  The real and imaginary parts of a line are two columns of X; each
+// wave owns 16 x 16 output blocks of the first h rows and streams the even
+// and odd halves of K in steps of 4, taking W from the cache hierarchy and X
+// from LDS.
 template <typename R>
-__device__ __forceinline__ void gemm_lines(const Cx<R> *X, Cx<R> *Y, int np, int lp, const R *__restrict__ W) {
-  constexpr int KU = 4;   // K steps in flight
+__device__ __forceinline__ void gemm_lines(const Cx<R> *X, Cx<R> *Y, int n, int np, int lp,
+                                           const R *__restrict__ W) {
+  constexpr int KU = 4;   // K steps in flight per half
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int nrb = np >> 4;
+  const int h = (n + 1) >> 1, hp = gemm_hp(n);
+  const int nrb = hp >> 4;
   const int ncb = (2 * lp + 15) >> 4;
-  const int kq = np >> 2;   // multiple of KU since np is a multiple of 16
+  const int kq = hp >> 2;   // multiple of KU since hp is a multiple of 16
   const R *Xr = reinterpret_cast<const R *>(X);
   R *Yr = reinterpret_cast<R *>(Y);
   const int kl = lane >> 4;
@@ -700,23 +710,37 @@ __device__ __forceinline__ void gemm_lines(const Cx<R> *X, Cx<R> *Y, int np, int
     const int col = cb * 16 + (lane & 15);
     const bool valid = col < 2 * lp;
     const int line = valid ? (col >> 1) : 0, part = col & 1;
-    const CSL_G R *wrow = gbl(W) + m * np + kl;
-    const R *xcol = Xr + (line * np + kl) * 2 + part;
-    typename Mfma<R>::acc c = {0, 0, 0, 0};
+    const CSL_G R *we = gbl(W) + m * hp + kl;
+    const CSL_G R *wo = we + hp * hp;
+    // even k = 2 (kl + 4 s), odd k = that + 1; element k of the line at 2k
+    const R *xe = Xr + (line * np + 2 * kl) * 2 + part;
+    typename Mfma<R>::acc ce = {0, 0, 0, 0}, co = {0, 0, 0, 0};
     for (int kk = 0; kk < kq; kk += KU) {
-      R a[KU], b[KU];
+      R ae[KU], ao[KU], be[KU], bo[KU];
 #pragma unroll
       for (int u = 0; u < KU; ++u) {
-        a[u] = wrow[(kk + u) * 4];
-        b[u] = valid ? xcol[(kk + u) * 8] : (R)0;
+        const int k = 2 * kl + 8 * (kk + u);
+        ae[u] = we[(kk + u) * 4];
+        ao[u] = wo[(kk + u) * 4];
+        be[u] = (valid && k < n) ? xe[(kk + u) * 16] : (R)0;
+        bo[u] = (valid && k + 1 < n) ? xe[(kk + u) * 16 + 2] : (R)0;
       }
 #pragma unroll
-      for (int u = 0; u < KU; ++u) c = Mfma<R>::step(a[u], b[u], c);
+      for (int u = 0; u < KU; ++u) {
+        ce = Mfma<R>::step(ae[u], be[u], ce);
+        co = Mfma<R>::step(ao[u], bo[u], co);
+      }
     }
     if (valid) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        Yr[(line * np + rb * 16 + Mfma<R>::row(r, lane)) * 2 + part] = c[r];
+      for (int r = 0; r < 4; ++r) {
+        const int mr = rb * 16 + Mfma<R>::row(r, lane);
+        if (mr < h) {
+          Yr[(line * np + mr) * 2 + part] = ce[r] + co[r];
+          const int mm = n - 1 - mr;
+          if (mm != mr) Yr[(line * np + mm) * 2 + part] = ce[r] - co[r];
+        }
+      }
     }
   }
   __syncthreads();
@@ -769,7 +793,6 @@ template <typename R, int LDSB> struct FftEng {
   }
 };
 
-__device__ __forceinline__ int gemm_np(int n) { return (n + 15) & ~15; }
 
 template <typename R, int LDSB> struct GemmEng {
   template <int U, class Load>
@@ -838,7 +861,7 @@ template <typename R, int LDSB> struct GemmEng {
                                                      const Cx<R> *, const R *W) {
     const int np = gemm_np(t.n);
     Cx<R> *Y = buf + t.lp * np;
-    gemm_lines<R>(buf, Y, np, t.lp, W);
+    gemm_lines<R>(buf, Y, t.n, np, t.lp, W);
     return Y;
   }
   template <class Scale>
@@ -861,7 +884,7 @@ template <typename R, int LDSB> struct GemmEng {
       }
     }
     __syncthreads();
-    gemm_lines<R>(Y, buf, np, t.lp, W);
+    gemm_lines<R>(Y, buf, t.n, np, t.lp, W);
     *out = buf;
     return acc;
   }

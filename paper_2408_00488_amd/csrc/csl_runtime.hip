@@ -90,16 +90,34 @@ int gemm_pad(int n) { return (n + 15) & ~15; }
 // or both GEMM operands 2 np where that is larger (n + 1 not a power of two)
 int line_elems(int n) { return pow2_axis(n) ? 2 * (n + 1) : 2 * std::max(n + 1, gemm_pad(n)); }
 
-// Orthonormal DST-I matrix sqrt(2/(n+1)) sin(pi (m+1)(k+1)/(n+1)), zero
-// padded to np x np; the angle is reduced exactly in integers first.
-void sine_matrix(int n, int np, std::vector<double> &W) {
-  W.assign((size_t)np * np, 0.0);
-  const int N2 = 2 * (n + 1);
-  const double sc = std::sqrt(2.0 / (n + 1));
-  for (int m = 0; m < n; ++m)
-    for (int k = 0; k < n; ++k) {
-      const int j = ((m + 1) * (k + 1)) % N2;
-      W[(size_t)m * np + k] = sc * std::sin(M_PI * (double)j / (double)(n + 1));
+// Orthonormal DST-I matrix entry sqrt(2/(n+1)) sin(pi (m+1)(k+1)/(n+1)),
+// the angle reduced exactly in integers to [0, pi/2] first (exact zeros
+// where (m+1)(k+1) is a multiple of n + 1).
+double sine_entry(int n, int m, int k) {
+  const int N1 = n + 1;
+  int j = ((m + 1) * (k + 1)) % (2 * N1);
+  double sg = 1.0;
+  if (j >= N1) {
+    j -= N1;
+    sg = -1.0;
+  }
+  if (j == 0) return 0.0;
+  j = std::min(j, N1 - j);
+  return sg * std::sqrt(2.0 / N1) * std::sin(M_PI * (double)j / (double)N1);
+}
+
+// The matrix as the kernels take it: since W[n-1-m][k] = (-1)^k W[m][k],
+// only rows m < h = ceil(n/2) are kept, split by the parity of k into two
+// hp x hp blocks (hp = h rounded up to 16, zero padded):
+// We[m][j] = W[m][2j], then Wo[m][j] = W[m][2j+1].
+int gemm_half(int n) { return (((n + 1) / 2) + 15) & ~15; }
+void sine_matrix(int n, std::vector<double> &W) {
+  const int h = (n + 1) / 2, hp = gemm_half(n);
+  W.assign((size_t)2 * hp * hp, 0.0);
+  for (int m = 0; m < h; ++m)
+    for (int j = 0; j < h; ++j) {
+      if (2 * j < n) W[(size_t)m * hp + j] = sine_entry(n, m, 2 * j);
+      if (2 * j + 1 < n) W[(size_t)hp * hp + (size_t)m * hp + j] = sine_entry(n, m, 2 * j + 1);
     }
 }
 
@@ -722,9 +740,9 @@ static csl_status create_problem_impl(const csl_grid *grid, const double *a_noda
     if (!gemm_eligible(h.n[ax])) continue;
     elig |= 1 << ax;
     if (gemm_required(h.n[ax])) req |= 1 << ax;
-    const size_t np2 = (size_t)gemm_pad(h.n[ax]) * gemm_pad(h.n[ax]);
-    o_w[ax] = take(sizeof(double) * np2);
-    o_wf[ax] = take(sizeof(float) * np2);
+    const size_t wsz = (size_t)2 * gemm_half(h.n[ax]) * gemm_half(h.n[ax]);
+    o_w[ax] = take(sizeof(double) * wsz);
+    o_wf[ax] = take(sizeof(float) * wsz);
   }
   hipError_t e = hipMalloc(&p->mem, off);
   if (e != hipSuccess) {
@@ -795,8 +813,7 @@ static csl_status create_problem_impl(const csl_grid *grid, const double *a_noda
   std::vector<float> Wtf[3];
   for (int ax = 0; ax < h.d; ++ax) {
     if (!(elig >> ax & 1)) continue;
-    const int np = gemm_pad(h.n[ax]);
-    sine_matrix(h.n[ax], np, Wt[ax]);
+    sine_matrix(h.n[ax], Wt[ax]);
     Wtf[ax].resize(Wt[ax].size());
     for (size_t i = 0; i < Wt[ax].size(); ++i) Wtf[ax][i] = (float)Wt[ax][i];
     PCHK(hipMemcpyAsync((void *)h.Wm[ax], Wt[ax].data(), sizeof(double) * Wt[ax].size(),

@@ -49,8 +49,10 @@ def main():
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) / args.reps * 1e3
     iters = sum(i["iters"] for i in infos)
-    np_ = (n + 15) // 16 * 16
-    flops = 4 * n * 4 * np_ * np_ * iters if args.engine == "gemm" else 0
+    # per line transform: re and im columns, even and odd halves of the first
+    # ceil(n/2) rows (padded to hp), 2 flops per product; 4 passes of n lines
+    hp = ((n + 1) // 2 + 15) // 16 * 16
+    flops = 4 * n * 8 * hp * hp * iters if args.engine == "gemm" else 0
     print(json.dumps({"engine": args.engine, "n": n, "count": cnt, "fp32": args.fp32,
                       "engines": list(probs[0].dst_engines), "ms_per_solve": ms,
                       "solves_per_s": cnt / ms * 1e3, "iters": iters,
