@@ -41,6 +41,22 @@ def test_dst_equals_dense_sine_matrix(n):
     assert np.allclose(W @ W, np.eye(n), atol=1e-13)
 
 
+@pytest.mark.parametrize("n", [3, 4, 12, 45, 200])
+def test_dst_row_reflection(n):
+    # The DST-I matrix satisfies W[n-1-m][k] = (-1)^k W[m][k] (0-based): the
+    # even-k and odd-k partial sums E, O of row m give the transform at m
+    # (E + O) and at n-1-m (E - O).  Brute-force sums, checked against the
+    # oracle's DST.
+    x = _crand(n, 3 * n)
+    c = math.sqrt(2.0 / (n + 1))
+    y = O.dst1(x)
+    for m in range((n + 1) // 2):
+        E = sum(c * math.sin(math.pi * (m + 1) * (k + 1) / (n + 1)) * x[k] for k in range(0, n, 2))
+        Od = sum(c * math.sin(math.pi * (m + 1) * (k + 1) / (n + 1)) * x[k] for k in range(1, n, 2))
+        assert abs(y[m] - (E + Od)) <= 1e-12
+        assert abs(y[n - 1 - m] - (E - Od)) <= 1e-12
+
+
 @pytest.mark.parametrize("n", [3, 7, 16, 31, 45])
 def test_mu_closed_form_and_diagonalisation(n):
     # Section 2.3: W L W = Lambda with positive diagonal.
