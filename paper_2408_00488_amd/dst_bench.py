@@ -4,8 +4,9 @@ Solves `count` copies of a 2-D system on an n x n grid (coefficient and
 shifts as in the batched-shift workload) in one batched launch with every
 axis on the chosen engine, and prints one JSON line: time per batched
 solve, solves/s, iterations, and the matrix-core flops the GEMM engine
-issues per solve (4 np^2 per line transform, np = n rounded up to 16; four
-line transforms of n lines per iteration in 2-D).  Used to pick the engine
+issues per solve (8 hp^2 per line transform, hp = ceil(n/2) rounded up to
+16: re and im columns times the even and odd halves of the first ceil(n/2)
+rows; four line transforms of n lines per iteration in 2-D).  Used to pick the engine
 per axis by measurement and to read MFMA utilisation under rocprofv3.
 
   python -m paper_2408_00488_amd.dst_bench --engine gemm --n 127 --count 64 [--fp32]
