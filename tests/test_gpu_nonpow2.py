@@ -171,3 +171,35 @@ def test_adjoint_non_power_of_two(csl):
     assert g["alpha"].item() == pytest.approx(go["alpha"], rel=1e-9)
     assert g["beta"].item() == pytest.approx(go["beta"], rel=1e-9)
     p.close()
+
+
+def test_batch_with_long_sine_matrix_lines(csl):
+    # lines past 511 points take the 64 KiB tiles; the batch shares one
+    # launch with short-line and power-of-two systems
+    shapes = [(1000, 9), (9, 600), (63, 63), (200, 45), (15, 31, 700)]
+    probs, refs = [], []
+    for j, shape in enumerate(shapes):
+        a = _coef(shape, 40 + j)
+        f = _crand(shape, 50 + j)
+        lam = complex(8.0 + j, 35.0)
+        p = csl.Problem(cuda(a), lam.real, lam.imag, pinv_fp32=(j % 2 == 1))
+        probs.append(p)
+        refs.append((a, lam, f, p.abar, p.pinv_fp32))
+    b = csl.Batch(probs, timeout_ms=60000)
+    zs, infos = b.solve([cuda(r[2]) for r in refs])
+    for (a, lam, f, abar, fp32), z, info in zip(refs, zs, infos):
+        po = O.Problem(a, lam.real, lam.imag, abar_rule="given", abar=abar)
+        assert info["status"] == 0
+        zg = z.cpu().numpy()
+        if fp32:
+            r = f - O.apply_A(po.K, lam.real, lam.imag, np.conj(zg))
+            assert np.linalg.norm(r) / np.linalg.norm(f) <= 1.01e-8
+            continue
+        zo, io = po.solve(f)
+        assert abs(info["iters"] - io["iters"]) <= 1
+        zf = zo if info["iters"] == io["iters"] else po.solve(f, fixed_iters=info["iters"])[0]
+        _say(a.shape, info["iters"], rel(zg, zf))
+        assert rel(zg, zf) <= 1e-10
+    b.close()
+    for p in probs:
+        p.close()
