@@ -299,8 +299,11 @@ csl_status batch_solve(csl_batch b, const double *const *f, double *const *z,
  * each candidate tile size, LDS budget and allowed workgroup size, and on
  * grids of at most 65536 points also chunks of 512 and 1024 elements (tol
  * 1e-8), timing each on stream s, and keeps the fastest
- * (problem_set_schedule).  Blocks until done; out may be NULL (its
- * grid_size is the single-solve grid). */
+ * (problem_set_schedule).  With dst_engine CSL_DST_AUTO and a matrix-core
+ * axis that also has an FFT, the candidates are timed with the FFT on such
+ * axes as well, and the engines of the fastest are kept
+ * (problem_dst_engines reports them).  Blocks until done; out may be NULL
+ * (its grid_size is the single-solve grid). */
 csl_status problem_tune(csl_problem p, const double *f, double *z,
                         csl_batch_tuning *out, hipStream_t s);
 

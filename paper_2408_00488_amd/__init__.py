@@ -219,10 +219,14 @@ class Problem:
         ab, mn, mx = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         _check(L.problem_info(h, ctypes.byref(ab), ctypes.byref(mn), ctypes.byref(mx)))
         self.abar, self.a_min, self.a_max = ab.value, mn.value, mx.value
+        self._dim = g.dim
+        self._read_engines()
+
+    def _read_engines(self):
         eng = (ctypes.c_int * 3)()
-        _check(L.problem_dst_engines(h, eng))
+        _check(load_library().problem_dst_engines(self._h, eng))
         #: sine-transform engine per axis: "fft" or "gemm"
-        self.dst_engines = tuple(_DST_NAMES[eng[k]] for k in range(g.dim))
+        self.dst_engines = tuple(_DST_NAMES[eng[k]] for k in range(self._dim))
 
     @property
     def handle(self):
@@ -293,6 +297,7 @@ class Problem:
         t = _BatchTuning()
         _check(load_library().problem_tune(self.handle, _ptr(f), _ptr(z), ctypes.byref(t),
                                            _stream(self.device)))
+        self._read_engines()   # the tuner may move a matrix-core axis to the FFT
         return _tuning_dict(t)
 
     def close(self):

@@ -138,6 +138,7 @@ hipError_t solve_occupancy_wg(int wg, bool all2d, size_t smem, int *blocks_per_c
 }
 // The 512-thread solver applies: the FFT on every axis.
 bool fft_everywhere(const SysDesc &h) { return !h.gemm[0] && !h.gemm[1] && !h.gemm[2]; }
+bool fft_everywhere_mask(int m) { return (m & 7) == 0; }
 // Workgroup size for a request (0 = the larger one where allowed).
 int resolve_wg(int block_threads, bool wg512_ok) {
   if (block_threads == 256) return 256;
@@ -1092,25 +1093,47 @@ csl_status problem_tune(csl_problem p, const double *f, double *z, csl_batch_tun
   if (f == z) return fail(CSL_ERR_ARG, "problem_tune: f and z must not alias");
   const int tp0 = p->tile_points, lds0 = p->lds_bytes, wg0 = p->block_threads,
             te0 = p->single_te;
-  const long long per_wg = std::max<long long>(1, p->h.M / std::max(1, p->cap));
-  // candidates: the current schedule first, then tile sizes around one tile
-  // per workgroup with both LDS budgets and every allowed workgroup size,
-  // and on small grids the smaller chunks as well
+  // engine sets: the creation-time one and, where the engines were chosen
+  // automatically, the FFT on every axis that has one: the creation-time
+  // timing runs the default schedule, under which a matrix-core axis can
+  // win and then lose once both are tuned
+  int mask0 = 0, req = 0;
+  for (int ax = 0; ax < p->h.d; ++ax) {
+    if (p->h0.gemm[ax]) mask0 |= 1 << ax;
+    if (gemm_required(p->h.n[ax])) req |= 1 << ax;
+  }
+  const int nmask = (p->opts.dst_engine == CSL_DST_AUTO && mask0 != req) ? 2 : 1;
+  const int masks[2] = {mask0, req};
+  auto set_mask = [&](int m) {
+    for (int ax = 0; ax < 3; ++ax) p->h0.gemm[ax] = p->h.gemm[ax] = (m >> ax) & 1;
+    p->wg512_ok = fft_everywhere(p->h0);
+  };
   struct Cand {
-    int tp, lds, wg, te;
+    int tp, lds, wg, te, mask;
   };
   std::vector<Cand> cands;
-  cands.push_back({tp0, lds0, wg0, te0});
-  for (int wg : {256, 512}) {
-    if (wg == 512 && !p->wg512_ok) continue;
-    for (int lds : {32768, 65536})
-      for (long long tp : {0LL, 1LL, per_wg / 2, per_wg * 2, 8192LL})
-        if (tp >= 0 && !((int)tp == tp0 && lds == lds0 && wg == wg0 && te0 == 0))
-          cands.push_back({(int)tp, lds, wg, 0});
-    if (p->h.M <= kSmallChunkPoints)
-      for (int te : kSmallChunkElems)
-        for (long long tp : {0LL, 1LL, per_wg})
-          if (!((int)tp == tp0 && wg == wg0 && te == te0)) cands.push_back({(int)tp, 32768, wg, te});
+  cands.push_back({tp0, lds0, wg0, te0, mask0});
+  for (int mi = 0; mi < nmask; ++mi) {
+    const int m = masks[mi];
+    const bool w512 = fft_everywhere_mask(m);
+    const long long per_wg = std::max<long long>(1, p->h.M / std::max(1, p->cap));
+    for (int wg : {256, 512}) {
+      if (wg == 512 && !w512) continue;
+      for (int lds : {32768, 65536}) {
+        std::vector<long long> tps;
+        for (long long tp : {0LL, 1LL, per_wg / 2, per_wg * 2, per_wg * 4, per_wg * 8, 4096LL, 8192LL})
+          if (tp >= 0 && tp <= (1LL << 30) && std::find(tps.begin(), tps.end(), tp) == tps.end())
+            tps.push_back(tp);
+        for (long long tp : tps)
+          if (!((int)tp == tp0 && lds == lds0 && wg == wg0 && te0 == 0 && m == mask0))
+            cands.push_back({(int)tp, lds, wg, 0, m});
+      }
+      if (p->h.M <= kSmallChunkPoints)
+        for (int te : kSmallChunkElems)
+          for (long long tp : {0LL, 1LL, per_wg})
+            if (!((int)tp == tp0 && wg == wg0 && te == te0 && m == mask0))
+              cands.push_back({(int)tp, 32768, wg, te, m});
+    }
   }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(hipEventCreate(&e0));
@@ -1120,9 +1143,10 @@ csl_status problem_tune(csl_problem p, const double *f, double *z, csl_batch_tun
   }
   const SolveParams P = make_params(0.0, 0, 1, 0, p->wall_khz);
   double best = INFINITY, first = INFINITY;
-  int best_tp = tp0, best_lds = lds0, best_wg = wg0, best_te = te0, timed = 0;
+  int best_tp = tp0, best_lds = lds0, best_wg = wg0, best_te = te0, best_mask = mask0, timed = 0;
   csl_status st = CSL_OK;
   for (size_t c = 0; c < cands.size() && st == CSL_OK; ++c) {
+    set_mask(cands[c].mask);
     p->single_te = cands[c].te;
     st = configure_single(p, cands[c].tp, cands[c].lds, cands[c].wg, s);
     if (st == CSL_ERR_ARG && cands[c].te > 0) {   // more chunks than partial-sum slots
@@ -1153,10 +1177,12 @@ csl_status problem_tune(csl_problem p, const double *f, double *z, csl_batch_tun
       best_lds = p->lds_bytes;
       best_wg = p->block_threads;
       best_te = cands[c].te;
+      best_mask = cands[c].mask;
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  set_mask(best_mask);
   p->single_te = best_te;
   const csl_status st2 = configure_single(p, best_tp, best_lds, best_wg, s);
   if (st != CSL_OK) return st;
