@@ -155,3 +155,31 @@ def test_batch_gemm_and_fft_mixed(csl):
         assert info["status"] == 0 and info["relres_true"] <= 1e-8, info
         zo = O.Problem(s.a, s.lam.real, s.lam.imag, abar_rule="given", abar=p.abar).direct(s.f)
         assert rel(z, zo) <= 1e-6
+
+
+def test_tune_keeps_forced_engines_and_may_move_auto_ones(csl):
+    # problem_tune may move an automatically chosen matrix-core axis to the
+    # FFT (never a forced one, never an axis without an FFT); the tuned
+    # problem still solves to the oracle's result
+    shape = (31, 31, 31)
+    a = _coef(shape, 7)
+    f = _crand(shape, 8)
+    lam = complex(12.0, 30.0)
+    forced = csl.Problem(cuda(a), lam.real, lam.imag, dst="gemm", pinv_fp32=True)
+    forced.tune(cuda(f))
+    assert forced.dst_engines == ("gemm", "gemm", "gemm")
+    auto = csl.Problem(cuda(a), lam.real, lam.imag, pinv_fp32=True)
+    before = auto.dst_engines
+    t = auto.tune(cuda(f))
+    after = auto.dst_engines
+    _say("auto engines", before, "->", after, t)
+    assert all(e2 == e1 or e2 == "fft" for e1, e2 in zip(before, after))
+    z, info = csl.minres_solve(auto, cuda(f), timeout_ms=30000)
+    po = O.Problem(a, lam.real, lam.imag, abar_rule="given", abar=auto.abar)
+    r = f - O.apply_A(po.K, lam.real, lam.imag, np.conj(z.cpu().numpy()))
+    assert info["status"] == 0 and np.linalg.norm(r) / np.linalg.norm(f) <= 1.01e-8
+    mixed = csl.Problem(cuda(_coef((20, 63), 9)), lam.real, lam.imag)
+    mixed.tune(cuda(_crand((20, 63), 10)))
+    assert mixed.dst_engines[0] == "gemm"   # n + 1 = 21 has no FFT
+    for p in (forced, auto, mixed):
+        p.close()
