@@ -82,7 +82,7 @@ def test_many_right_hand_sides_as_a_batch(csl):
     fs_h = [_crand(shape, 100 + j) for j in range(count)]
     b = csl.Batch(probs, timeout_ms=30000)
     zs, infos = b.solve([cuda(f) for f in fs_h])
-    po = O.Problem(a, lam.real, lam.imag, abar_rule="given", abar=p.abar)
+    po = O.Problem(a, lam.real, lam.imag)
     worst = 0.0
     for f, z, info in zip(fs_h, zs, infos):
         zo, io = po.solve(f)

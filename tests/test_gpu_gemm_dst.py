@@ -108,7 +108,7 @@ def test_solve_gemm_matches_oracle_and_fft(csl, n):
     zf, if_ = csl.minres_solve(pf, cuda(s.f), raise_on_error=False, timeout_ms=30000)
     assert ig["status"] == 0 and if_["status"] == 0
     assert ig["relres_true"] <= 1e-8
-    po = O.Problem(s.a, s.lam.real, s.lam.imag, abar_rule="given", abar=pg.abar)
+    po = O.Problem(s.a, s.lam.real, s.lam.imag)
     zo, io = po.solve(s.f, tol=1e-8)
     zg = zg.cpu().numpy()
     if ig["iters"] == io["iters"]:
@@ -130,10 +130,16 @@ def test_solve_3d_gemm(csl, shape):
     p = csl.Problem(cuda(a), lam.real, lam.imag, dst="gemm", pinv_fp32=True)
     z, info = csl.minres_solve(p, cuda(f), raise_on_error=False, timeout_ms=30000)
     assert info["status"] == 0 and info["relres_true"] <= 1e-8
-    po = O.Problem(a, lam.real, lam.imag, abar_rule="given", abar=p.abar)
-    r = f - O.apply_A(po.K, lam.real, lam.imag, np.conj(z.cpu().numpy()))
+    po = O.Problem(a, lam.real, lam.imag)
+    zg = z.cpu().numpy()
+    r = f - O.apply_A(po.K, lam.real, lam.imag, np.conj(zg))
     # the user solution z solves (K + lambda I) z = f; apply_A acts on conj
     assert np.linalg.norm(r) / np.linalg.norm(f) <= 1e-8
+    # element by element against the FP64 oracle's iterate after the GPU's
+    # number of steps (FP32 preconditioner form: 1e-6)
+    zx, _ = po.solve(f, fixed_iters=info["iters"])
+    _say("  vs oracle", info["iters"], rel(zg, zx))
+    assert rel(zg, zx) <= 1e-6
 
 
 def test_batch_gemm_and_fft_mixed(csl):
@@ -153,7 +159,7 @@ def test_batch_gemm_and_fft_mixed(csl):
             assert np.array_equal(z1, z2.cpu().numpy())
     for s, z, info, p in zip(w.systems, first, infos, probs):
         assert info["status"] == 0 and info["relres_true"] <= 1e-8, info
-        zo = O.Problem(s.a, s.lam.real, s.lam.imag, abar_rule="given", abar=p.abar).direct(s.f)
+        zo = O.Problem(s.a, s.lam.real, s.lam.imag).direct(s.f)
         assert rel(z, zo) <= 1e-6
 
 
@@ -174,10 +180,17 @@ def test_tune_keeps_forced_engines_and_may_move_auto_ones(csl):
     after = auto.dst_engines
     _say("auto engines", before, "->", after, t)
     assert all(e2 == e1 or e2 == "fft" for e1, e2 in zip(before, after))
-    z, info = csl.minres_solve(auto, cuda(f), timeout_ms=30000)
-    po = O.Problem(a, lam.real, lam.imag, abar_rule="given", abar=auto.abar)
-    r = f - O.apply_A(po.K, lam.real, lam.imag, np.conj(z.cpu().numpy()))
-    assert info["status"] == 0 and np.linalg.norm(r) / np.linalg.norm(f) <= 1.01e-8
+    po = O.Problem(a, lam.real, lam.imag)
+    for p in (forced, auto):
+        z, info = csl.minres_solve(p, cuda(f), timeout_ms=30000)
+        zg = z.cpu().numpy()
+        r = f - O.apply_A(po.K, lam.real, lam.imag, np.conj(zg))
+        assert info["status"] == 0 and np.linalg.norm(r) / np.linalg.norm(f) <= 1.01e-8
+        # tuner-moved (auto) and forced engines: element by element against the
+        # FP64 oracle after the GPU's number of steps
+        zx, _ = po.solve(f, fixed_iters=info["iters"])
+        _say("  ", p.dst_engines, "vs oracle", rel(zg, zx))
+        assert rel(zg, zx) <= 1e-6
     mixed = csl.Problem(cuda(_coef((20, 63), 9)), lam.real, lam.imag)
     mixed.tune(cuda(_crand((20, 63), 10)))
     assert mixed.dst_engines[0] == "gemm"   # n + 1 = 21 has no FFT

@@ -101,7 +101,7 @@ def test_solve(csl, shape, lengths):
     p = csl.Problem(cuda(a), lam.real, lam.imag, lengths=lengths)
     z, info = csl.minres_solve(p, cuda(f), timeout_ms=30000)
     zg = z.cpu().numpy()
-    po = O.Problem(a, lam.real, lam.imag, abar_rule="given", abar=p.abar, lengths=lengths)
+    po = O.Problem(a, lam.real, lam.imag, lengths=lengths)
     zo, io = po.solve(f)
     _say(info, io["iters"])
     assert info["status"] == 0
@@ -111,11 +111,17 @@ def test_solve(csl, shape, lengths):
         assert abs(info["iters"] - io["iters"]) <= 1
         zf, _ = po.solve(f, fixed_iters=info["iters"])
         assert rel(zg, zf) <= 1e-10
-    # FP32 preconditioner: the oracle's own residual of the GPU solution
+    # FP32 preconditioner: the oracle's own residual of the GPU solution, and
+    # the solution element by element against the FP64 oracle's iterate after
+    # the GPU's number of steps (1e-6)
     p32 = csl.Problem(cuda(a), lam.real, lam.imag, lengths=lengths, pinv_fp32=True)
     z32, i32 = csl.minres_solve(p32, cuda(f), timeout_ms=30000)
-    r = f - O.apply_A(po.K, lam.real, lam.imag, np.conj(z32.cpu().numpy()))
+    z32 = z32.cpu().numpy()
+    r = f - O.apply_A(po.K, lam.real, lam.imag, np.conj(z32))
     assert i32["status"] == 0 and np.linalg.norm(r) / np.linalg.norm(f) <= 1.01e-8
+    z32o, _ = po.solve(f, fixed_iters=i32["iters"])
+    _say("  fp32 vs oracle", rel(z32, z32o))
+    assert rel(z32, z32o) <= 1e-6
     p.close()
     p32.close()
 
@@ -135,7 +141,8 @@ def test_mixed_batch_and_engine_rules(csl):
     assert b.schedule["block_threads"] == 256   # the matrix-core axes need the 256-thread solver
     zs, infos = b.solve(fs)
     for (a, lam, f, abar), z, info in zip(refs, zs, infos):
-        po = O.Problem(a, lam.real, lam.imag, abar_rule="given", abar=abar)
+        po = O.Problem(a, lam.real, lam.imag)
+        assert abar == pytest.approx(po.abar, rel=1e-14)
         zo, io = po.solve(f)
         assert info["status"] == 0 and abs(info["iters"] - io["iters"]) <= 1
         zf = zo if info["iters"] == io["iters"] else po.solve(f, fixed_iters=info["iters"])[0]
@@ -188,12 +195,18 @@ def test_batch_with_long_sine_matrix_lines(csl):
     b = csl.Batch(probs, timeout_ms=60000)
     zs, infos = b.solve([cuda(r[2]) for r in refs])
     for (a, lam, f, abar, fp32), z, info in zip(refs, zs, infos):
-        po = O.Problem(a, lam.real, lam.imag, abar_rule="given", abar=abar)
+        po = O.Problem(a, lam.real, lam.imag)
+        assert abar == pytest.approx(po.abar, rel=1e-14)
         assert info["status"] == 0
         zg = z.cpu().numpy()
         if fp32:
             r = f - O.apply_A(po.K, lam.real, lam.imag, np.conj(zg))
             assert np.linalg.norm(r) / np.linalg.norm(f) <= 1.01e-8
+            # FP32 preconditioner on long sine-matrix lines: element by
+            # element against the FP64 oracle after the GPU's steps (1e-6)
+            zx, _ = po.solve(f, fixed_iters=info["iters"])
+            _say(a.shape, "fp32", info["iters"], rel(zg, zx))
+            assert rel(zg, zx) <= 1e-6
             continue
         zo, io = po.solve(f)
         assert abs(info["iters"] - io["iters"]) <= 1

@@ -103,7 +103,9 @@ def _solve_both(csl, a, lam, f, fp32=False, tol=1e-8, maxit=1000, abar_rule="mea
     z, info = csl.minres_solve(p, cuda(f), tol=tol, maxit=maxit, raise_on_error=False,
                                timeout_ms=30000)
     zg = z.cpu().numpy()
-    po = O.Problem(a, lam.real, lam.imag, abar_rule="given", abar=p.abar, lengths=lengths)
+    # the oracle takes its own abar by the same rule
+    po = O.Problem(a, lam.real, lam.imag, abar_rule=abar_rule, lengths=lengths)
+    assert p.abar == pytest.approx(po.abar, rel=1e-14)
     zo, io = po.solve(f, tol=tol, maxit=maxit)
     return p, zg, info, po, zo, io
 
@@ -200,7 +202,7 @@ def test_status_paths(csl):
     p = csl.Problem(cuda(a), -50.0, 2.0)
     z, info = csl.minres_solve(p, cuda(f), maxit=2, raise_on_error=False)
     assert info["status"] == 3 and info["iters"] == 2
-    po = O.Problem(a, -50.0, 2.0, abar_rule="given", abar=p.abar)
+    po = O.Problem(a, -50.0, 2.0)
     zo, io = po.solve(f, maxit=2)
     assert rel(z.cpu().numpy(), zo) <= 1e-12
     z, info = csl.minres_solve(p, torch.zeros((n, n), dtype=torch.complex128, device="cuda"))
@@ -244,7 +246,7 @@ def test_batch_matches_oracle_and_replays(csl):
     _say("batch", [i["iters"] for i in infos])
     for s, p, z, info in zip(w.systems, probs, zs, infos):
         assert info["status"] == 0
-        po = O.Problem(s.a, s.lam.real, s.lam.imag, abar_rule="given", abar=p.abar)
+        po = O.Problem(s.a, s.lam.real, s.lam.imag)
         zo, io = po.solve(s.f)
         assert _compare_iterates(po, s.f, z.cpu().numpy(), info, zo, io, 1e-10) <= 1e-10
     # graph replay: same results, bitwise, on every replay
@@ -271,7 +273,7 @@ def test_batch_mixed_precision_uneven(csl):
     b = csl.Batch(probs)
     zs, infos = b.solve(fs)
     for s, p, z, info in zip(w.systems, probs, zs, infos):
-        po = O.Problem(s.a, s.lam.real, s.lam.imag, abar_rule="given", abar=p.abar)
+        po = O.Problem(s.a, s.lam.real, s.lam.imag)
         zo, io = po.solve(s.f)
         assert info["status"] == 0 and abs(info["iters"] - io["iters"]) <= 1
         assert rel(z.cpu().numpy(), zo) <= 1e-6
@@ -403,7 +405,7 @@ def test_iterate_after_k_steps(csl, fp32):
     # (even k), against the oracle's iterate after exactly k steps
     s = WL.workload("c1", n_override=31).systems[0]
     p = csl.Problem(cuda(s.a), s.lam.real, s.lam.imag, pinv_fp32=fp32)
-    po = O.Problem(s.a, s.lam.real, s.lam.imag, abar_rule="given", abar=p.abar)
+    po = O.Problem(s.a, s.lam.real, s.lam.imag)
     f = cuda(s.f)
     for k in range(1, 8):
         z, info = csl.minres_solve(p, f, maxit=k, tol=1e-30, raise_on_error=False)

@@ -61,7 +61,7 @@ def test_lanczos_and_ritz_match_oracle(csl, shape):
     _, info = csl.minres_solve(p, cuda(f), timeout_ms=30000)
     d, g = p.lanczos()
     assert d.size == info["iters"] and g.size == info["iters"]
-    po = O.Problem(a, lam.real, lam.imag, abar_rule="given", abar=p.abar)
+    po = O.Problem(a, lam.real, lam.imag)
     _, io = po.solve(f)
     k = min(d.size, len(io["delta"]))
     _say(shape, "steps", d.size, len(io["delta"]))

@@ -98,7 +98,7 @@ def test_batch_more_than_64_systems(csl, block_threads):
     worst = 0.0
     for (shape, a, lam, f), p, z, info in zip(systems, probs, zs, infos):
         assert info["status"] == 0, (shape, lam, info)
-        po = O.Problem(a, lam.real, lam.imag, abar_rule="given", abar=p.abar)
+        po = O.Problem(a, lam.real, lam.imag)
         zo, io = po.solve(f)
         worst = max(worst, _vs_oracle(po, lam, f, z.cpu().numpy(), info, zo, io))
     _say("worst relative difference", worst)
@@ -161,7 +161,7 @@ def test_time_limit_batch(csl):
             assert info["status_name"] in ("OK", "ERR_TIMEOUT")
             if info["status"] == 0:
                 # a system that finished before the limit keeps its solution
-                po = O.Problem(a, lam.real, lam.imag, abar_rule="given", abar=p.abar)
+                po = O.Problem(a, lam.real, lam.imag)
                 zo, io = po.solve(f)
                 assert _vs_oracle(po, lam, f, z.cpu().numpy(), info, zo, io) <= 1e-9
     with pytest.raises(csl.CSLError, match="ERR_TIMEOUT"):
@@ -267,7 +267,7 @@ def test_chunk_size_schedule(csl):
     a = _coef(shape, 80)
     f = _crand(shape, 81)
     p = csl.Problem(cuda(a), lam.real, lam.imag)
-    po = O.Problem(a, lam.real, lam.imag, abar_rule="given", abar=p.abar)
+    po = O.Problem(a, lam.real, lam.imag)
     zo, io = po.solve(f)
     for te in (512, 1024, 0):
         p.set_schedule(0, 0, 0, te)

