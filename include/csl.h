@@ -227,6 +227,28 @@ csl_status minres_solve(csl_problem p, const double *f, double *z,
                         const csl_solve_opts *opts, csl_solve_info *info,
                         hipStream_t s);
 
+/* minres_solve for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * problem is given directly (grid, a_nodal, alpha, beta, opts as for
+ * create_problem; a_nodal is read in place, not copied) and solved once,
+ * with no handle and no allocation.  Every workspace of the solve lives in
+ * one static device array of 64 MiB per GPU that the library holds from the
+ * moment it is loaded until the process ends.  Limits: every axis needs
+ * n + 1 a power of two (the FFT engine; dst_engine AUTO or FFT), and the
+ * grid's workspace must fit the 64 MiB (2-D grids up to 511 x 511, 3-D up to
+ * 63^3 in FP64): larger grids, or an axis without an FFT, return CSL_ERR_ARG
+ * before any device work.  Set-up runs on every call and synchronises s once
+ * (the coefficient check and abar, as in create_problem); the solve itself
+ * is minres_solve's kernel, and with info != NULL s is synchronised again.
+ * All calls on one GPU share its array: calls that overlap on one device
+ * (from several threads or streams) race and give undefined results; one
+ * call's device work must complete before the next call on that device is
+ * queued on another stream.  f, z: device, M complex, must not alias. */
+csl_status minres_solve_noalloc(const csl_grid *grid, const double *a_nodal, double alpha,
+                                double beta, const csl_problem_opts *opts, const double *f,
+                                double *z, const csl_solve_opts *sopts, csl_solve_info *info,
+                                hipStream_t s);
+
 /* Adjoint of z = (K + lambda I)^{-1} f for a real loss L(z).
  * gz = dL/dRe z + i dL/dIm z (device, M complex).  One extra MINRES solve
  * y = (K + conj(lambda) I)^{-1} gz on the same symmetric block matrix, then

@@ -19,7 +19,7 @@ from dataclasses import dataclass
 
 __all__ = [
     "CSLError", "Problem", "Batch", "create_problem", "destroy_problem",
-    "apply_A", "apply_Pinv", "minres_solve", "minres_adjoint",
+    "apply_A", "apply_Pinv", "minres_solve", "minres_solve_noalloc", "minres_adjoint",
     "batch_create", "batch_solve", "batch_destroy", "CSLSolve", "solve",
     "library_path", "load_library",
 ]
@@ -115,6 +115,9 @@ def load_library():
     L.apply_Pinv.argtypes = [vp, vp, vp, vp]
     L.minres_solve.argtypes = [vp, vp, vp, ctypes.POINTER(_SolveOpts),
                                ctypes.POINTER(_SolveInfo), vp]
+    L.minres_solve_noalloc.argtypes = [ctypes.POINTER(_Grid), vp, ctypes.c_double,
+                                       ctypes.c_double, ctypes.POINTER(_ProblemOpts), vp, vp,
+                                       ctypes.POINTER(_SolveOpts), ctypes.POINTER(_SolveInfo), vp]
     L.minres_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(_SolveOpts),
                                  ctypes.POINTER(_SolveInfo), vp]
     L.batch_create.argtypes = [ctypes.POINTER(vp), ip, ctypes.POINTER(_BatchOpts),
@@ -374,6 +377,51 @@ def minres_solve(p: Problem, f, z=None, tol=1e-8, maxit=1000, check_true=True,
     st = load_library().minres_solve(p.handle, _ptr(f), _ptr(z), ctypes.byref(o),
                                      ctypes.byref(info) if want_info else None,
                                      _stream(p.device))
+    d = _info_dict(info) if want_info else None
+    if raise_on_error and st != 0:
+        _check(st, d)
+    return z, d
+
+
+def minres_solve_noalloc(a, alpha: float, beta: float, f, z=None, lengths=None,
+                         abar_rule: str = "mean", abar: float | None = None,
+                         pinv_fp32: bool = False, tol=1e-8, maxit=1000, check_true=True,
+                         timeout_ms=0, want_info=True, raise_on_error=True):
+    """Solve (K + lambda I) z = f once without a problem handle, through the
+    library's allocation-free entry point (its workspace is a static device
+    array; n + 1 a power of two on every axis).  Returns (z, info or None)."""
+    torch = _torch()
+    if not (isinstance(a, torch.Tensor) and a.is_cuda and a.dtype == torch.float64):
+        raise TypeError("a must be a float64 CUDA tensor")
+    if a.dim() not in (2, 3) or not a.is_contiguous():
+        raise ValueError("a must be a contiguous 2-D or 3-D tensor")
+    shape = tuple(a.shape)
+    for name, v in (("f", f), ("z", z)):
+        if v is None:
+            continue
+        if not (isinstance(v, torch.Tensor) and v.is_cuda and v.dtype == torch.complex128
+                and tuple(v.shape) == shape and v.is_contiguous() and v.device == a.device):
+            raise ValueError(f"{name} must be a contiguous complex128 CUDA tensor of shape "
+                             f"{shape} on {a.device}")
+    if z is None:
+        z = torch.empty_like(f)
+    g = _Grid()
+    g.dim = a.dim()
+    for k in range(3):
+        g.n[k] = shape[k] if k < g.dim else 0
+        g.length[k] = float(lengths[k]) if (lengths is not None and k < g.dim) else 1.0
+    po = _ProblemOpts()
+    po.abar_rule = _ABAR[abar_rule]
+    po.pinv_prec = 1 if pinv_fp32 else 0
+    po.abar = float(abar) if abar is not None else 0.0
+    po.dst_engine = _DST["fft"]
+    o = _solve_opts(tol, maxit, check_true, timeout_ms)
+    info = _SolveInfo()
+    with torch.cuda.device(a.device):
+        st = load_library().minres_solve_noalloc(
+            ctypes.byref(g), _ptr(a), float(alpha), float(beta), ctypes.byref(po), _ptr(f),
+            _ptr(z), ctypes.byref(o), ctypes.byref(info) if want_info else None,
+            _stream(a.device))
     d = _info_dict(info) if want_info else None
     if raise_on_error and st != 0:
         _check(st, d)

@@ -809,6 +809,26 @@ __global__ void init_kernel(const SysDesc *__restrict__ sys, int nsys, Glob *G) 
   }
 }
 
+// Descriptor of a system whose workspaces the caller placed in a buffer of
+// its own: the descriptor arrives by value and is stored at dst, and the
+// per-axis eigenvalue tables mu_k = (4 / h^2) sin^2(k pi / (2 (n + 1))) of L
+// it points to are filled in FP64 and FP32 (0 on the axes past the grid's
+// dimension).  One workgroup.
+__global__ void write_desc_kernel(SysDesc h, SysDesc *dst) {
+  if (threadIdx.x == 0) *dst = h;
+  for (int ax = 0; ax < 3; ++ax) {
+    double *mu = const_cast<double *>(h.mu[ax]);
+    float *muf = const_cast<float *>(h.mu_f[ax]);
+    const int n = h.n[ax];
+    for (int k = 1 + (int)threadIdx.x; k <= n; k += blockDim.x) {
+      const double sv = sin((double)k * M_PI / (2.0 * (n + 1)));
+      const double m = ax < h.d ? 4.0 * h.h2[ax] * sv * sv : 0.0;
+      mu[k - 1] = m;
+      muf[k - 1] = (float)m;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Stand-alone operators.
 // ---------------------------------------------------------------------------
@@ -1256,6 +1276,11 @@ hipError_t solve_occupancy(size_t smem, int *blocks_per_cu) {
 #if !CSL_SOLVE_ONLY
 hipError_t launch_init(const SysDesc *dsys, int nsys, Glob *G, hipStream_t s) {
   hipLaunchKernelGGL(init_kernel, dim3(1), dim3(64), 0, s, dsys, nsys, G);
+  return hipGetLastError();
+}
+
+hipError_t launch_write_desc(const SysDesc &h, SysDesc *dst, hipStream_t s) {
+  hipLaunchKernelGGL(write_desc_kernel, dim3(1), dim3(256), 0, s, h, dst);
   return hipGetLastError();
 }
 

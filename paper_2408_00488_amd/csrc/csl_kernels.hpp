@@ -32,6 +32,9 @@ hipError_t launch_conj(const double2 *x, double2 *y, int M, hipStream_t s);
 // inverse = its inverse.
 hipError_t launch_step_transform(const double2 *x, double2 *y, int M, int lg, double alpha_c,
                                  int inverse, hipStream_t s);
+// Store the descriptor h at dst (device) and fill the eigenvalue tables
+// h.mu[*], h.mu_f[*] point to.
+hipError_t launch_write_desc(const SysDesc &h, SysDesc *dst, hipStream_t s);
 hipError_t launch_coef_stats(const SysDesc *dsys, int d, int M, double *part, int nblk,
                              double *out, hipStream_t s);
 

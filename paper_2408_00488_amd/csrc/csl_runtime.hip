@@ -20,6 +20,15 @@
 
 using namespace csl;
 
+// Workspace of the allocation-free solve (minres_solve_noalloc): one array
+// per device, loaded with the library, holding the descriptor, the control
+// block, the partial sums, the eigenvalue tables and every work vector of the
+// one system such a call solves.  Host code reaches it only through the
+// address hipGetSymbolAddress returns on each device (the array's name is a
+// host-side stand-in there).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
 
 thread_local std::string g_err;
@@ -146,6 +155,16 @@ int resolve_wg(int block_threads, bool wg512_ok) {
   return wg512_ok ? 512 : 256;
 }
 bool valid_block_threads(int v) { return v == 0 || v == 256 || v == 512; }
+
+// Per-device record of the allocation-free solve's workspace (the array
+// `scratch` below).
+struct ScratchDev {
+  char *ptr = nullptr;   // this device's copy of `scratch`
+  int cus = 0;
+  double wall_khz = 0.0;
+};
+ScratchDev g_scratch[kMaxDevices];
+std::mutex g_scratch_mu;
 
 // Engine choices made by timing, per device and grid shape and precision.
 typedef std::tuple<int, int, int, int, int, int> ShapeKey;   // dev, d, n0, n1, n2, prec
@@ -603,36 +622,10 @@ csl_status configure_batch(csl_batch b, int tile_points, int lds_bytes, int bloc
   return CSL_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-int csl_version(void) { return 200; }
-
-const char *csl_last_error(void) { return g_err.c_str(); }
-
-// forced_mask >= 0: the matrix-core axes are given (problem_clone), no
-// engine selection
-static csl_status create_problem_impl(const csl_grid *grid, const double *a_nodal, double alpha,
-                                      double beta, const csl_problem_opts *opts, hipStream_t s,
-                                      csl_problem *out, int forced_mask) {
-  if (!out) return fail(CSL_ERR_ARG, "out is NULL");
-  *out = nullptr;
-  if (!grid || !a_nodal) return fail(CSL_ERR_ARG, "grid or coefficient is NULL");
+// Geometry of a system from the caller's grid: sizes, strides, mesh widths,
+// FFT lengths (the rest of the descriptor is left as it is).
+csl_status grid_desc(const csl_grid *grid, SysDesc &h) {
   if (grid->dim != 2 && grid->dim != 3) return fail(CSL_ERR_ARG, "dim must be 2 or 3");
-  if (!std::isfinite(alpha) || !std::isfinite(beta))
-    return fail(CSL_ERR_ARG, "shift must be finite");
-  csl_problem_opts o{};
-  o.abar_rule = CSL_ABAR_MEAN;
-  o.pinv_prec = CSL_PREC_FP64;
-  if (opts) o = *opts;
-  if (o.abar_rule < 0 || o.abar_rule > 2) return fail(CSL_ERR_ARG, "unknown abar rule");
-  if (o.pinv_prec != CSL_PREC_FP64 && o.pinv_prec != CSL_PREC_FP32)
-    return fail(CSL_ERR_ARG, "unknown preconditioner precision");
-  if (o.abar_rule == CSL_ABAR_GIVEN && !(o.abar > 0 && std::isfinite(o.abar)))
-    return fail(CSL_ERR_ARG, "given abar must be finite and positive");
-
-  SysDesc h{};
   h.d = grid->dim;
   long long M = 1;
   for (int ax = 0; ax < 3; ++ax) {
@@ -658,6 +651,62 @@ static csl_status create_problem_impl(const csl_grid *grid, const double *a_noda
   h.st[h.d - 1] = 1;
   for (int ax = h.d - 2; ax >= 0; --ax) h.st[ax] = h.st[ax + 1] * h.n[ax + 1];
   h.rows = h.M / h.n[h.d - 1];
+  return CSL_OK;
+}
+
+// The singularity test of P (beta = 0 and abar * mu + alpha = 0 for some mode
+// k): true if min_k |abar mu_k + alpha| is 0 or negligible against the
+// largest.  mu: the per-axis tables back to back (n0 + n1 + n2 entries).
+bool preconditioner_singular(const SysDesc &h, const std::vector<double> &mu, double abar,
+                             double alpha, double beta) {
+  if (beta != 0.0) return false;
+  double mn = INFINITY, mxv = 0.0;
+  const int n0 = h.n[0], n1 = h.n[1], n2 = h.d == 3 ? h.n[2] : 1;
+  const double *m0 = mu.data(), *m1 = mu.data() + h.n[0], *m2 = mu.data() + h.n[0] + h.n[1];
+  for (int i = 0; i < n0; ++i)
+    for (int j = 0; j < n1; ++j)
+      for (int k = 0; k < n2; ++k) {
+        const double lam = m0[i] + m1[j] + (h.d == 3 ? m2[k] : 0.0);
+        const double v = std::fabs(abar * lam + alpha);
+        mn = std::min(mn, v);
+        mxv = std::max(mxv, v);
+      }
+  return mn <= 1e-300 || mn <= 1e-14 * mxv;
+}
+
+}  // namespace
+
+extern "C" {
+
+int csl_version(void) { return 200; }
+
+const char *csl_last_error(void) { return g_err.c_str(); }
+
+// forced_mask >= 0: the matrix-core axes are given (problem_clone), no
+// engine selection
+static csl_status create_problem_impl(const csl_grid *grid, const double *a_nodal, double alpha,
+                                      double beta, const csl_problem_opts *opts, hipStream_t s,
+                                      csl_problem *out, int forced_mask) {
+  if (!out) return fail(CSL_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!grid || !a_nodal) return fail(CSL_ERR_ARG, "grid or coefficient is NULL");
+  if (!std::isfinite(alpha) || !std::isfinite(beta))
+    return fail(CSL_ERR_ARG, "shift must be finite");
+  csl_problem_opts o{};
+  o.abar_rule = CSL_ABAR_MEAN;
+  o.pinv_prec = CSL_PREC_FP64;
+  if (opts) o = *opts;
+  if (o.abar_rule < 0 || o.abar_rule > 2) return fail(CSL_ERR_ARG, "unknown abar rule");
+  if (o.pinv_prec != CSL_PREC_FP64 && o.pinv_prec != CSL_PREC_FP32)
+    return fail(CSL_ERR_ARG, "unknown preconditioner precision");
+  if (o.abar_rule == CSL_ABAR_GIVEN && !(o.abar > 0 && std::isfinite(o.abar)))
+    return fail(CSL_ERR_ARG, "given abar must be finite and positive");
+
+  SysDesc h{};
+  {
+    const csl_status st = grid_desc(grid, h);
+    if (st != CSL_OK) return st;
+  }
   h.prec = o.pinv_prec;
   h.alpha = alpha;
   h.beta = beta;
@@ -841,23 +890,10 @@ static csl_status create_problem_impl(const csl_grid *grid, const double *a_noda
   h.alpha_f = (float)alpha;
   h.beta_f = (float)beta;
   // P is singular only if beta = 0 and abar * mu_sum + alpha = 0 for some mode
-  if (beta == 0.0) {
-    double mn = INFINITY, mxv = 0.0;
-    const int n0 = h.n[0], n1 = h.n[1], n2 = h.d == 3 ? h.n[2] : 1;
-    const double *m0 = mu.data(), *m1 = mu.data() + h.n[0], *m2 = mu.data() + h.n[0] + h.n[1];
-    for (int i = 0; i < n0; ++i)
-      for (int j = 0; j < n1; ++j)
-        for (int k = 0; k < n2; ++k) {
-          const double lam = m0[i] + m1[j] + (h.d == 3 ? m2[k] : 0.0);
-          const double v = std::fabs(abar * lam + alpha);
-          mn = std::min(mn, v);
-          mxv = std::max(mxv, v);
-        }
-    if (mn <= 1e-300 || mn <= 1e-14 * mxv) {
-      free_problem(p);
-      return fail(CSL_ERR_SINGULAR, "preconditioner is singular: beta = 0 and "
-                                    "abar*mu + alpha = 0 for some mode");
-    }
+  if (preconditioner_singular(h, mu, abar, alpha, beta)) {
+    free_problem(p);
+    return fail(CSL_ERR_SINGULAR, "preconditioner is singular: beta = 0 and "
+                                  "abar*mu + alpha = 0 for some mode");
   }
   p->h = h;
   PCHK(hipMemcpyAsync(p->d_desc, &p->h, sizeof(SysDesc), hipMemcpyHostToDevice, s));
@@ -1056,6 +1092,189 @@ csl_status minres_solve(csl_problem p, const double *f, double *z, const csl_sol
   if (st != CSL_OK) return st;
   if (!info) return CSL_OK;
   return fetch_single_info(p, info, s);
+}
+
+// One-shot solve without a problem handle and without any allocation: the
+// descriptor, control block, partial sums, eigenvalue tables and work vectors
+// of the system live in this device's `scratch` array, the coefficient is
+// read from the caller's a_nodal.  The set-up of create_problem (coefficient
+// check, abar, singularity test, tiling) runs on every call; the solve is
+// minres_solve's persistent kernel.
+csl_status minres_solve_noalloc(const csl_grid *grid, const double *a_nodal, double alpha,
+                                double beta, const csl_problem_opts *popts, const double *f,
+                                double *z, const csl_solve_opts *sopts, csl_solve_info *info,
+                                hipStream_t s) {
+  if (!grid || !a_nodal || !f || !z) return fail(CSL_ERR_ARG, "NULL argument");
+  if (f == z) return fail(CSL_ERR_ARG, "minres_solve_noalloc: f and z must not alias");
+  if (!std::isfinite(alpha) || !std::isfinite(beta))
+    return fail(CSL_ERR_ARG, "shift must be finite");
+  csl_problem_opts o{};
+  o.abar_rule = CSL_ABAR_MEAN;
+  o.pinv_prec = CSL_PREC_FP64;
+  if (popts) o = *popts;
+  if (o.abar_rule < 0 || o.abar_rule > 2) return fail(CSL_ERR_ARG, "unknown abar rule");
+  if (o.pinv_prec != CSL_PREC_FP64 && o.pinv_prec != CSL_PREC_FP32)
+    return fail(CSL_ERR_ARG, "unknown preconditioner precision");
+  if (o.abar_rule == CSL_ABAR_GIVEN && !(o.abar > 0 && std::isfinite(o.abar)))
+    return fail(CSL_ERR_ARG, "given abar must be finite and positive");
+  if (o.tile_elems < 0) return fail(CSL_ERR_ARG, "tile_elems must be >= 0");
+  if (o.dst_engine != CSL_DST_AUTO && o.dst_engine != CSL_DST_FFT)
+    return fail(CSL_ERR_ARG, "minres_solve_noalloc runs the FFT engine only");
+  csl_solve_opts so{};
+  if (sopts) so = *sopts;
+  if (check_solve_opts(so) != CSL_OK) return CSL_ERR_ARG;
+  SysDesc h{};
+  {
+    const csl_status st = grid_desc(grid, h);
+    if (st != CSL_OK) return st;
+  }
+  for (int ax = 0; ax < h.d; ++ax)
+    if (!pow2_axis(h.n[ax]))
+      return fail(CSL_ERR_ARG, "minres_solve_noalloc needs n + 1 a power of two on every axis");
+  h.prec = o.pinv_prec;
+  h.alpha = alpha;
+  h.beta = beta;
+  h.alpha_f = (float)alpha;
+  h.beta_f = (float)beta;
+  size_t smem = 0;
+  choose_tiles(h, o.tile_elems, 0, &smem);
+
+  // layout of the workspace, as create_problem's allocation without the
+  // coefficient copy, the adjoint buffers and the sine matrices
+  const int stats_nblk = std::min(1024, (h.M + kAuxThreads - 1) / kAuxThreads);
+  const size_t vec = align256(sizeof(double2) * (size_t)h.M);
+  const size_t Mb = (size_t)h.rows * (size_t)(h.n[h.d - 1] + 63);
+  const size_t vecb = align256(sizeof(double2) * Mb);
+  const size_t tsz = align256(Mb * (h.prec ? 8 : 16));
+  const int nmu = h.n[0] + h.n[1] + h.n[2];
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o2 = off;
+    off += align256(bytes);
+    return o2;
+  };
+  const size_t o_desc = take(sizeof(SysDesc));
+  const size_t o_ctl = take(sizeof(Ctl));
+  const size_t o_info = take(sizeof(DevInfo));
+  const size_t o_glob = take(sizeof(Glob));
+  const size_t o_stats = take(sizeof(double) * 4);
+  const size_t o_spart = take(sizeof(double) * 4 * stats_nblk);
+  const size_t o_part = take(sizeof(double) * std::max(1, h.maxtile));
+  const size_t o_lz = take(sizeof(double) * (2 * kLanczosCap + 1));
+  const size_t o_mu = take(sizeof(double) * nmu);
+  const size_t o_muf = take(sizeof(float) * nmu);
+  size_t o_v[7];
+  for (int i = 0; i < 7; ++i) o_v[i] = take(i < 3 ? vecb : vec);   // Tq, Tv0, Tv1 blocked
+  const size_t o_t = take(tsz);
+  if (off > kScratchBytes)
+    return fail(CSL_ERR_ARG, "minres_solve_noalloc: the grid needs " + std::to_string(off) +
+                                 " bytes of workspace, more than its " +
+                                 std::to_string(kScratchBytes) + "-byte limit");
+
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(CSL_ERR_ARG, "device index out of range");
+  {
+    const csl_status st = ensure_twiddles(dev);
+    if (st != CSL_OK) return st;
+  }
+  ScratchDev sd;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    ScratchDev &e = g_scratch[dev];
+    if (!e.ptr) {
+      void *ptr = nullptr;
+      HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+      hipDeviceProp_t prop;
+      HIPCHK(hipGetDeviceProperties(&prop, dev));
+      int khz = 0;
+      if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess ||
+          khz <= 0)
+        khz = 100000;
+      e.cus = prop.multiProcessorCount;
+      e.wall_khz = (double)khz;
+      e.ptr = (char *)ptr;
+    }
+    sd = e;
+  }
+  char *base = sd.ptr;
+  SysDesc *d_desc = (SysDesc *)(base + o_desc);
+  Glob *glob = (Glob *)(base + o_glob);
+  double *stats = (double *)(base + o_stats);
+  h.a = a_nodal;
+  h.ctl = (Ctl *)(base + o_ctl);
+  h.info = (DevInfo *)(base + o_info);
+  h.part = (double *)(base + o_part);
+  h.lz = (double *)(base + o_lz);
+  h.Tq = (double2 *)(base + o_v[0]);
+  h.Tv[0] = (double2 *)(base + o_v[1]);
+  h.Tv[1] = (double2 *)(base + o_v[2]);
+  h.Z[0] = (double2 *)(base + o_v[3]);
+  h.Z[1] = (double2 *)(base + o_v[4]);
+  h.W[0] = (double2 *)(base + o_v[5]);
+  h.W[1] = (double2 *)(base + o_v[6]);
+  h.T = base + o_t;
+  int mo = 0;
+  for (int ax = 0; ax < 3; ++ax) {
+    h.mu[ax] = (const double *)(base + o_mu) + mo;
+    h.mu_f[ax] = (const float *)(base + o_muf) + mo;
+    h.gemm[ax] = 0;
+    h.Wm[ax] = nullptr;
+    h.Wmf[ax] = nullptr;
+    mo += h.n[ax];
+  }
+  // coefficient statistics (sum, face bounds, invalid samples), read back
+  HIPCHK(wg256::launch_write_desc(h, d_desc, s));
+  HIPCHK(wg256::launch_coef_stats(d_desc, h.d, h.M, (double *)(base + o_spart), stats_nblk, stats,
+                                  s));
+  double st4[4];
+  HIPCHK(hipMemcpyAsync(st4, stats, sizeof(st4), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (st4[3] != 0.0) return fail(CSL_ERR_ARG, "coefficient samples must be finite and positive");
+  double abar = 0.0;
+  if (o.abar_rule == CSL_ABAR_MEAN) abar = st4[0] / (double)h.M;
+  else if (o.abar_rule == CSL_ABAR_GEOMEAN) abar = std::sqrt(st4[1] * st4[2]);
+  else abar = o.abar;
+  h.abar = abar;
+  h.abar_f = (float)abar;
+  if (beta == 0.0) {
+    std::vector<double> mu(nmu);
+    int k0 = 0;
+    for (int ax = 0; ax < 3; ++ax) {
+      const int n = h.n[ax];
+      for (int k = 1; k <= n; ++k) {
+        const double sv = std::sin((double)k * M_PI / (2.0 * (n + 1)));
+        mu[k0 + k - 1] = ax < h.d ? 4.0 * h.h2[ax] * sv * sv : 0.0;
+      }
+      k0 += n;
+    }
+    if (preconditioner_singular(h, mu, abar, alpha, beta))
+      return fail(CSL_ERR_SINGULAR, "preconditioner is singular: beta = 0 and "
+                                    "abar*mu + alpha = 0 for some mode");
+  }
+  // schedule of a problem's own solve: the 512-thread solver (the FFT runs
+  // on every axis), about one tile per workgroup and phase
+  const int wg = 512;
+  int bpc = 0;
+  HIPCHK(solve_occupancy_wg(wg, h.d == 2, smem, &bpc));
+  const int cap = std::max(1, bpc) * sd.cus;
+  set_tile_points(h, (int)std::min<long long>(1 << 30, h.M / cap));
+  int mt = 1;
+  for (int k = 0; k < K_NKINDS; ++k) mt = std::max(mt, h.ntile[k]);
+  HIPCHK(wg256::launch_write_desc(h, d_desc, s));
+  const SolveParams P = make_params(so.tol, so.maxit, so.check_true_residual, so.timeout_ms,
+                                    sd.wall_khz);
+  HIPCHK(wg256::launch_init(d_desc, 1, glob, s));
+  IOPtr io0{(const double2 *)f, (double2 *)z};
+  HIPCHK(solve_launch(wg, h.d == 2, d_desc, nullptr, io0, 1, P, glob, std::max(1, std::min(mt, cap)),
+                      smem, s));
+  if (!info) return CSL_OK;
+  DevInfo di;
+  HIPCHK(hipMemcpyAsync(&di, h.info, sizeof(di), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const csl_status st = info_from_device(di, info);
+  if (st != CSL_OK) g_err = std::string("solve ended with status: ") + status_name(st);
+  return st;
 }
 
 csl_status problem_set_schedule(csl_problem p, int tile_points, int lds_bytes, int block_threads,

@@ -111,3 +111,23 @@ def test_tridiagonal_eigenvalues_against_scipy(lib):
         assert np.abs(th - ref).max() <= 1e-13 * scale, (d.size, np.abs(th - ref).max())
     assert f(None, None, 0, None) == 0
     assert f(None, None, -1, None) == 1
+
+
+@pytest.mark.parametrize("dim,n,msg", [(2, (1023, 1023), "bytes of workspace"),
+                                       (3, (127, 127, 127), "bytes of workspace"),
+                                       (2, (100, 63), "power of two"),
+                                       (3, (31, 31, 20), "power of two")])
+def test_noalloc_refuses_on_the_host(lib, dim, n, msg):
+    # the allocation-free solve refuses grids its static workspace cannot
+    # hold, and axes without an FFT, before any device work
+    g = _grid(dim, n)
+    fake_a, fake_f, fake_z = (ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000),
+                              ctypes.c_void_p(0x3000))
+    st = lib.minres_solve_noalloc(ctypes.byref(g), fake_a, 1.0, 1.0, None, fake_f, fake_z, None,
+                                  None, None)
+    assert st == 1
+    assert msg in lib.csl_last_error().decode()
+    assert lib.minres_solve_noalloc(None, fake_a, 1.0, 1.0, None, fake_f, fake_z, None, None,
+                                    None) == 1
+    assert lib.minres_solve_noalloc(ctypes.byref(g), fake_a, 1.0, 1.0, None, fake_f, fake_f,
+                                    None, None, None) == 1
