@@ -317,6 +317,28 @@ csl_status batch_create(const csl_problem *problems, int count,
 csl_status batch_solve(csl_batch b, const double *const *f, double *const *z,
                        csl_solve_info *infos, hipStream_t s);
 
+/* Adjoint of every system of the batch at once (minres_adjoint for each
+ * system j, derived from Eq. (1)): z[j] the forward solution and gz[j] =
+ * dL/dRe z_j + i dL/dIm z_j (device, M_j complex each; host arrays of
+ * `count` pointers).  The adjoint solves y_j = (K + conj(lambda_j) I)^{-1}
+ * gz[j] of all systems run in one persistent launch (the batch's schedule),
+ * then, system by system in order:
+ *   gf[j] = y_j (device, M_j complex, written; gf or any gf[j] may be NULL),
+ *   galpha[j] = -Re(y_j^H z_j), gbeta[j] = Im(y_j^H z_j) (device arrays of
+ *   `count` doubles, written; either may be NULL),
+ *   ga[p] += sum over the systems of dL_j/da_p (device, M doubles,
+ *   ACCUMULATED in the order j = 0, 1, ...: the gradient of a loss summed
+ *   over systems that share one coefficient; every system must then be on
+ *   one grid, else CSL_ERR_ARG; may be NULL).
+ * opts: tolerance and limits of the adjoint solves (NULL: the batch's).
+ * Uses each problem's own adjoint workspaces: no problem of the batch may be
+ * solved or adjoint-solved elsewhere while this is queued.  If infos != NULL
+ * (host array of `count`), synchronises s, fills them (the adjoint solves)
+ * and returns CSL_OK only if every system converged. */
+csl_status batch_adjoint(csl_batch b, const double *const *z, const double *const *gz,
+                         double *const *gf, double *galpha, double *gbeta, double *ga,
+                         const csl_solve_opts *opts, csl_solve_info *infos, hipStream_t s);
+
 /* Autotuner of a problem's own schedule: solves (K + lambda I) z = f with
  * each candidate tile size, LDS budget and allowed workgroup size, and on
  * grids of at most 65536 points also chunks of 512 and 1024 elements (tol

@@ -124,6 +124,9 @@ def load_library():
                                ctypes.POINTER(vp)]
     L.batch_solve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp),
                               ctypes.POINTER(_SolveInfo), vp]
+    L.batch_adjoint.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                vp, vp, vp, ctypes.POINTER(_SolveOpts),
+                                ctypes.POINTER(_SolveInfo), vp]
     L.batch_destroy.argtypes = [vp]
     L.batch_tune.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp),
                              ctypes.POINTER(_BatchTuning), vp]
@@ -505,6 +508,42 @@ class Batch:
         if raise_on_error and st != 0:
             _check(st, d)
         return zs, d
+
+    def adjoint(self, zs, gzs, ga=None, tol=1e-8, maxit=1000, check_true=True, timeout_ms=0,
+                want_info=True, raise_on_error=True):
+        """Adjoint of every system at once (batch_adjoint): zs the forward
+        solutions, gzs = dL/dRe z + i dL/dIm z per system.  Returns (grads,
+        infos) with grads = dict(f=[per system], alpha=tensor(count),
+        beta=tensor(count), a=ga): the coefficient gradient summed over the
+        systems (accumulated into ``ga`` if given, else a fresh zero tensor;
+        every system must be on one grid)."""
+        torch = _torch()
+        n = len(self.problems)
+        if len(zs) != n or len(gzs) != n:
+            raise ValueError("need one solution and one loss gradient per system")
+        for p, z, gz in zip(self.problems, zs, gzs):
+            p._vec(z, "z")
+            p._vec(gz, "gz")
+        gfs = [torch.empty_like(gz) for gz in gzs]
+        gab = torch.zeros((2, n), dtype=torch.float64, device=self.device)
+        if ga is None:
+            ga = torch.zeros(self.problems[0].shape, dtype=torch.float64, device=self.device)
+        elif not (isinstance(ga, torch.Tensor) and ga.dtype == torch.float64 and ga.is_contiguous()
+                  and tuple(ga.shape) == self.problems[0].shape and ga.device == self.device):
+            raise ValueError("ga must be a contiguous float64 tensor of the grid's shape")
+        za = (ctypes.c_void_p * n)(*[z.data_ptr() for z in zs])
+        ga_arr = (ctypes.c_void_p * n)(*[g.data_ptr() for g in gzs])
+        fa = (ctypes.c_void_p * n)(*[g.data_ptr() for g in gfs])
+        o = _solve_opts(tol, maxit, check_true, timeout_ms)
+        infos = (_SolveInfo * n)()
+        st = load_library().batch_adjoint(
+            self._h, za, ga_arr, fa, ctypes.c_void_p(gab.data_ptr()),
+            ctypes.c_void_p(gab.data_ptr() + 8 * n), _ptr(ga), ctypes.byref(o),
+            infos if want_info else None, _stream(self.device))
+        d = [_info_dict(i) for i in infos] if want_info else None
+        if raise_on_error and st != 0:
+            _check(st, d)
+        return {"f": gfs, "alpha": gab[0], "beta": gab[1], "a": ga}, d
 
     def tune(self, fs, zs=None) -> dict:
         """Time the candidate schedules on these right-hand sides and keep

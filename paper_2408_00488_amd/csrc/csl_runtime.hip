@@ -218,6 +218,7 @@ struct csl_batch_s {
   SysDesc *d_desc = nullptr;
   IOPtr *d_io = nullptr;
   IOPtr *h_io = nullptr;       // pinned
+  IOPtr *d_io_adj = nullptr;   // (gtmp, ytmp) of every problem: the adjoint solves
   DevInfo *d_info = nullptr;
   Glob *glob = nullptr;
   void *mem = nullptr;
@@ -1468,6 +1469,7 @@ csl_status batch_create(const csl_problem *problems, int count, const csl_batch_
   };
   const size_t o_desc = take(sizeof(SysDesc) * count);
   const size_t o_io = take(sizeof(IOPtr) * count);
+  const size_t o_io_adj = take(sizeof(IOPtr) * count);
   const size_t o_info = take(sizeof(DevInfo) * count);
   const size_t o_glob = take(sizeof(Glob));
   hipError_t e = hipMalloc(&b->mem, off);
@@ -1478,6 +1480,7 @@ csl_status batch_create(const csl_problem *problems, int count, const csl_batch_
   char *base = (char *)b->mem;
   b->d_desc = (SysDesc *)(base + o_desc);
   b->d_io = (IOPtr *)(base + o_io);
+  b->d_io_adj = (IOPtr *)(base + o_io_adj);
   b->d_info = (DevInfo *)(base + o_info);
   b->glob = (Glob *)(base + o_glob);
   auto cleanup = [&](csl_status st, const std::string &msg) {
@@ -1513,6 +1516,15 @@ csl_status batch_create(const csl_problem *problems, int count, const csl_batch_
   }
   if (o.block_threads == 512 && !b->wg512_ok)
     return cleanup(CSL_ERR_ARG, "block_threads 512 needs the FFT engine on every axis of every problem");
+  {
+    // the adjoint solves read conj(G) from each problem's gtmp and write
+    // conj(y) to its ytmp
+    std::vector<IOPtr> adj(count);
+    for (int i = 0; i < count; ++i) adj[i] = IOPtr{problems[i]->gtmp, problems[i]->ytmp};
+    if (hipMemcpy(b->d_io_adj, adj.data(), sizeof(IOPtr) * count, hipMemcpyHostToDevice) !=
+        hipSuccess)
+      return cleanup(CSL_ERR_HIP, "hipMemcpy of the adjoint pointers failed");
+  }
   const csl_status st = configure_batch(b, o.tile_points > 0 ? o.tile_points : 8192,
                                         o.lds_bytes, o.block_threads, b->use_graph);
   if (st != CSL_OK) {
@@ -1573,6 +1585,71 @@ csl_status batch_solve(csl_batch b, const double *const *f, double *const *z,
   if (first != CSL_OK)
     g_err = "batch: " + std::to_string(nbad) + " system(s) ended without convergence, the first"
             " with status: " + status_name(first);
+  return first;
+}
+
+csl_status batch_adjoint(csl_batch b, const double *const *z, const double *const *gz,
+                         double *const *gf, double *galpha, double *gbeta, double *ga,
+                         const csl_solve_opts *opts, csl_solve_info *infos, hipStream_t s) {
+  if (!b || !z || !gz) return fail(CSL_ERR_ARG, "NULL argument");
+  for (int i = 0; i < b->count; ++i) {
+    if (!z[i] || !gz[i]) return fail(CSL_ERR_ARG, "NULL vector in batch");
+    if (gf && gf[i] && (const double *)gf[i] == z[i])
+      return fail(CSL_ERR_ARG, "batch_adjoint: gf and z must not alias");
+  }
+  if (ga) {
+    // one coefficient gradient for the whole batch: every system on the
+    // grid of the first
+    const SysDesc &h0 = b->probs[0]->h;
+    for (int i = 1; i < b->count; ++i) {
+      const SysDesc &h = b->probs[i]->h;
+      bool same = h.d == h0.d;
+      for (int ax = 0; ax < 3 && same; ++ax) same = h.n[ax] == h0.n[ax] && h.h2[ax] == h0.h2[ax];
+      if (!same)
+        return fail(CSL_ERR_ARG, "batch_adjoint: a summed coefficient gradient needs every "
+                                 "system on one grid");
+    }
+  }
+  csl_solve_opts o{};
+  o.tol = b->params.tol;
+  o.maxit = b->params.maxit;
+  o.check_true_residual = b->params.check_true;
+  if (opts) o = *opts;
+  if (check_solve_opts(o) != CSL_OK) return CSL_ERR_ARG;
+  const SolveParams P = make_params(o.tol, o.maxit, o.check_true_residual, o.timeout_ms,
+                                    b->probs[0]->wall_khz);
+  // y_j = (K + conj(lambda_j) I)^{-1} G_j for every system: the block system
+  // with right-hand side conj(G_j), all systems in one persistent launch
+  for (int i = 0; i < b->count; ++i) {
+    const csl_problem p = b->probs[i];
+    HIPCHK(wg256::launch_conj((const double2 *)gz[i], p->gtmp, p->h.M, s));
+  }
+  HIPCHK(wg256::launch_init(b->d_desc, b->count, b->glob, s));
+  IOPtr none{nullptr, nullptr};
+  HIPCHK(solve_launch(b->block_threads, b->all2d, b->d_desc, b->d_io_adj, none, b->count, P,
+                      b->glob, b->grid, b->smem, s));
+  // gradients system by system, in order: ga accumulates the systems'
+  // coefficient gradients in a fixed order
+  for (int i = 0; i < b->count; ++i) {
+    const csl_problem p = b->probs[i];
+    HIPCHK(wg256::launch_adjoint(p->d_desc, p->h.d, p->h.M, p->ytmp, (const double2 *)z[i],
+                                 gf ? (double2 *)gf[i] : nullptr, ga, p->adj_part, p->adj_nblk,
+                                 galpha ? galpha + i : nullptr, gbeta ? gbeta + i : nullptr, s));
+  }
+  if (!infos) return CSL_OK;
+  std::vector<DevInfo> di(b->count);
+  HIPCHK(hipMemcpyAsync(di.data(), b->d_info, sizeof(DevInfo) * b->count, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  csl_status first = CSL_OK;
+  int nbad = 0;
+  for (int i = 0; i < b->count; ++i) {
+    const csl_status st = info_from_device(di[i], &infos[i]);
+    if (st != CSL_OK && first == CSL_OK) first = st;
+    nbad += st != CSL_OK;
+  }
+  if (first != CSL_OK)
+    g_err = "batch adjoint: " + std::to_string(nbad) + " system(s) ended without convergence, "
+            "the first with status: " + status_name(first);
   return first;
 }
 
