@@ -34,12 +34,18 @@ if ROOT not in sys.path:
 
 METRIC = "MINRES solves/s at relres 1e-8: batched mixed-precision vs plain FP64, 1 GPU"
 PEAK_HBM_GBS = 8000.0
-# Algorithmic HBM bytes per grid point per MINRES iteration (2-D, FP32
-# preconditioner): stencil 40 + Lanczos/w/x 128 (the w/x updates of two
-# steps share one pass: 32 bytes less per iteration than one pass per step)
-# + 3 sine-transform passes of 16 bytes read + written.
-BYTES_PER_POINT_ITER_2D_FP32P = 216.0
-BYTES_PER_POINT_ITER_2D_FP64 = 264.0
+# Algorithmic HBM bytes per grid point per MINRES iteration: what the method
+# streams with one read of each operand and one write of each result per
+# step: stencil 40 (z 16 in, a 8, A z 16 out) + Lanczos recurrence and w / x
+# updates 160 (seven 16-byte reads, three writes) + p sine-transform passes
+# of 4 s bytes (read + write of a complex value of s-byte parts):
+#   2-D FP64 (p = 3, s = 8) 296, 2-D FP32 preconditioner (s = 4) 248,
+#   3-D FP64 (p = 5) 360, 3-D FP32 preconditioner (p = 3: the xy-plane of
+#   the two leading axes transformed in one pass) 248.
+BYTES_MODEL = {(2, False): 296.0, (2, True): 248.0, (3, False): 360.0, (3, True): 248.0}
+# The same model with the w / x updates of two consecutive steps sharing one
+# pass (what the solver does): 32 bytes less per iteration.
+BYTES_MODEL_PAIRED = {k: v - 32.0 for k, v in BYTES_MODEL.items()}
 
 
 def log(*a):
@@ -123,16 +129,34 @@ def measured_traffic():
         return None
 
 
-def cpu_baseline(workload, systems_idx, gpu_solutions):
-    """Time the CPU oracle (NumPy/SciPy FP64, every thread pool held to one
-    thread) on a sample of the batch; the sample keeps the batch's mix of
-    grid sizes."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_threads() -> int:
+    """Threads the oracle may use here: the cores this process may run on,
+    at most 16 (the host share of one GPU on the measurement machines)."""
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def cpu_baseline(workload, systems_idx, gpu_solutions, threads):
+    """Time the CPU oracle (NumPy/SciPy FP64) on a sample of the batch; the
+    sample keeps the batch's mix of grid sizes.  threads = 1 holds every
+    thread pool (BLAS, OpenMP, SciPy's FFT) to one thread; otherwise the
+    pools and SciPy's FFT get `threads` workers."""
+    import scipy.fft as sfft
     from threadpoolctl import threadpool_limits
     from oracle import csl_oracle as O
     t_total = 0.0
     errs = []
     iters = []
-    with threadpool_limits(limits=1):
+    with threadpool_limits(limits=threads), sfft.set_workers(threads):
         for j in systems_idx:
             s = workload.systems[j]
             t0 = time.perf_counter()
@@ -176,11 +200,13 @@ def other_configs(C, WL, dev):
             sched = p.tune(f, z)
             reps = 20 if s.a.size < 100000 else 3
             ms, info = time_solve(C, p, f, z, reps)
-            bpp = (216.0 if fp32 else (264.0 if s.a.ndim == 2 else 328.0))
+            bpp = BYTES_MODEL[(s.a.ndim, fp32)]
             out[f"{name}_{'fp32p' if fp32 else 'fp64'}"] = {
                 "points": int(s.a.size), "ms_per_solve": ms, "iters": info["iters"],
                 "relres_true": info["relres_true"], "status": info["status_name"],
                 "alg_GBps": info["iters"] * s.a.size * bpp / ms / 1e6,
+                "alg_frac_of_8TBps": info["iters"] * s.a.size * bpp / ms / 1e6 / PEAK_HBM_GBS,
+                "bytes_per_point_iter": bpp,
                 "schedule": {"tile_points": sched["tile_points"],
                              "lds_bytes": sched["lds_bytes"],
                              "block_threads": sched["block_threads"]}}
@@ -207,9 +233,37 @@ def other_configs(C, WL, dev):
     t0 = time.perf_counter()
     worst = run()
     torch.cuda.synchronize()
+    ms_seq = (time.perf_counter() - t0) * 1e3
+    # the same work as one batched forward solve and one batched adjoint
+    # (two persistent launches for the 16 systems)
+    b = C.Batch(probs)
+    b.tune(fs)
+    zs = [torch.empty_like(f) for f in fs]
+
+    def run_batched():
+        ga = torch.zeros_like(at)
+        _, infos = b.solve(fs, zs, want_info=False)
+        gzs = [2.0 * (z - zt) for z, zt in zip(zs, zts)]
+        b.adjoint(zs, gzs, ga=ga, want_info=False)
+        return ga
+
+    run_batched()
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        run_batched()
+    torch.cuda.synchronize()
+    ms_batched = (time.perf_counter() - t0) / reps * 1e3
+    _, finfos = b.solve(fs, zs)
+    _, ainfos = b.adjoint(zs, [2.0 * (z - zt) for z, zt in zip(zs, zts)])
+    b.close()
     out["c5_adjoint"] = {"systems": len(w.systems), "points_each": int(w.systems[0].a.size),
-                         "ms_forward_plus_adjoint_all": (time.perf_counter() - t0) * 1e3,
-                         "max_relres": worst}
+                         "ms_forward_plus_adjoint_all": ms_seq,
+                         "ms_batched_forward_plus_adjoint": ms_batched,
+                         "speedup_batched_vs_sequential": ms_seq / ms_batched,
+                         "max_relres": worst,
+                         "max_relres_batched": max(i["relres_true"] for i in finfos + ainfos)}
     out["paradiag"] = paradiag_config(C, WL, dev)
     out["many_rhs"] = many_rhs_config(C, WL, dev)
     out["paper_table2a"] = table2a_config(C, WL, dev)
@@ -427,8 +481,9 @@ def main():
     Zcpu = [z.cpu().numpy() for z in Z]
 
     # algorithmic bytes of one launch (per-iteration model x iterations)
-    alg_bytes = sum(it * s.a.size * BYTES_PER_POINT_ITER_2D_FP32P
-                    for it, s in zip(iters, w.systems))
+    alg_bytes = sum(it * s.a.size * BYTES_MODEL[(2, True)] for it, s in zip(iters, w.systems))
+    alg_bytes_paired = sum(it * s.a.size * BYTES_MODEL_PAIRED[(2, True)]
+                           for it, s in zip(iters, w.systems))
     avg_launch_s = float(np.mean(launch_ms)) * 1e-3
     achieved = alg_bytes / avg_launch_s / 1e9
 
@@ -436,15 +491,14 @@ def main():
     probs64 = [C.Problem(a, s.lam.real, s.lam.imag, pinv_fp32=False)
                for a, s in zip(A, w.systems)]
     Z64 = [torch.empty_like(f) for f in F]
-    # each grid size's single-solve schedule from the problem autotuner
+    # every problem's single-solve schedule (tile size, LDS budget, workgroup
+    # size, chunk size, and the engines where they were chosen automatically)
+    # from the problem autotuner on its own right-hand side
     plain_sched = {}
     for p, f, z, s in zip(probs64, F, Z64, w.systems):
-        if s.n not in plain_sched:
-            t = p.tune(f, z)
-            plain_sched[s.n] = (t["tile_points"], t["lds_bytes"], t["block_threads"],
-                                t["tile_elems"])
-        else:
-            p.set_schedule(*plain_sched[s.n])
+        t = p.tune(f, z)
+        plain_sched.setdefault(str(s.n), []).append(
+            (t["tile_points"], t["lds_bytes"], t["block_threads"], t["tile_elems"]))
     for p, f, z in zip(probs64, F, Z64):
         C.minres_solve(p, f, z, want_info=False)
     torch.cuda.synchronize()
@@ -460,17 +514,43 @@ def main():
         _, inf = C.minres_solve(p, f, z)
         iters64.append(inf["iters"])
 
+    # ---------------- batched plain FP64 (one tuned graph replay): splits the
+    # speed-up over the plain solver into batching and precision
+    batch64 = C.Batch(probs64, tol=1e-8, maxit=1000, check_true=True, use_graph=True)
+    tuning64 = batch64.tune(F, Z64)
+    _, infos_b64 = batch64.solve(F, Z64)
+    for _ in range(max(1, args.warmup)):
+        batch64.solve(F, Z64, want_info=False)
+    torch.cuda.synchronize()
+    reps64 = max(3, args.steps // 2)
+    t0 = time.perf_counter()
+    for _ in range(reps64):
+        batch64.solve(F, Z64, want_info=False)
+    torch.cuda.synchronize()
+    b64_wall = (time.perf_counter() - t0) / reps64
+    b64_value = len(w.systems) / b64_wall
+    batch64.close()
+
     # ---------------- CPU oracle on a bounded sample
     cpu = None
     err_vs_oracle = None
     if not args.no_cpu_baseline:
         k = max(4, min(args.cpu_sample, len(w.systems)))
         idx = list(range(k))
-        t_cpu, errs, it_o = cpu_baseline(w, idx, Zcpu)
-        cpu = {"value": k / t_cpu, "unit": "solves/s", "cores": 1, "kind": "oracle",
-               "sample": f"first {k} systems of the batch (n = 63,127,255,511 in turn), "
-                         f"FP64 NumPy/SciPy, thread pools held to one thread, {t_cpu:.1f} s"}
-        err_vs_oracle = max(errs)
+        nthr = cpu_threads()
+        model = cpu_model()
+        t_cpu, errs, it_o = cpu_baseline(w, idx, Zcpu, nthr)
+        t_cpu1, errs1, _ = cpu_baseline(w, idx, Zcpu, 1)
+        sample = (f"first {k} systems of the batch (n = 63,127,255,511 in turn), FP64 "
+                  f"NumPy/SciPy, on {model}")
+        cpu = {"value": k / t_cpu, "unit": "solves/s", "cores": nthr, "kind": "oracle",
+               "sample": f"{sample}, thread pools and SciPy's FFT given {nthr} threads, "
+                         f"{t_cpu:.1f} s",
+               "cpu_model": model, "affinity_cores": len(os.sched_getaffinity(0)),
+               "single_thread": {"value": k / t_cpu1, "unit": "solves/s", "cores": 1,
+                                 "sample": f"{sample}, every thread pool held to one thread, "
+                                           f"{t_cpu1:.1f} s"}}
+        err_vs_oracle = max(errs + errs1)
         log("oracle iters", it_o, "gpu", iters[:k], "max rel err vs oracle", err_vs_oracle)
 
     extra = None if args.no_extra else other_configs(C, WL, dev)
@@ -496,13 +576,25 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": measured_traffic(),
                      "kernel": "solve_kernel", "avg_launch_ms": avg_launch_s * 1e3,
-                     "alg_bytes_per_launch": alg_bytes},
+                     "alg_bytes_per_launch": alg_bytes,
+                     "bytes_per_point_iter": BYTES_MODEL[(2, True)],
+                     "paired_update_model": {
+                         "bytes_per_point_iter": BYTES_MODEL_PAIRED[(2, True)],
+                         "alg_bytes_per_launch": alg_bytes_paired,
+                         "achieved": alg_bytes_paired / avg_launch_s / 1e9,
+                         "frac": alg_bytes_paired / avg_launch_s / 1e9 / PEAK_HBM_GBS}},
         "cpu_baseline": cpu,
         "plain_fp64": {"value": plain_value, "unit": "solves/s",
                        "ms_per_64": plain_wall * 1e3,
                        "iters_min": min(iters64), "iters_max": max(iters64),
-                       "schedules": {str(k): v for k, v in plain_sched.items()}},
+                       "schedules": plain_sched},
+        "batched_fp64": {"value": b64_value, "unit": "solves/s", "ms_per_64": b64_wall * 1e3,
+                         "iters_max": max(i["iters"] for i in infos_b64),
+                         "all_converged": all(i["status"] == 0 for i in infos_b64),
+                         "schedule": tuning64},
         "speedup_vs_plain_fp64": value / plain_value,
+        "speedup_split": {"batching_fp64": b64_value / plain_value,
+                          "precision_batched": value / b64_value},
         "iters": {"min": min(iters), "max": max(iters), "sum": int(sum(iters))},
         "max_relres_true": max(relres),
         "all_converged": all(s == 0 for s in statuses),

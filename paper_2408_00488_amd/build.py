@@ -1,5 +1,8 @@
 """Build the gfx950 shared library libcsl.so in-tree with hipcc.
 
+Each HIP source is compiled to an object in its own hipcc process (in
+parallel), then the objects are linked into libcsl.so.
+
 Usage: python -m paper_2408_00488_amd.build   (or build() from Python).
 """
 from __future__ import annotations
@@ -8,6 +11,7 @@ import os
 import shutil
 import subprocess
 import sys
+import tempfile
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -15,6 +19,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libcsl.so")
 SOURCES = ["csl_kernels.hip", "csl_kernels_wg512.hip", "csl_kernels_wg512x.hip", "csl_runtime.hip"]
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
 def hipcc() -> str:
@@ -26,18 +32,34 @@ def hipcc() -> str:
 
 def build(verbose: bool = False, extra: list[str] | None = None) -> str:
     """Compile every HIP source for gfx950 into libcsl.so (always rebuilds)."""
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-I", INCLUDE, "-I", CSRC]
-    cmd += [os.path.join(CSRC, s) for s in SOURCES]
-    cmd += (extra or []) + ["-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed")
+    cc = hipcc()
+    with tempfile.TemporaryDirectory(prefix="csl_build_") as tmpdir:
+        procs, objs = [], []
+        for src in SOURCES:
+            obj = os.path.join(tmpdir, os.path.splitext(src)[0] + ".o")
+            cmd = [cc] + FLAGS + ["-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src),
+                                  "-o", obj] + (extra or [])
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE,
+                                                stderr=subprocess.STDOUT, text=True)))
+            objs.append(obj)
+        failed = []
+        for src, pr in procs:
+            out, _ = pr.communicate()
+            if pr.returncode != 0:
+                sys.stderr.write(out)
+                failed.append(src)
+        if failed:
+            raise RuntimeError("hipcc failed on " + ", ".join(failed))
+        tmp = LIB + ".tmp"
+        cmd = [cc, "--offload-arch=gfx950", "-fPIC", "-shared"] + objs + ["-o", tmp]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError("hipcc link failed")
     os.replace(tmp, LIB)
     return LIB
 
