@@ -94,6 +94,7 @@ def copy_calibration():
 
 
 KERNEL_SOURCES = ["paper_2408_00488_amd/csrc/csl_kernels.hip",
+                  "paper_2408_00488_amd/csrc/csl_kernels_wg256h.hip",
                   "paper_2408_00488_amd/csrc/csl_kernels_wg512.hip",
                   "paper_2408_00488_amd/csrc/csl_kernels_wg512x.hip",
                   "paper_2408_00488_amd/csrc/csl_device.hpp",

@@ -92,7 +92,7 @@ enum {
 };
 
 /* How the orthonormal DST-I along an axis is computed (the W of
- * P^{-1} = W diag(s) W, Section 3).  Both give the same transform up to
+ * P^{-1} = W diag(s) W, Section 2.3).  All give the same transform up to
  * rounding. */
 enum {
     CSL_DST_AUTO = 0,       /* per axis, the faster of FFT and GEMM, timed on
@@ -102,10 +102,18 @@ enum {
     CSL_DST_FFT = 1,        /* FFT of the odd extension, staged in LDS
                                (CSL_ERR_ARG if an axis has n + 1 not a
                                power of two)                               */
-    CSL_DST_GEMM = 2        /* product with the dense n x n sine matrix on
+    CSL_DST_GEMM = 2,       /* product with the dense n x n sine matrix on
                                the matrix cores, for axes with
                                15 <= n <= 127 or n + 1 not a power of two
                                (any n up to 1022); FFT on the other axes   */
+    CSL_DST_GEMM16 = 3      /* the same axes as CSL_DST_GEMM, with the
+                               preconditioner's products on FP16 matrix
+                               cores: every line scaled by a power of two,
+                               matrix and line split into FP16 high and low
+                               parts, three products accumulated in FP32
+                               (FP32 accuracy).  Needs CSL_PREC_FP32; the
+                               FP64 pass of the Lanczos vectors keeps the
+                               FP64 product                                */
 };
 
 typedef struct csl_problem_opts {
@@ -181,7 +189,7 @@ csl_status problem_set_schedule(csl_problem p, int tile_points, int lds_bytes,
 /* Lanczos coefficients of the problem's last completed solve (its own
  * minres_solve / minres_adjoint, or its system within a batch_solve):
  * delta_1..delta_k, the diagonal of the tridiagonal T_k that MINRES builds
- * for P^{-1} A (Section 3), and gamma_2..gamma_{k+1}, its off-diagonal
+ * for P^{-1} A (Section 2.2), and gamma_2..gamma_{k+1}, its off-diagonal
  * (gamma_{k+1} couples step k to the next), k = the steps taken (at most
  * 4096 recorded).  delta, gamma: host arrays of cap entries (the first
  * min(cap, k) are written; may be NULL when cap = 0); *count = k.

@@ -301,8 +301,8 @@ def minres(A, Pinv, b, tol=1e-8, maxit=1000, check_true=True,
     iterate is advanced along the search directions w_j.  |eta_k| is the
     P^{-1}-norm of the residual b - A x_k.
 
-    Stopping rule (reading of Section 3's "reduction in relative residual
-    norms"): stop after iteration k when |eta_k|/|eta_0| <= tol and, if
+    Stopping rule (reading of Section 3, which stops on a relative residual
+    reduction without naming the norm): stop after iteration k when |eta_k|/|eta_0| <= tol and, if
     check_true, also ||b - A x_k||_2 / ||b||_2 <= tol (checked only once the
     first test has passed).  One iteration = one product with A and one
     with P^{-1}; the initial P^{-1} b is not counted.

@@ -183,8 +183,8 @@ def _info_dict(i: _SolveInfo) -> dict:
 
 
 _ABAR = {"mean": 0, "geomean": 1, "given": 2}
-_DST = {"auto": 0, "fft": 1, "gemm": 2}
-_DST_NAMES = {1: "fft", 2: "gemm"}
+_DST = {"auto": 0, "fft": 1, "gemm": 2, "gemm16": 3}
+_DST_NAMES = {1: "fft", 2: "gemm", 3: "gemm16"}
 
 
 class Problem:

@@ -96,9 +96,13 @@ struct SysDesc {
   double alpha, beta, abar;
   float alpha_f, beta_f, abar_f;
   const double *a;         // nodal coefficient (face coefficients are formed from it)
-  int gemm[3];             // 1: sine transforms along this axis by MFMA matrix product
+  int gemm[3];             // sine transforms along this axis by a matrix product on
+                           // the matrix cores: 0 no (FFT), 1 in the preconditioner's
+                           // precision, 2 FP16 products of split operands (FP32
+                           // preconditioner only; the FP64 row pass keeps 1)
   const double *Wm[3];     // padded orthonormal DST-I matrix per axis (FP64), if gemm
   const float *Wmf[3];     // FP32 copy
+  const void *Wmh[3];      // FP16 high and low parts of 2^kGemm16Shift W, if gemm == 2
   const double *mu[3];     // per-axis eigenvalues of L, FP64
   const float *mu_f[3];    // FP32 copies
   double2 *Tq;             // W_c (A zhat_j)               (column-blocked)
@@ -117,6 +121,9 @@ struct SysDesc {
 };
 
 constexpr int kLanczosCap = 4096;
+// The FP16 split-product engine stores the sine matrix scaled by 2^8, so that
+// the low parts of its entries stay normal FP16 numbers.
+constexpr int kGemm16Shift = 8;
 
 // Right-hand side and output of one system for one solve.
 struct IOPtr {

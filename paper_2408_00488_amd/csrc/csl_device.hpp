@@ -746,9 +746,129 @@ __device__ __forceinline__ void gemm_lines(const Cx<R> *X, Cx<R> *Y, int n, int 
   __syncthreads();
 }
 
+// ---------------------------------------------------------------------------
+// The same half-matrix product with FP16 matrix-core operations: operands
+// split into high and low FP16 parts, x = xh + xl, W = Wh + Wl, and
+// W x ~ Wh xh + Wh xl + Wl xh accumulated in FP32 (the dropped Wl xl is of
+// order 2^-22 relative), which keeps the product at FP32 accuracy.  FP16
+// has a narrow exponent range, so every column of X (the real or imaginary
+// part of one line) is scaled by a power of two that puts its largest
+// magnitude in [2^14, 2^15) before the split, and W is stored pre-scaled
+// by 2^kGemm16Shift; both scales are exact and undone on output.  Stored
+// matrix: four hp x hp FP16 blocks, Weh, Woh, Wel, Wol (even / odd columns
+// of the first h rows, high / low parts).  16x16x16 f16 tiles: lane l feeds
+// A[l%16][4(l/16) + j] and B[4(l/16) + j][l%16], j < 4; the accumulator row
+// of register r is 4(l/16) + r, its column l%16.
+// ---------------------------------------------------------------------------
+typedef _Float16 mfma_h4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void split_h(float x, _Float16 &hi, _Float16 &lo) {
+  hi = (_Float16)x;
+  lo = (_Float16)(x - (float)hi);
+}
+
+// Exponent e per column of the chunk (2 lp columns: re and im of each line)
+// such that max |x| 2^e lies in [2^14, 2^15); 0 for an all-zero column.
+__device__ __forceinline__ void gemm16_col_scales(const Cx<float> *X, int n, int np, int lp,
+                                                  int *colexp) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int l = wave; l < lp; l += NT / 64) {
+    float mr = 0.f, mi = 0.f;
+    for (int k = lane; k < n; k += 64) {
+      const Cx<float> v = X[l * np + k];
+      mr = fmaxf(mr, fabsf(v.x));
+      mi = fmaxf(mi, fabsf(v.y));
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      mr = fmaxf(mr, __shfl_xor(mr, off, 64));
+      mi = fmaxf(mi, __shfl_xor(mi, off, 64));
+    }
+    if (lane == 0) {
+      int er = 0, ei = 0;
+      if (mr > 0.f) (void)frexpf(mr, &er);   // mr = m 2^er, m in [0.5, 1)
+      if (mi > 0.f) (void)frexpf(mi, &ei);
+      colexp[2 * l] = mr > 0.f ? 15 - er : 0;
+      colexp[2 * l + 1] = mi > 0.f ? 15 - ei : 0;
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void gemm_lines16(const Cx<float> *X, Cx<float> *Y, int n, int np,
+                                             int lp, const _Float16 *__restrict__ W) {
+  __shared__ int colexp[128];
+  gemm16_col_scales(X, n, np, lp, colexp);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int h = (n + 1) >> 1, hp = gemm_hp(n);
+  const int nrb = hp >> 4;
+  const int ncb = (2 * lp + 15) >> 4;
+  const int kb = hp >> 4;   // K blocks of 16
+  const float *Xr = reinterpret_cast<const float *>(X);
+  float *Yr = reinterpret_cast<float *>(Y);
+  const int kl = lane >> 4;
+  const size_t blk2 = (size_t)hp * hp;
+  for (int blk = wave; blk < nrb * ncb; blk += NT / 64) {
+    const int rb = blk / ncb, cb = blk - rb * ncb;
+    const int m = rb * 16 + (lane & 15);
+    const int col = cb * 16 + (lane & 15);
+    const bool valid = col < 2 * lp;
+    const int line = valid ? (col >> 1) : 0, part = col & 1;
+    const int e = valid ? colexp[col] : 0;
+    const float sc = ldexpf(1.0f, e);
+    const CSL_G _Float16 *weh = gbl(W) + (size_t)m * hp + 4 * kl;
+    const CSL_G _Float16 *woh = weh + blk2;
+    const CSL_G _Float16 *wel = weh + 2 * blk2;
+    const CSL_G _Float16 *wol = weh + 3 * blk2;
+    // element k of the line sits at float index 2 k (re) or 2 k + 1 (im)
+    const float *xl = Xr + (size_t)line * np * 2 + part;
+    mfma_f4 ce = {0, 0, 0, 0}, co = {0, 0, 0, 0};
+    for (int kk = 0; kk < kb; ++kk) {
+      const mfma_h4 aeh = *(const CSL_G mfma_h4 *)(weh + kk * 16);
+      const mfma_h4 aoh = *(const CSL_G mfma_h4 *)(woh + kk * 16);
+      const mfma_h4 ael = *(const CSL_G mfma_h4 *)(wel + kk * 16);
+      const mfma_h4 aol = *(const CSL_G mfma_h4 *)(wol + kk * 16);
+      mfma_h4 beh, bel, boh, bol;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int ke = 2 * (kk * 16 + 4 * kl + j);   // even k; the odd one is ke + 1
+        const float xe = (valid && ke < n) ? xl[2 * ke] * sc : 0.f;
+        const float xo = (valid && ke + 1 < n) ? xl[2 * ke + 2] * sc : 0.f;
+        _Float16 hh, ll;
+        split_h(xe, hh, ll);
+        beh[j] = hh;
+        bel[j] = ll;
+        split_h(xo, hh, ll);
+        boh[j] = hh;
+        bol[j] = ll;
+      }
+      ce = __builtin_amdgcn_mfma_f32_16x16x16f16(ael, beh, ce, 0, 0, 0);
+      ce = __builtin_amdgcn_mfma_f32_16x16x16f16(aeh, bel, ce, 0, 0, 0);
+      ce = __builtin_amdgcn_mfma_f32_16x16x16f16(aeh, beh, ce, 0, 0, 0);
+      co = __builtin_amdgcn_mfma_f32_16x16x16f16(aol, boh, co, 0, 0, 0);
+      co = __builtin_amdgcn_mfma_f32_16x16x16f16(aoh, bol, co, 0, 0, 0);
+      co = __builtin_amdgcn_mfma_f32_16x16x16f16(aoh, boh, co, 0, 0, 0);
+    }
+    if (valid) {
+      const float us = ldexpf(1.0f, -(e + kGemm16Shift));
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int mr = rb * 16 + 4 * kl + r;
+        if (mr < h) {
+          Yr[((size_t)line * np + mr) * 2 + part] = (ce[r] + co[r]) * us;
+          const int mm = n - 1 - mr;
+          if (mm != mr) Yr[((size_t)line * np + mm) * 2 + part] = (ce[r] - co[r]) * us;
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // Transform engines: the same tile code drives the LDS FFT (FftEng) or the
 // MFMA sine-matrix product (GemmEng).
 template <typename R, int LDSB> struct FftEng {
+  static __device__ __forceinline__ const R *matrix(const SysDesc &, int) { return nullptr; }
   template <int U, class Load>
   static __device__ __forceinline__ void fill(Cx<R> *buf, const LineTile &t, Load &&load) {
     lines_fill<R, U>(buf, t, load);
@@ -795,6 +915,10 @@ template <typename R, int LDSB> struct FftEng {
 
 
 template <typename R, int LDSB> struct GemmEng {
+  static __device__ __forceinline__ const R *matrix(const SysDesc &S, int ax) {
+    if constexpr (sizeof(R) == 8) return reinterpret_cast<const R *>(S.Wm[ax]);
+    else return reinterpret_cast<const R *>(S.Wmf[ax]);
+  }
   template <int U, class Load>
   static __device__ __forceinline__ void fill(Cx<R> *buf, const LineTile &t, Load &&load) {
     const int np = gemm_np(t.n);
@@ -962,6 +1086,45 @@ template <typename R, int LDSB> struct GemmEng {
         if (pp[u] >= 0) post(pp[u], vv[u], pv[u]);
     }
     __syncthreads();
+  }
+};
+
+// The matrix-core engine with FP16 split products (FP32 preconditioner data):
+// the fills, stores and scaling of GemmEng, the product of gemm_lines16.
+template <int LDSB> struct GemmEng16 : GemmEng<float, LDSB> {
+  static __device__ __forceinline__ const float *matrix(const SysDesc &S, int ax) {
+    return reinterpret_cast<const float *>(S.Wmh[ax]);
+  }
+  static __device__ __forceinline__ Cx<float> *transform(Cx<float> *buf, const LineTile &t,
+                                                         const Cx<float> *, const float *W) {
+    const int np = gemm_np(t.n);
+    Cx<float> *Y = buf + t.lp * np;
+    gemm_lines16(buf, Y, t.n, np, t.lp, reinterpret_cast<const _Float16 *>(W));
+    return Y;
+  }
+  template <class Scale>
+  static __device__ __forceinline__ double scale_transform(Cx<float> *buf, const LineTile &t,
+                                                           const Cx<float> *, const float *W,
+                                                           Scale &&sc, Cx<float> **out) {
+    const int np = gemm_np(t.n);
+    Cx<float> *Y = buf + t.lp * np;
+    double acc = 0.0;
+    const int total = tile_elems(t);
+    for (int e = threadIdx.x; e < total; e += NT) {
+      int l, r;
+      if (split_elem(t, e, l, r)) {
+        Cx<float> v = Y[l * np + r];
+        const float s = sc(l, r);
+        acc += (double)s * ((double)v.x * (double)v.x + (double)v.y * (double)v.y);
+        v.x *= s;
+        v.y *= s;
+        Y[l * np + r] = v;
+      }
+    }
+    __syncthreads();
+    gemm_lines16(Y, buf, t.n, np, t.lp, reinterpret_cast<const _Float16 *>(W));
+    *out = buf;
+    return acc;
   }
 };
 

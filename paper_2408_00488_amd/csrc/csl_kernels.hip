@@ -9,6 +9,8 @@
 // csl_kernels_wg512.hip for 2-D ones (CSL_2D_FFT_ONLY) and
 // csl_kernels_wg512x.hip for either dimension (CSL_FFT_ONLY).  Eight waves
 // per workgroup at 128 registers keep twice the waves per CU in flight.
+// csl_kernels_wg256h.hip is a 256-thread solver with the FP16 split-product
+// sine-matrix engine (CSL_GEMM16) for the systems that use it.
 #include <math.h>
 
 #include "csl_device.hpp"
@@ -22,6 +24,9 @@
 #endif
 #ifndef CSL_FFT_ONLY
 #define CSL_FFT_ONLY 0
+#endif
+#ifndef CSL_GEMM16
+#define CSL_GEMM16 0
 #endif
 
 namespace csl {
@@ -43,7 +48,7 @@ __device__ __forceinline__ Cx<R> to_cx(double2 v) {
 template <int D, int LDSB, class E>
 __device__ __forceinline__ void tile_X(const SysDesc &S, const IOPtr &io, int iter, int tile, char *smem,
                        double *red) {
-  const double *Wm = S.Wm[D - 1];
+  const double *Wm = E::matrix(S, D - 1);
   Cx<double> *buf = reinterpret_cast<Cx<double> *>(smem);
   Cx<double> *twl = reinterpret_cast<Cx<double> *>(smem + LDSB);
   load_twiddles_cached<double>(twl, S.lg[D - 1]);
@@ -102,8 +107,7 @@ template <typename R, int D, int LDSB, class E>
 __device__ __forceinline__ void tile_Y(const SysDesc &S, int kind, int iter, int tile, char *smem, double *red) {
   Cx<R> *buf = reinterpret_cast<Cx<R> *>(smem);
   const int ax = (kind == K_Y) ? 0 : 1;
-  const R *Wm = (sizeof(R) == 8) ? reinterpret_cast<const R *>(S.Wm[ax])
-                                 : reinterpret_cast<const R *>(S.Wmf[ax]);
+  const R *Wm = E::matrix(S, ax);
   Cx<R> *twl = reinterpret_cast<Cx<R> *>(smem + LDSB);
   load_twiddles_cached<R>(twl, S.lg[ax]);
   CSL_G Cx<R> *T = gbl(reinterpret_cast<Cx<R> *>(S.T));
@@ -194,8 +198,7 @@ __device__ __forceinline__ void tile_Y(const SysDesc &S, int kind, int iter, int
 // ---------------------------------------------------------------------------
 template <typename R, int D, int LDSB, class E>
 __device__ __forceinline__ void tile_Z(const SysDesc &S, const IOPtr &io, int iter, int tile, char *smem) {
-  const R *Wm = (sizeof(R) == 8) ? reinterpret_cast<const R *>(S.Wm[D - 1])
-                                 : reinterpret_cast<const R *>(S.Wmf[D - 1]);
+  const R *Wm = E::matrix(S, D - 1);
   Cx<R> *buf = reinterpret_cast<Cx<R> *>(smem);
   Cx<R> *twl = reinterpret_cast<Cx<R> *>(smem + LDSB);
   const Ctl *C = S.ctl;
@@ -364,6 +367,21 @@ __device__ __forceinline__ void process_tile(const SysDesc &S, const IOPtr &io, 
   typedef FftEng<float, LDSB> F32;
   typedef GemmEng<double, LDSB> G64;
   typedef GemmEng<float, LDSB> G32;
+#if CSL_GEMM16
+  // FP16 split products: the preconditioner-precision passes of FP32
+  // preconditioners on axes marked 2 (the FP64 row pass keeps G64)
+  if (g && S.gemm[ax] == 2 && S.prec && kind != K_X && kind != K_PR) {
+    typedef GemmEng16<LDSB> G16;
+    if (kind == K_Z) {
+      if (d3) tile_Z<float, 3, LDSB, G16>(S, io, iter, tile, smem);
+      else tile_Z<float, 2, LDSB, G16>(S, io, iter, tile, smem);
+    } else {
+      if (d3) tile_Y<float, 3, LDSB, G16>(S, kind, iter, tile, smem, red);
+      else tile_Y<float, 2, LDSB, G16>(S, kind, iter, tile, smem, red);
+    }
+    return;
+  }
+#endif
   switch (kind) {
     case K_X:
       if (d3) g ? tile_X<3, LDSB, G64>(S, io, iter, tile, smem, red)
@@ -424,8 +442,7 @@ __device__ __forceinline__ void tile_pinv(const SysDesc &S, int pass, const doub
   const LineTile t = line_tile(S, ax, lp, tile);
   Cx<R> *twl = reinterpret_cast<Cx<R> *>(smem + LDSB);
   load_twiddles<R>(twl, t.lg);
-  const R *Wm = (sizeof(R) == 8) ? reinterpret_cast<const R *>(S.Wm[ax])
-                                 : reinterpret_cast<const R *>(S.Wmf[ax]);
+  const R *Wm = E::matrix(S, ax);
   // T is column-blocked: the row passes reach it in blocked order, the
   // strided passes through their tile addressing
   if (pass == 0) E::template fill<4>(buf, t, [&](int, int, int p) { return to_cx<R>(ldg(X + p)); });
@@ -985,6 +1002,12 @@ __global__ __launch_bounds__(NT) void pinv_pass_kernel(const SysDesc *__restrict
   extern __shared__ __align__(16) char smem[];
   const SysDesc &S = *sys;
   const int ax = (pass == 0 || pass == 4) ? D - 1 : (pass == 2 ? 0 : 1);
+  if constexpr (sizeof(R) == 4) {
+    if (S.gemm[ax] == 2) {
+      tile_pinv<R, D, LDSB, GemmEng16<LDSB>>(S, pass, x, y, blockIdx.x, smem);
+      return;
+    }
+  }
   if (S.gemm[ax]) tile_pinv<R, D, LDSB, GemmEng<R, LDSB>>(S, pass, x, y, blockIdx.x, smem);
   else tile_pinv<R, D, LDSB, FftEng<R, LDSB>>(S, pass, x, y, blockIdx.x, smem);
 }

@@ -1,5 +1,7 @@
 // Host-callable launch wrappers of the gfx950 kernels.  The device code is
-// built three times: csl::wg256 (256-thread workgroups; every kernel),
+// built four times: csl::wg256 (256-thread workgroups; every kernel),
+// csl::wg256h (the 256-thread persistent solver with the FP16 split-product
+// sine-matrix engine),
 // csl::wg512 (512-thread workgroups; the persistent solver for 2-D systems
 // whose transforms all run on the LDS FFT) and csl::wg512x (the same for
 // FFT systems of either dimension).
@@ -48,6 +50,15 @@ hipError_t launch_solve(const SysDesc *dsys, const IOPtr *dio, IOPtr io0, int ns
 hipError_t solve_occupancy(size_t smem, int *blocks_per_cu);
 
 }  // namespace wg512
+
+namespace wg256h {
+
+hipError_t upload_twiddles(const double2 *tw64, const float2 *tw32);
+hipError_t launch_solve(const SysDesc *dsys, const IOPtr *dio, IOPtr io0, int nsys,
+                        const SolveParams &P, Glob *G, int grid, size_t smem, hipStream_t s);
+hipError_t solve_occupancy(size_t smem, int *blocks_per_cu);
+
+}  // namespace wg256h
 
 namespace wg512x {
 

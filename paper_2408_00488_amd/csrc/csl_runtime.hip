@@ -65,6 +65,7 @@ csl_status ensure_twiddles(int dev) {
   HIPCHK(wg256::upload_twiddles(t64.data(), t32.data()));
   HIPCHK(wg512::upload_twiddles(t64.data(), t32.data()));
   HIPCHK(wg512x::upload_twiddles(t64.data(), t32.data()));
+  HIPCHK(wg256h::upload_twiddles(t64.data(), t32.data()));
   g_tw_ready[dev] = true;
   return CSL_OK;
 }
@@ -132,19 +133,26 @@ void sine_matrix(int n, std::vector<double> &W) {
 
 // The persistent solver instance of a workgroup size: 512 threads for
 // systems with the FFT on every axis (csl::wg512 when every system is 2-D,
-// csl::wg512x otherwise) or 256.
-hipError_t solve_launch(int wg, bool all2d, const SysDesc *dsys, const IOPtr *dio, IOPtr io0,
-                        int nsys, const SolveParams &P, Glob *G, int grid, size_t smem,
+// csl::wg512x otherwise) or 256 (csl::wg256h when a system has an axis on
+// the FP16 split-product engine, csl::wg256 otherwise).
+hipError_t solve_launch(int wg, bool all2d, bool g16, const SysDesc *dsys, const IOPtr *dio,
+                        IOPtr io0, int nsys, const SolveParams &P, Glob *G, int grid, size_t smem,
                         hipStream_t s) {
-  if (wg != 512) return wg256::launch_solve(dsys, dio, io0, nsys, P, G, grid, smem, s);
+  if (wg != 512)
+    return g16 ? wg256h::launch_solve(dsys, dio, io0, nsys, P, G, grid, smem, s)
+               : wg256::launch_solve(dsys, dio, io0, nsys, P, G, grid, smem, s);
   return all2d ? wg512::launch_solve(dsys, dio, io0, nsys, P, G, grid, smem, s)
                : wg512x::launch_solve(dsys, dio, io0, nsys, P, G, grid, smem, s);
 }
-hipError_t solve_occupancy_wg(int wg, bool all2d, size_t smem, int *blocks_per_cu) {
-  if (wg != 512) return wg256::solve_occupancy(smem, blocks_per_cu);
+hipError_t solve_occupancy_wg(int wg, bool all2d, bool g16, size_t smem, int *blocks_per_cu) {
+  if (wg != 512)
+    return g16 ? wg256h::solve_occupancy(smem, blocks_per_cu)
+               : wg256::solve_occupancy(smem, blocks_per_cu);
   return all2d ? wg512::solve_occupancy(smem, blocks_per_cu)
                : wg512x::solve_occupancy(smem, blocks_per_cu);
 }
+// Some axis of the system runs on the FP16 split-product engine.
+bool has_gemm16(const SysDesc &h) { return h.gemm[0] == 2 || h.gemm[1] == 2 || h.gemm[2] == 2; }
 // The 512-thread solver applies: the FFT on every axis.
 bool fft_everywhere(const SysDesc &h) { return !h.gemm[0] && !h.gemm[1] && !h.gemm[2]; }
 bool fft_everywhere_mask(int m) { return (m & 7) == 0; }
@@ -236,6 +244,7 @@ struct csl_batch_s {
   int block_threads = 256;
   bool wg512_ok = false; // every problem allows the 512-thread solver
   bool all2d = true;     // every problem is 2-D (the 2-D-only 512-thread instance)
+  bool g16 = false;      // some problem has an axis on the FP16 split-product engine
 };
 
 struct csl_paradiag_s {
@@ -484,7 +493,7 @@ csl_status configure_single(csl_problem p, int tile_points, int lds_bytes, int b
   if (h.maxtile > p->part_cap) return fail(CSL_ERR_ARG, "chunking exceeds the partial-sum slots");
   const int wg = resolve_wg(block_threads, p->wg512_ok);
   int bpc = 0;
-  HIPCHK(solve_occupancy_wg(wg, p->h0.d == 2, sm, &bpc));
+  HIPCHK(solve_occupancy_wg(wg, p->h0.d == 2, has_gemm16(p->h0), sm, &bpc));
   const int cap = std::max(1, bpc) * p->cus;
   const int tp = tile_points > 0 ? tile_points : (int)std::min<long long>(1 << 30, h.M / cap);
   set_tile_points(h, tp);
@@ -544,7 +553,8 @@ csl_status tune_engines(csl_problem p, int elig, int req, hipStream_t s, int *be
       if (r == 1) err = hipEventRecord(e0, s);   // the first solve is a warm-up
       if (err == hipSuccess) err = wg256::launch_init(p->d_desc, 1, p->glob, s);
       if (err == hipSuccess)
-        err = solve_launch(p->block_threads, h.d == 2, p->d_desc, nullptr, io0, 1, P, p->glob,
+        err = solve_launch(p->block_threads, h.d == 2, has_gemm16(h), p->d_desc, nullptr, io0, 1,
+                           P, p->glob,
                            p->grid1,
                            p->smem, s);
     }
@@ -597,7 +607,7 @@ csl_status configure_batch(csl_batch b, int tile_points, int lds_bytes, int bloc
   b->lds_bytes = smem <= 32768 ? 32768 : 65536;
   b->block_threads = resolve_wg(block_threads, b->wg512_ok);
   int bpc = 0;
-  HIPCHK(solve_occupancy_wg(b->block_threads, b->all2d, smem, &bpc));
+  HIPCHK(solve_occupancy_wg(b->block_threads, b->all2d, b->g16, smem, &bpc));
   // tiles are claimed dynamically, so a full-occupancy grid keeps every CU
   // busy whatever the mix of systems
   const int cap = std::max(1, bpc) * b->probs[0]->cus;
@@ -609,7 +619,7 @@ csl_status configure_batch(csl_batch b, int tile_points, int lds_bytes, int bloc
   if (ok) {
     ok = wg256::launch_init(b->d_desc, b->count, b->glob, cs) == hipSuccess;
     IOPtr none{nullptr, nullptr};
-    ok = ok && solve_launch(b->block_threads, b->all2d, b->d_desc, b->d_io, none, b->count,
+    ok = ok && solve_launch(b->block_threads, b->all2d, b->g16, b->d_desc, b->d_io, none, b->count,
                             b->params,
                             b->glob, b->grid, b->smem, cs) == hipSuccess;
     hipGraph_t g = nullptr;
@@ -702,6 +712,10 @@ static csl_status create_problem_impl(const csl_grid *grid, const double *a_noda
     return fail(CSL_ERR_ARG, "unknown preconditioner precision");
   if (o.abar_rule == CSL_ABAR_GIVEN && !(o.abar > 0 && std::isfinite(o.abar)))
     return fail(CSL_ERR_ARG, "given abar must be finite and positive");
+  if (o.dst_engine < CSL_DST_AUTO || o.dst_engine > CSL_DST_GEMM16)
+    return fail(CSL_ERR_ARG, "unknown sine-transform engine");
+  if (o.dst_engine == CSL_DST_GEMM16 && o.pinv_prec != CSL_PREC_FP32)
+    return fail(CSL_ERR_ARG, "the FP16 split-product engine needs the FP32 preconditioner");
 
   SysDesc h{};
   {
@@ -785,8 +799,9 @@ static csl_status create_problem_impl(const csl_grid *grid, const double *a_noda
   const size_t o_gtmp = take(vec);
   const size_t o_apart = take(sizeof(double) * 2 * p->adj_nblk);
   const size_t o_lz = take(sizeof(double) * (2 * kLanczosCap + 1));
-  size_t o_w[3] = {0, 0, 0}, o_wf[3] = {0, 0, 0};
+  size_t o_w[3] = {0, 0, 0}, o_wf[3] = {0, 0, 0}, o_wh[3] = {0, 0, 0};
   int elig = 0, req = 0;
+  const bool g16 = o.dst_engine == CSL_DST_GEMM16;
   for (int ax = 0; ax < h.d; ++ax) {
     if (!gemm_eligible(h.n[ax])) continue;
     elig |= 1 << ax;
@@ -794,6 +809,7 @@ static csl_status create_problem_impl(const csl_grid *grid, const double *a_noda
     const size_t wsz = (size_t)2 * gemm_half(h.n[ax]) * gemm_half(h.n[ax]);
     o_w[ax] = take(sizeof(double) * wsz);
     o_wf[ax] = take(sizeof(float) * wsz);
+    if (g16) o_wh[ax] = take(sizeof(_Float16) * 2 * wsz);   // high and low parts
   }
   hipError_t e = hipMalloc(&p->mem, off);
   if (e != hipSuccess) {
@@ -830,6 +846,7 @@ static csl_status create_problem_impl(const csl_grid *grid, const double *a_noda
     h.gemm[ax] = 0;
     h.Wm[ax] = (elig >> ax & 1) ? (const double *)(base + o_w[ax]) : nullptr;
     h.Wmf[ax] = (elig >> ax & 1) ? (const float *)(base + o_wf[ax]) : nullptr;
+    h.Wmh[ax] = (g16 && (elig >> ax & 1)) ? (const void *)(base + o_wh[ax]) : nullptr;
   }
 
   // per-axis eigenvalues of L: (4/h^2) sin^2(k pi / (2(n+1)))
@@ -862,6 +879,7 @@ static csl_status create_problem_impl(const csl_grid *grid, const double *a_noda
   PCHK(hipMemcpyAsync(d_muf, muf.data(), sizeof(float) * nmu, hipMemcpyHostToDevice, s));
   std::vector<double> Wt[3];
   std::vector<float> Wtf[3];
+  std::vector<_Float16> Wth[3];
   for (int ax = 0; ax < h.d; ++ax) {
     if (!(elig >> ax & 1)) continue;
     sine_matrix(h.n[ax], Wt[ax]);
@@ -871,6 +889,20 @@ static csl_status create_problem_impl(const csl_grid *grid, const double *a_noda
                         hipMemcpyHostToDevice, s));
     PCHK(hipMemcpyAsync((void *)h.Wmf[ax], Wtf[ax].data(), sizeof(float) * Wtf[ax].size(),
                         hipMemcpyHostToDevice, s));
+    if (g16) {
+      // 2^kGemm16Shift W split into FP16 high and low parts: both even / odd
+      // blocks of the high part, then both of the low part
+      const size_t wsz = Wt[ax].size();
+      Wth[ax].resize(2 * wsz);
+      for (size_t i = 0; i < wsz; ++i) {
+        const double w = std::ldexp(Wt[ax][i], kGemm16Shift);
+        const _Float16 hi = (_Float16)w;
+        Wth[ax][i] = hi;
+        Wth[ax][wsz + i] = (_Float16)(w - (double)hi);
+      }
+      PCHK(hipMemcpyAsync((void *)h.Wmh[ax], Wth[ax].data(), sizeof(_Float16) * Wth[ax].size(),
+                          hipMemcpyHostToDevice, s));
+    }
   }
   PCHK(hipMemcpyAsync(p->d_desc, &h, sizeof(SysDesc), hipMemcpyHostToDevice, s));
   PCHK(wg256::launch_coef_stats(p->d_desc, h.d, h.M, p->stats_part, p->stats_nblk, p->stats, s));
@@ -899,10 +931,6 @@ static csl_status create_problem_impl(const csl_grid *grid, const double *a_noda
   p->h = h;
   PCHK(hipMemcpyAsync(p->d_desc, &p->h, sizeof(SysDesc), hipMemcpyHostToDevice, s));
   PCHK(hipStreamSynchronize(s));
-  if (o.dst_engine < CSL_DST_AUTO || o.dst_engine > CSL_DST_GEMM) {
-    free_problem(p);
-    return fail(CSL_ERR_ARG, "unknown sine-transform engine");
-  }
   if (o.dst_engine == CSL_DST_FFT && req) {
     free_problem(p);
     return fail(CSL_ERR_ARG, "an axis with n + 1 not a power of two needs the dense sine-matrix "
@@ -911,7 +939,7 @@ static csl_status create_problem_impl(const csl_grid *grid, const double *a_noda
   int mask = req;
   if (forced_mask >= 0) {
     mask = forced_mask & elig;
-  } else if (o.dst_engine == CSL_DST_GEMM) {
+  } else if (o.dst_engine == CSL_DST_GEMM || g16) {
     mask = elig;
   } else if (o.dst_engine == CSL_DST_AUTO && elig != req) {
     const ShapeKey key{dev, h.d, h.n[0], h.n[1], h.n[2], h.prec};
@@ -934,7 +962,7 @@ static csl_status create_problem_impl(const csl_grid *grid, const double *a_noda
       g_engine_cache[key] = mask;
     }
   }
-  for (int ax = 0; ax < 3; ++ax) p->h.gemm[ax] = (mask >> ax) & 1;
+  for (int ax = 0; ax < 3; ++ax) p->h.gemm[ax] = ((mask >> ax) & 1) ? (g16 ? 2 : 1) : 0;
   PCHK(hipMemcpyAsync(p->d_desc, &p->h, sizeof(SysDesc), hipMemcpyHostToDevice, s));
   PCHK(hipStreamSynchronize(s));
   p->h0 = p->h;
@@ -1038,7 +1066,8 @@ csl_status problem_info(csl_problem p, double *abar, double *a_min, double *a_ma
 
 csl_status problem_dst_engines(csl_problem p, int engines[3]) {
   if (!p || !engines) return fail(CSL_ERR_ARG, "NULL argument");
-  for (int ax = 0; ax < 3; ++ax) engines[ax] = p->h.gemm[ax] ? CSL_DST_GEMM : CSL_DST_FFT;
+  for (int ax = 0; ax < 3; ++ax)
+    engines[ax] = p->h.gemm[ax] == 2 ? CSL_DST_GEMM16 : (p->h.gemm[ax] ? CSL_DST_GEMM : CSL_DST_FFT);
   return CSL_OK;
 }
 
@@ -1060,7 +1089,8 @@ static csl_status run_single(csl_problem p, const double2 *f, double2 *x, const 
                              hipStream_t s) {
   HIPCHK(wg256::launch_init(p->d_desc, 1, p->glob, s));
   IOPtr io0{f, x};
-  HIPCHK(solve_launch(p->block_threads, p->h.d == 2, p->d_desc, nullptr, io0, 1, P, p->glob,
+  HIPCHK(solve_launch(p->block_threads, p->h.d == 2, has_gemm16(p->h), p->d_desc, nullptr, io0, 1,
+                      P, p->glob,
                       p->grid1, p->smem,
                       s));
   return CSL_OK;
@@ -1257,7 +1287,7 @@ csl_status minres_solve_noalloc(const csl_grid *grid, const double *a_nodal, dou
   // on every axis), about one tile per workgroup and phase
   const int wg = 512;
   int bpc = 0;
-  HIPCHK(solve_occupancy_wg(wg, h.d == 2, smem, &bpc));
+  HIPCHK(solve_occupancy_wg(wg, h.d == 2, false, smem, &bpc));
   const int cap = std::max(1, bpc) * sd.cus;
   set_tile_points(h, (int)std::min<long long>(1 << 30, h.M / cap));
   int mt = 1;
@@ -1267,7 +1297,7 @@ csl_status minres_solve_noalloc(const csl_grid *grid, const double *a_nodal, dou
                                     sd.wall_khz);
   HIPCHK(wg256::launch_init(d_desc, 1, glob, s));
   IOPtr io0{(const double2 *)f, (double2 *)z};
-  HIPCHK(solve_launch(wg, h.d == 2, d_desc, nullptr, io0, 1, P, glob, std::max(1, std::min(mt, cap)),
+  HIPCHK(solve_launch(wg, h.d == 2, false, d_desc, nullptr, io0, 1, P, glob, std::max(1, std::min(mt, cap)),
                       smem, s));
   if (!info) return CSL_OK;
   DevInfo di;
@@ -1324,8 +1354,9 @@ csl_status problem_tune(csl_problem p, const double *f, double *z, csl_batch_tun
   }
   const int nmask = (p->opts.dst_engine == CSL_DST_AUTO && mask0 != req) ? 2 : 1;
   const int masks[2] = {mask0, req};
+  const int gcode = p->opts.dst_engine == CSL_DST_GEMM16 ? 2 : 1;
   auto set_mask = [&](int m) {
-    for (int ax = 0; ax < 3; ++ax) p->h0.gemm[ax] = p->h.gemm[ax] = (m >> ax) & 1;
+    for (int ax = 0; ax < 3; ++ax) p->h0.gemm[ax] = p->h.gemm[ax] = ((m >> ax) & 1) ? gcode : 0;
     p->wg512_ok = fft_everywhere(p->h0);
   };
   struct Cand {
@@ -1513,6 +1544,7 @@ csl_status batch_create(const csl_problem *problems, int count, const csl_batch_
   for (int i = 0; i < count; ++i) {
     b->wg512_ok = b->wg512_ok && problems[i]->wg512_ok;
     b->all2d = b->all2d && problems[i]->h.d == 2;
+    b->g16 = b->g16 || has_gemm16(problems[i]->h);
   }
   if (o.block_threads == 512 && !b->wg512_ok)
     return cleanup(CSL_ERR_ARG, "block_threads 512 needs the FFT engine on every axis of every problem");
@@ -1568,7 +1600,7 @@ csl_status batch_solve(csl_batch b, const double *const *f, double *const *z,
   } else {
     HIPCHK(wg256::launch_init(b->d_desc, b->count, b->glob, s));
     IOPtr none{nullptr, nullptr};
-    HIPCHK(solve_launch(b->block_threads, b->all2d, b->d_desc, b->d_io, none, b->count, b->params,
+    HIPCHK(solve_launch(b->block_threads, b->all2d, b->g16, b->d_desc, b->d_io, none, b->count, b->params,
                         b->glob, b->grid, b->smem, s));
   }
   if (!infos) return CSL_OK;
@@ -1626,7 +1658,7 @@ csl_status batch_adjoint(csl_batch b, const double *const *z, const double *cons
   }
   HIPCHK(wg256::launch_init(b->d_desc, b->count, b->glob, s));
   IOPtr none{nullptr, nullptr};
-  HIPCHK(solve_launch(b->block_threads, b->all2d, b->d_desc, b->d_io_adj, none, b->count, P,
+  HIPCHK(solve_launch(b->block_threads, b->all2d, b->g16, b->d_desc, b->d_io_adj, none, b->count, P,
                       b->glob, b->grid, b->smem, s));
   // gradients system by system, in order: ga accumulates the systems'
   // coefficient gradients in a fixed order
