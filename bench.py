@@ -97,6 +97,7 @@ KERNEL_SOURCES = ["paper_2408_00488_amd/csrc/csl_kernels.hip",
                   "paper_2408_00488_amd/csrc/csl_kernels_wg256h.hip",
                   "paper_2408_00488_amd/csrc/csl_kernels_wg512.hip",
                   "paper_2408_00488_amd/csrc/csl_kernels_wg512x.hip",
+                  "paper_2408_00488_amd/csrc/csl_kernels_wg1024p.hip",
                   "paper_2408_00488_amd/csrc/csl_device.hpp",
                   "paper_2408_00488_amd/csrc/csl_common.hpp"]
 TRAFFIC_FILE = "profiles/solve_kernel_batch64_hbm_traffic.txt"

@@ -12,7 +12,8 @@ constexpr int MAX_LG = 11;     // log2(TWN)
 // Phase kinds of one MINRES iteration.  The Lanczos vectors are kept
 // transformed along the contiguous axis (W_c v, W_c the orthonormal sine
 // transform of that axis, which is its own inverse); inner products are
-// unchanged by it.  A 2-D iteration j is X, Y, Z; a 3-D one X, Y1, Y, Y1I, Z.
+// unchanged by it.  A 2-D iteration j is X, Y, Z; a 3-D one X, Y1, Y, Y1I, Z,
+// or X, Y, Z with the plane pass (SysDesc::plane).
 enum Kind : int {
   K_X = 0,    // contiguous-axis rows: q = A zhat_j (stencil), delta_j partial,
               // forward transform of q -> Tq (FP64).  Iteration 0: W_c f -> Tv_1
@@ -88,6 +89,9 @@ struct SysDesc {
                   // (row, c) at ((c / B) rows + row) B + c % B, so a strided
                   // tile's lines are one contiguous block
   int rpt;        // rows per tile of the residual pass
+  int plane;      // 3-D: the transforms along axes 1 and 0 in one phase (K_Y), on
+                  // one plane of those axes at a time held in LDS (lgB = 0: the
+                  // plane of contiguous-axis index c is contiguous in Tq, Tv, T)
   int nchunk[K_NKINDS];  // LDS-sized chunks of each phase kind
   int cpt[K_NKINDS];     // chunks per tile (one scheduling unit)
   int ntile[K_NKINDS];   // ceil(nchunk / cpt)
@@ -121,6 +125,15 @@ struct SysDesc {
 };
 
 constexpr int kLanczosCap = 4096;
+// Dynamic LDS of the plane-phase solver instance (the whole 160 KiB of a CU
+// less a margin for its static variables), and what a plane needs of it: the
+// plane (FP32, padded to 128 bytes), 16 staged lines of up to 256 points, the
+// twiddles of both lengths.
+constexpr int kPlaneLdsBytes = 163840 - 512;
+__host__ __device__ inline int plane_lds_bytes(int n0, int n1, int lg0, int lg1) {
+  const int pb = (n0 * n1 * 8 + 127) & ~127;
+  return pb + 16 * 256 * 8 + ((1 << lg0) / 4 + (1 << lg1) / 4) * 8;
+}
 // The FP16 split-product engine stores the sine matrix scaled by 2^8, so that
 // the low parts of its entries stay normal FP16 numbers.
 constexpr int kGemm16Shift = 8;

@@ -305,12 +305,22 @@ __device__ __forceinline__ LineTile line_tile(const SysDesc &S, int ax, int lp, 
 // lp x B blocks (contiguous runs in memory) while its LDS accesses stay
 // conflict-free (a row segment is 256 bytes of LDS).
 // Returns the tile-local (line, position) and the blocked index q.
+// With a block width of one (lgB = 0, planes of the two leading axes
+// contiguous) the rows are the contiguous direction: lanes then run over the
+// lp rows first.
 template <int LGW>
 __device__ __forceinline__ int tile_elems_blk(const LineTile &t) {
+  if (t.lgB == 0) return t.n << t.lgl;
   return ((t.n + (1 << LGW) - 1) >> LGW) << (LGW + t.lgl);
 }
 template <int LGW>
 __device__ __forceinline__ bool split_blk(const LineTile &t, int e, int &l, int &r, int &q) {
+  if (t.lgB == 0) {
+    l = e & (t.lp - 1);
+    r = e >> t.lgl;
+    q = r * t.qblk + t.qrow0 + l;
+    return l < t.nl && r < t.n;
+  }
   const int rl = e & ((1 << LGW) - 1);
   l = (e >> LGW) & (t.lp - 1);
   r = ((e >> (LGW + t.lgl)) << LGW) + rl;

@@ -28,6 +28,12 @@
 #ifndef CSL_GEMM16
 #define CSL_GEMM16 0
 #endif
+#ifndef CSL_PLANE
+#define CSL_PLANE 0
+#endif
+#ifndef CSL_WAVES_PER_EU
+#define CSL_WAVES_PER_EU (CSL_NT / 128)
+#endif
 
 namespace csl {
 namespace CSL_KNS {
@@ -349,6 +355,253 @@ __device__ __forceinline__ void tile_PR(const SysDesc &S, const IOPtr &io, int t
   if (threadIdx.x == 0) S.part[tile] = s;
 }
 
+#if CSL_PLANE
+// ---------------------------------------------------------------------------
+// Plane phase (3-D, FP32 preconditioner, FFT on axes 0 and 1): tile c is the
+// plane of contiguous-axis index c, contiguous in Tq, Tv and T (block width
+// one).  In one pass over it:
+//   Tv_{j+1} = Tq - (delta_j/gamma_j) Tv_j - (gamma_j/gamma_{j-1}) Tv_{j-1}
+//     (FP64, stored; Tv_1 at iteration 0), rounded to FP32 into the plane
+//     held in LDS;
+//   the forward transforms of the axis-1 lines, then of the axis-0 lines
+//     with the per-mode factor and the partial of gamma_{j+1}^2, their
+//     inverses, then the inverses of the axis-1 lines;
+//   T' written once.
+// The values are those of the three strided phases (K_Y1, K_Y, K_Y1I) with
+// their FP32 intermediate kept in LDS instead of T.
+//
+// Each wave transforms whole lines on its own: a line of the odd extension
+// (L = 2^lg points) takes L/4 lanes, one radix-4 butterfly per lane and
+// Stockham stage (a radix-2 stage first when lg is odd), so a wave holds
+// 256/L lines and exchanges values between stages through its own 2 KiB of
+// LDS with no workgroup barrier.  A stage computes exactly what the
+// workgroup-wide transform computes for the same butterfly.
+// ---------------------------------------------------------------------------
+constexpr int kPlaneWaveElts = 256;   // complex FP32 values per wave buffer
+
+// Order the wave's own LDS accesses around an exchange between its lanes:
+// LDS operations of one wave complete in issue order, so only the compiler
+// has to be kept from moving them.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// FFT of one line of L = 2^lg points (lg >= 2) by Q = L/4 lanes.  Lane j
+// enters with a[q] = x[j + q Q] and leaves with a[q] = X[j + q Q]; the line
+// occupies elements lo .. lo + L - 1 of the wave buffer wb.
+__device__ __forceinline__ void wave_fft_line(Cx<float> a[4], Cx<float> *wb, int lo, int j, int lg,
+                                              const Cx<float> *twl) {
+  const int L = 1 << lg, Q = L >> 2;
+  int Ns = 1;
+  if (lg & 1) {
+    // radix-2 stage: butterflies j and j + Q, of (x[b], x[b + L/2])
+    wb[lo + 2 * j] = cadd(a[0], a[2]);
+    wb[lo + 2 * j + 1] = csub(a[0], a[2]);
+    wb[lo + 2 * (j + Q)] = cadd(a[1], a[3]);
+    wb[lo + 2 * (j + Q) + 1] = csub(a[1], a[3]);
+    wave_lds_sync();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) a[q] = wb[lo + j + q * Q];
+    Ns = 2;
+  }
+  for (;; Ns <<= 2) {
+    const int k = j & (Ns - 1);
+    Cx<float> x0 = a[0], x1 = a[1], x2 = a[2], x3 = a[3];
+    if (Ns > 1) {
+      const Cx<float> w1 = twl[k * (L / (4 * Ns))];
+      const Cx<float> w2 = cmul(w1, w1);
+      const Cx<float> w3 = cmul(w2, w1);
+      x1 = cmul(x1, w1);
+      x2 = cmul(x2, w2);
+      x3 = cmul(x3, w3);
+    }
+    const Cx<float> t0 = cadd(x0, x2), t1 = csub(x0, x2);
+    const Cx<float> t2 = cadd(x1, x3), t3 = csub(x1, x3);
+    const Cx<float> mt3 = {t3.y, -t3.x};   // -i t3
+    a[0] = cadd(t0, t2);
+    a[1] = cadd(t1, mt3);
+    a[2] = csub(t0, t2);
+    a[3] = csub(t1, mt3);
+    // the last stage (Ns = Q) leaves output j + q Q in a[q]
+    if (4 * Ns == L) break;
+    const int base = lo + ((j - k) << 2) + k;
+    wave_lds_sync();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) wb[base + q * Ns] = a[q];
+    wave_lds_sync();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) a[q] = wb[lo + j + q * Q];
+  }
+  wave_lds_sync();
+}
+
+// Odd extension of a line of n = L/2 - 1 points read from the plane: x[m] =
+// v[m-1] below L/2, -v[L-1-m] above it, zero at 0 and L/2.
+__device__ __forceinline__ Cx<float> plane_ext(const Cx<float> *line, int ldp, int m, int L, bool act) {
+  const int N = L >> 1;
+  if (!act || m == 0 || m == N) return Cx<float>{0.f, 0.f};
+  if (m < N) return line[(m - 1) * ldp];
+  const Cx<float> v = line[(L - 1 - m) * ldp];
+  return Cx<float>{-v.x, -v.y};
+}
+
+// Sine transform, in place, of the nlines lines of the plane (line l at
+// plane[l ldl + r ldp], n = 2^(lg-1) - 1 points).
+__device__ __forceinline__ void plane_dst_lines(Cx<float> *plane, Cx<float> *wbuf, const Cx<float> *twl,
+                                                int nlines, int lg, int ldl, int ldp) {
+  const int L = 1 << lg, Q = L >> 2, N = L >> 1;
+  const int G = 64 >> (lg - 2);   // lines per wave
+  const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
+  const int g = t >> (lg - 2), j = t & (Q - 1);
+  Cx<float> *wb = wbuf + w * kPlaneWaveElts;
+  const int lo = g * L;
+  const float cf = 1.0f / sqrtf((float)L);
+  for (int l0 = w * G; l0 < nlines; l0 += (NT / 64) * G) {
+    const int l = l0 + g;
+    const bool act = l < nlines;
+    Cx<float> *line = plane + (size_t)(act ? l : 0) * ldl;
+    Cx<float> a[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) a[q] = plane_ext(line, ldp, j + q * Q, L, act);
+    wave_fft_line(a, wb, lo, j, lg, twl);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int k = j + q * Q;
+      if (act && k >= 1 && k < N) line[(k - 1) * ldp] = dst_out(a[q], cf);
+    }
+  }
+}
+
+__device__ __forceinline__ void tile_YP(const SysDesc &S, int iter, int tile, char *smem,
+                                        double *red) {
+  typedef float R;
+  const int n0 = S.n[0], n1 = S.n[1];
+  const int rows = S.rows;   // n0 n1: the plane
+  const int c = tile;
+  Cx<R> *plane = reinterpret_cast<Cx<R> *>(smem);
+  const size_t pb = ((size_t)rows * sizeof(Cx<R>) + 127) & ~(size_t)127;
+  Cx<R> *wbuf = reinterpret_cast<Cx<R> *>(smem + pb);
+  const int lg0 = S.lg[0], lg1 = S.lg[1];
+  Cx<R> *tw0 = wbuf + (NT / 64) * kPlaneWaveElts;
+  Cx<R> *tw1 = tw0 + ((1 << lg0) >> 2);
+  // the line buffer's twiddle cache lies inside the plane: restage later
+  if (threadIdx.x == 0) s_twkey = -1;
+  load_twiddles<R>(tw0, lg0);
+  load_twiddles<R>(tw1, lg1);
+  const size_t off = (size_t)c * rows;   // element (row, c) at c rows + row
+  const int j = iter;
+  if (j == 0) {
+    const CSL_G double2 *__restrict__ v1 = gbl(S.Tv[1]) + off;
+    for (int e = threadIdx.x; e < rows; e += NT) plane[e] = to_cx<R>(ldg(v1 + e));
+  } else {
+    const Ctl *C = S.ctl;
+    const double g = ld_ctl(&C->gamma), go = ld_ctl(&C->gamma_old);
+    const double dl = ld_ctl(&C->delta);
+    const double cd = dl / g, cg = g / go;
+    const CSL_G double2 *__restrict__ tq = gbl(S.Tq) + off;
+    const CSL_G double2 *__restrict__ vj = gbl(S.Tv[j & 1]) + off;
+    CSL_G double2 *__restrict__ vout = gbl(S.Tv[(j + 1) & 1]) + off;   // holds Tv_{j-1}
+    const bool has_vm1 = j >= 2;
+    constexpr int U = 4;
+    for (int e0 = 0; e0 < rows; e0 += NT * U) {
+      double2 q[U], a1[U], a0[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * NT + (int)threadIdx.x;
+        if (e < rows) {
+          q[u] = ldg(tq + e);
+          a1[u] = ldg(vj + e);
+          a0[u] = has_vm1 ? ldg(vout + e) : make_double2(0.0, 0.0);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * NT + (int)threadIdx.x;
+        if (e < rows) {
+          const double vx = q[u].x - cd * a1[u].x - cg * a0[u].x;
+          const double vy = q[u].y - cd * a1[u].y - cg * a0[u].y;
+          st_nt(vout + e, vx, vy);
+          plane[e] = Cx<R>{(R)vx, (R)vy};
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // axis 1 forward: n0 lines of n1 points, contiguous in the plane
+  plane_dst_lines(plane, wbuf, tw1, n0, lg1, n1, 1);
+  __syncthreads();
+  // axis 0: n1 lines of n0 points at stride n1; forward transform, the
+  // per-mode factor with the partial of gamma^2, and the inverse, the
+  // scaled modes staying in registers as the inverse's input (the factor of
+  // mode k applied to output k and, by the odd symmetry, to output L - k)
+  double gacc = 0.0;
+  {
+    const int L = 1 << lg0, Q = L >> 2, N = L >> 1;
+    const int G = 64 >> (lg0 - 2);
+    const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
+    const int g = t >> (lg0 - 2), jl = t & (Q - 1);
+    Cx<R> *wb = wbuf + w * kPlaneWaveElts;
+    const int lo = g * L;
+    const R ab = (R)S.abar_f, al = (R)S.alpha_f, be = (R)S.beta_f;
+    const CSL_G R *mu0 = gbl(S.mu_f[0]);
+    const CSL_G R *mu1 = gbl(S.mu_f[1]);
+    const R m2 = gbl(S.mu_f[2])[c];
+    const float cf0 = 1.0f / sqrtf((float)L);
+    // mode (0-based) of output k, and its axis-0 eigenvalue: fixed per lane
+    int md[4];
+    R m0[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = jl + q * Q;
+      md[q] = (k == 0 || k == N) ? -1 : (k < N ? k - 1 : L - 1 - k);
+      m0[q] = md[q] >= 0 ? mu0[md[q]] : (R)0;
+    }
+    for (int l0 = w * G; l0 < n1; l0 += (NT / 64) * G) {
+      const int l = l0 + g;
+      const bool act = l < n1;
+      Cx<R> *line = plane + (act ? l : 0);
+      const R m1 = mu1[act ? l : 0];
+      Cx<R> a[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[q] = plane_ext(line, n1, jl + q * Q, L, act);
+      wave_fft_line(a, wb, lo, jl, lg0, tw0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        Cx<R> v = dst_out(a[q], cf0);
+        if (md[q] < 0) {
+          v = Cx<R>{0, 0};
+        } else {
+          const R lam = (m0[q] + m1) + m2;
+          const R sh = ab * lam + al;
+          const R sc = (R)1 / sqrt(sh * sh + be * be);
+          if (act && q < 2)
+            gacc += (double)sc * ((double)v.x * (double)v.x + (double)v.y * (double)v.y);
+          v.x *= sc;
+          v.y *= sc;
+        }
+        a[q] = v;
+      }
+      wave_fft_line(a, wb, lo, jl, lg0, tw0);
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int k = jl + q * Q;
+        if (act && k >= 1 && k < N) line[(k - 1) * n1] = dst_out(a[q], cf0);
+      }
+    }
+  }
+  __syncthreads();
+  // axis 1 inverse
+  plane_dst_lines(plane, wbuf, tw1, n0, lg1, n1, 1);
+  __syncthreads();
+  CSL_G Cx<R> *T = gbl(reinterpret_cast<Cx<R> *>(S.T)) + off;
+  for (int e = threadIdx.x; e < rows; e += NT) st_nt(T + e, plane[e]);
+  const double sg = wg_sum(gacc, red);
+  if (threadIdx.x == 0) S.part[tile] = sg;
+}
+#endif  // CSL_PLANE
+
 template <int LDSB>
 __device__ __forceinline__ void process_tile(const SysDesc &S, const IOPtr &io, int kind, int iter, int tile,
                              char *smem, double *red) {
@@ -379,6 +632,12 @@ __device__ __forceinline__ void process_tile(const SysDesc &S, const IOPtr &io, 
       if (d3) tile_Y<float, 3, LDSB, G16>(S, kind, iter, tile, smem, red);
       else tile_Y<float, 2, LDSB, G16>(S, kind, iter, tile, smem, red);
     }
+    return;
+  }
+#endif
+#if CSL_PLANE
+  if (kind == K_Y && S.plane) {
+    tile_YP(S, iter, tile, smem, red);
     return;
   }
 #endif
@@ -546,7 +805,8 @@ __device__ __forceinline__ void epilogue(const SysDesc &S, const SolveParams &P,
   if (threadIdx.x != 0) return;
   Ctl *C = S.ctl;
   const double nan = __longlong_as_double(0x7ff8000000000000ll);
-  const int first_strided = (S.d == 3) ? K_Y1 : K_Y;
+  const bool five = (S.d == 3) && !S.plane;   // 3-D with the three strided phases
+  const int first_strided = five ? K_Y1 : K_Y;
   if (kind == K_X) {
     if (iter == 0) {
       const double bn = sqrt(sum);
@@ -601,7 +861,7 @@ __device__ __forceinline__ void epilogue(const SysDesc &S, const SolveParams &P,
       C->s_old = 0.0;
       C->after_z = 0;
       C->pend = 0;
-      publish(C, 0, S.d == 3 ? K_Y1I : K_Z);
+      publish(C, 0, five ? K_Y1I : K_Z);
       return;
     }
     if (g2 < 0.0) {
@@ -658,7 +918,7 @@ __device__ __forceinline__ void epilogue(const SysDesc &S, const SolveParams &P,
     const int zm = C->pend ? ZM_PAIR : (C->after_z != 0 ? ZM_SINGLE : ZM_DEFER);
     C->zmode = zm;
     C->pend = (zm == ZM_DEFER);
-    publish(C, iter, S.d == 3 ? K_Y1I : K_Z);
+    publish(C, iter, five ? K_Y1I : K_Z);
     return;
   }
   if (kind == K_Z) {
@@ -693,7 +953,7 @@ __device__ __forceinline__ void epilogue(const SysDesc &S, const SolveParams &P,
 // (status left unset) instead of running on in the workgroups still busy.
 // ---------------------------------------------------------------------------
 template <int LDSB>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) void solve_kernel(
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(CSL_WAVES_PER_EU))) void solve_kernel(
     const SysDesc *__restrict__ sys, const IOPtr *__restrict__ io, IOPtr io0, int nsys,
     SolveParams P, Glob *G) {
   extern __shared__ __align__(16) char smem[];
@@ -1279,21 +1539,34 @@ hipError_t upload_twiddles(const double2 *tw64, const float2 *tw32) {
 
 hipError_t launch_solve(const SysDesc *dsys, const IOPtr *dio, IOPtr io0, int nsys,
                         const SolveParams &P, Glob *G, int grid, size_t smem, hipStream_t s) {
+#if CSL_PLANE
+  // the plane phase uses the whole LDS (the row phases its first 72 KiB)
+  (void)smem;
+  hipLaunchKernelGGL(solve_kernel<65536>, dim3(grid), dim3(NT), kPlaneLdsBytes, s, dsys, dio, io0,
+                     nsys, P, G);
+#else
   if (smem <= 32768)
     hipLaunchKernelGGL(solve_kernel<32768>, dim3(grid), dim3(NT), 32768 + tw_lds_bytes(32768), s, dsys, dio,
                        io0, nsys, P, G);
   else
     hipLaunchKernelGGL(solve_kernel<65536>, dim3(grid), dim3(NT), 65536 + tw_lds_bytes(65536), s, dsys, dio,
                        io0, nsys, P, G);
+#endif
   return hipGetLastError();
 }
 
 hipError_t solve_occupancy(size_t smem, int *blocks_per_cu) {
+#if CSL_PLANE
+  (void)smem;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, solve_kernel<65536>, NT,
+                                                      kPlaneLdsBytes);
+#else
   if (smem <= 32768)
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, solve_kernel<32768>, NT,
                                                         32768 + tw_lds_bytes(32768));
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, solve_kernel<65536>, NT,
                                                       65536 + tw_lds_bytes(65536));
+#endif
 }
 
 #if !CSL_SOLVE_ONLY

@@ -66,6 +66,7 @@ csl_status ensure_twiddles(int dev) {
   HIPCHK(wg512::upload_twiddles(t64.data(), t32.data()));
   HIPCHK(wg512x::upload_twiddles(t64.data(), t32.data()));
   HIPCHK(wg256h::upload_twiddles(t64.data(), t32.data()));
+  HIPCHK(wg1024p::upload_twiddles(t64.data(), t32.data()));
   g_tw_ready[dev] = true;
   return CSL_OK;
 }
@@ -131,13 +132,15 @@ void sine_matrix(int n, std::vector<double> &W) {
     }
 }
 
-// The persistent solver instance of a workgroup size: 512 threads for
-// systems with the FFT on every axis (csl::wg512 when every system is 2-D,
-// csl::wg512x otherwise) or 256 (csl::wg256h when a system has an axis on
-// the FP16 split-product engine, csl::wg256 otherwise).
+// The persistent solver instance of a workgroup size: 1024 threads for a 3-D
+// problem's own solves with the plane phase (csl::wg1024p), 512 for systems
+// with the FFT on every axis (csl::wg512 when every system is 2-D,
+// csl::wg512x otherwise) or 256 (csl::wg256h when a system has an axis on the
+// FP16 split-product engine, csl::wg256 otherwise).
 hipError_t solve_launch(int wg, bool all2d, bool g16, const SysDesc *dsys, const IOPtr *dio,
                         IOPtr io0, int nsys, const SolveParams &P, Glob *G, int grid, size_t smem,
                         hipStream_t s) {
+  if (wg == 1024) return wg1024p::launch_solve(dsys, dio, io0, nsys, P, G, grid, smem, s);
   if (wg != 512)
     return g16 ? wg256h::launch_solve(dsys, dio, io0, nsys, P, G, grid, smem, s)
                : wg256::launch_solve(dsys, dio, io0, nsys, P, G, grid, smem, s);
@@ -145,6 +148,7 @@ hipError_t solve_launch(int wg, bool all2d, bool g16, const SysDesc *dsys, const
                : wg512x::launch_solve(dsys, dio, io0, nsys, P, G, grid, smem, s);
 }
 hipError_t solve_occupancy_wg(int wg, bool all2d, bool g16, size_t smem, int *blocks_per_cu) {
+  if (wg == 1024) return wg1024p::solve_occupancy(smem, blocks_per_cu);
   if (wg != 512)
     return g16 ? wg256h::solve_occupancy(smem, blocks_per_cu)
                : wg256::solve_occupancy(smem, blocks_per_cu);
@@ -156,13 +160,37 @@ bool has_gemm16(const SysDesc &h) { return h.gemm[0] == 2 || h.gemm[1] == 2 || h
 // The 512-thread solver applies: the FFT on every axis.
 bool fft_everywhere(const SysDesc &h) { return !h.gemm[0] && !h.gemm[1] && !h.gemm[2]; }
 bool fft_everywhere_mask(int m) { return (m & 7) == 0; }
+// The plane phase applies: 3-D, FP32 preconditioner, the FFT on every axis,
+// lines of at most 127 points along the two leading axes and their plane
+// (with the staged lines and twiddles) inside the instance's LDS.
+bool plane_ok(const SysDesc &h) {
+  return h.d == 3 && h.prec == 1 && fft_everywhere(h) && h.n[0] <= 127 && h.n[1] <= 127 &&
+         plane_lds_bytes(h.n[0], h.n[1], h.lg[0], h.lg[1]) <= kPlaneLdsBytes;
+}
+// Rewrite a tiling for the plane phase: block width one (the plane of
+// contiguous-axis index c contiguous in Tq, Tv, T), one K_Y chunk per plane,
+// no separate strided phases.
+void plane_tiling(SysDesc &h) {
+  h.plane = 1;
+  h.lgB = 0;
+  h.nchunk[K_Y] = h.n[2];
+  h.nchunk[K_Y1] = h.nchunk[K_Y1I] = 0;
+  int mx = 0;
+  for (int k = 0; k < K_NKINDS; ++k) {
+    h.ntile[k] = h.nchunk[k];
+    h.cpt[k] = 1;
+    mx = std::max(mx, h.ntile[k]);
+  }
+  h.maxtile = mx;
+}
 // Workgroup size for a request (0 = the larger one where allowed).
 int resolve_wg(int block_threads, bool wg512_ok) {
   if (block_threads == 256) return 256;
   if (block_threads == 512) return 512;
+  if (block_threads == 1024) return 1024;
   return wg512_ok ? 512 : 256;
 }
-bool valid_block_threads(int v) { return v == 0 || v == 256 || v == 512; }
+bool valid_block_threads(int v) { return v == 0 || v == 256 || v == 512 || v == 1024; }
 
 // Per-device record of the allocation-free solve's workspace (the array
 // `scratch` below).
@@ -354,6 +382,7 @@ void set_tile_points(SysDesc &h, int points) {
     if (h.d == 3) cpts[K_Y1] = cpts[K_Y1I] = per(h.lpt_s[1] * h.n[1]);
     cpts[K_PR] = per(h.rpt * nlast);
   }
+  if (h.plane) cpts[K_Y] = 1;   // one plane (all of LDS) per tile
   // ntile <= nchunk, so the partials buffer sized by the chunk counts (maxtile)
   // holds every tile's partial
   for (int k = 0; k < K_NKINDS; ++k) {
@@ -487,8 +516,19 @@ csl_status configure_single(csl_problem p, int tile_points, int lds_bytes, int b
                             hipStream_t s) {
   SysDesc h = p->h0;
   size_t sm = p->smem0;
-  if (p->single_te > 0) choose_tiles(h, p->single_te, lds_bytes, &sm);
-  else if (lds_bytes > 32768 && p->smem0 <= 32768) choose_tiles(h, p->tile_elems, lds_bytes, &sm);
+  const bool plane = block_threads == 1024;
+  if (plane) {
+    if (!plane_ok(h))
+      return fail(CSL_ERR_ARG, "block_threads 1024 (the plane phase) needs a 3-D problem with the "
+                               "FP32 preconditioner, the FFT on every axis and n0, n1 <= 127");
+    // the row phases on a 64 KiB line buffer, then the plane layout
+    choose_tiles(h, p->single_te > 0 ? p->single_te : p->tile_elems, 65536, &sm);
+    plane_tiling(h);
+  } else if (p->single_te > 0) {
+    choose_tiles(h, p->single_te, lds_bytes, &sm);
+  } else if (lds_bytes > 32768 && p->smem0 <= 32768) {
+    choose_tiles(h, p->tile_elems, lds_bytes, &sm);
+  }
   // every tile of every phase owns a partial-sum slot
   if (h.maxtile > p->part_cap) return fail(CSL_ERR_ARG, "chunking exceeds the partial-sum slots");
   const int wg = resolve_wg(block_threads, p->wg512_ok);
@@ -782,6 +822,9 @@ static csl_status create_problem_impl(const csl_grid *grid, const double *a_noda
   // partial-sum slots: the creation-time chunking, and on small grids the
   // smallest chunks problem_tune may choose for the problem's own solves
   int part_cap = std::max(1, h.maxtile);
+  // the plane phase's tiling (3-D): one tile per plane of the contiguous
+  // axis, its row phases on chunks no smaller than these
+  if (h.d == 3) part_cap = std::max(part_cap, h.n[2]);
   if (h.M <= kSmallChunkPoints) {
     SysDesc t = h;
     size_t sm_t = 0;
@@ -1316,7 +1359,7 @@ csl_status problem_set_schedule(csl_problem p, int tile_points, int lds_bytes, i
   if (lds_bytes != 0 && lds_bytes != 32768 && lds_bytes != 65536)
     return fail(CSL_ERR_ARG, "lds_bytes must be 0, 32768 or 65536");
   if (!valid_block_threads(block_threads))
-    return fail(CSL_ERR_ARG, "block_threads must be 0, 256 or 512");
+    return fail(CSL_ERR_ARG, "block_threads must be 0, 256, 512 or 1024");
   if (block_threads == 512 && !p->wg512_ok)
     return fail(CSL_ERR_ARG, "block_threads 512 needs the FFT engine on every axis");
   const int te0 = p->single_te;
@@ -1368,9 +1411,14 @@ csl_status problem_tune(csl_problem p, const double *f, double *z, csl_batch_tun
     const int m = masks[mi];
     const bool w512 = fft_everywhere_mask(m);
     const long long per_wg = std::max<long long>(1, p->h.M / std::max(1, p->cap));
-    for (int wg : {256, 512}) {
+    SysDesc hm = p->h0;
+    for (int ax = 0; ax < 3; ++ax) hm.gemm[ax] = ((m >> ax) & 1) ? 1 : 0;
+    const bool w1024 = plane_ok(hm);
+    for (int wg : {256, 512, 1024}) {
       if (wg == 512 && !w512) continue;
+      if (wg == 1024 && !w1024) continue;
       for (int lds : {32768, 65536}) {
+        if (wg == 1024 && lds != 65536) continue;   // the plane instance's own budget
         std::vector<long long> tps;
         for (long long tp : {0LL, 1LL, per_wg / 2, per_wg * 2, per_wg * 4, per_wg * 8, 4096LL, 8192LL})
           if (tp >= 0 && tp <= (1LL << 30) && std::find(tps.begin(), tps.end(), tp) == tps.end())
@@ -1537,8 +1585,8 @@ csl_status batch_create(const csl_problem *problems, int count, const csl_batch_
   if (o.lds_bytes != 0 && o.lds_bytes != 32768 && o.lds_bytes != 65536)
     return cleanup(CSL_ERR_ARG, "lds_bytes must be 0, 32768 or 65536");
   if (o.tile_points < 0) return cleanup(CSL_ERR_ARG, "tile_points must be >= 0");
-  if (!valid_block_threads(o.block_threads))
-    return cleanup(CSL_ERR_ARG, "block_threads must be 0, 256 or 512");
+  if (!valid_block_threads(o.block_threads) || o.block_threads == 1024)
+    return cleanup(CSL_ERR_ARG, "block_threads must be 0, 256 or 512 for a batch");
   b->wg512_ok = true;
   b->all2d = true;
   for (int i = 0; i < count; ++i) {

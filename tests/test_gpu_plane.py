@@ -1,0 +1,153 @@
+"""GPU parity of the 3-D plane phase (block_threads 1024: one workgroup per
+CU holding a plane of the two leading axes in LDS, so an FP32-preconditioner
+iteration is X, plane, Z instead of five phases) against the CPU oracle and
+against the five-phase solver, through the C ABI.
+
+Tolerances (relative 2-norm): against the FP64 oracle's iterate after the
+GPU's number of steps 1e-6 (the FP32 preconditioner form).  Against the
+five-phase 512-thread solver the same 1e-6 on converged solves, and after k
+steps twice the five-phase solver's own distance from the oracle: the plane
+phase forms the upper half of each odd extension from its own FFT outputs
+instead of mirroring the lower half, so the two FP32 preconditioners agree
+to FP32 rounding, not bitwise.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import csl_oracle as O
+from paper_2408_00488_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def csl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2408_00488_amd as C
+    C.load_library()
+    return C
+
+
+def _crand(shape, seed):
+    g = np.random.default_rng(seed)
+    return g.standard_normal(shape) + 1j * g.standard_normal(shape)
+
+
+def _coef(shape, seed, lo=1.0, hi=3.0):
+    return np.random.default_rng(seed).uniform(lo, hi, shape)
+
+
+def cuda(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def rel(a, b):
+    a = np.asarray(a).ravel()
+    b = np.asarray(b).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+SHAPES = [((15, 15, 15), None), ((7, 15, 31), [0.5, 1.0, 2.0]), ((31, 31, 31), None),
+          ((63, 31, 15), None), ((31, 63, 3), None), ((127, 127, 7), None)]
+
+
+@pytest.mark.parametrize("shape,lengths", SHAPES)
+def test_plane_solve_matches_oracle_and_five_phases(csl, shape, lengths):
+    _say("plane solve", shape, lengths)
+    a = _coef(shape, 61)
+    f = _crand(shape, 62)
+    lam = 10.0 + 100.0j
+    p = csl.Problem(cuda(a), lam.real, lam.imag, pinv_fp32=True, lengths=lengths, dst="fft")
+    p.set_schedule(0, 65536, 1024)
+    assert p.schedule["block_threads"] == 1024
+    z, info = csl.minres_solve(p, cuda(f), timeout_ms=30000)
+    assert info["status"] == 0 and info["relres_true"] <= 1e-8, info
+    zg = z.cpu().numpy()
+    po = O.Problem(a, lam.real, lam.imag, lengths=lengths)
+    zx, _ = po.solve(f, fixed_iters=info["iters"])
+    e = rel(zg, zx)
+    # the five-phase solver on the same problem
+    p.set_schedule(0, 0, 512)
+    z5, i5 = csl.minres_solve(p, cuda(f), timeout_ms=30000)
+    _say("  iters", info["iters"], i5["iters"], "vs oracle", e)
+    assert e <= 1e-6
+    if i5["iters"] == info["iters"]:
+        e5 = rel(zg, z5.cpu().numpy())
+        _say("  vs five phases", e5)
+        assert e5 <= 1e-6
+    else:
+        assert abs(i5["iters"] - info["iters"]) <= 1
+    p.close()
+
+
+def test_plane_iterate_after_k_steps(csl):
+    # every k exercises a different form of the paired w/x updates; the plane
+    # solver against the five-phase one and both against the FP64 oracle
+    # after k steps
+    shape = (15, 31, 15)
+    a = _coef(shape, 63)
+    f = _crand(shape, 64)
+    lam = -40.0 + 25.0j
+    p = csl.Problem(cuda(a), lam.real, lam.imag, pinv_fp32=True, dst="fft")
+    q = csl.Problem(cuda(a), lam.real, lam.imag, pinv_fp32=True, dst="fft")
+    p.set_schedule(0, 65536, 1024)
+    q.set_schedule(0, 0, 512)
+    po = O.Problem(a, lam.real, lam.imag)
+    for k in range(1, 8):
+        z, info = csl.minres_solve(p, cuda(f), maxit=k, tol=1e-30, raise_on_error=False)
+        z5, i5 = csl.minres_solve(q, cuda(f), maxit=k, tol=1e-30, raise_on_error=False)
+        assert info["iters"] == k and info["status_name"] == "ERR_NOT_CONVERGED", info
+        zo, io = po.solve(f, fixed_iters=k)
+        e5, eo, eo5 = rel(z.cpu().numpy(), z5.cpu().numpy()), rel(z.cpu().numpy(), zo), \
+            rel(z5.cpu().numpy(), zo)
+        _say("  k", k, "vs five phases", e5, "vs oracle", eo, "five phases vs oracle", eo5)
+        assert e5 <= max(1e-6, 2.0 * eo5), k
+        assert eo <= max(1e-6, 1.5 * eo5), k
+        assert info["relres_est"] == pytest.approx(i5["relres_est"], rel=1e-5)
+
+
+def test_plane_rules(csl):
+    a3 = cuda(_coef((15, 15, 15), 1))
+    a2 = cuda(_coef((63, 63), 2))
+    for p in (csl.Problem(a3, 1.0, 5.0, pinv_fp32=False, dst="fft"),
+              csl.Problem(a2, 1.0, 5.0, pinv_fp32=True, dst="fft"),
+              csl.Problem(cuda(_coef((255, 15, 15), 3)), 1.0, 5.0, pinv_fp32=True, dst="fft"),
+              csl.Problem(a3, 1.0, 5.0, pinv_fp32=True, dst="gemm")):
+        with pytest.raises(csl.CSLError, match="ERR_ARG"):
+            p.set_schedule(0, 65536, 1024)
+    p = csl.Problem(a3, 1.0, 5.0, pinv_fp32=True, dst="fft")
+    with pytest.raises(csl.CSLError, match="ERR_ARG"):
+        csl.Batch([p], block_threads=1024)
+    # the tuner may pick the plane phase; the tuned problem still solves
+    f = cuda(_crand((15, 15, 15), 4))
+    t = p.tune(f)
+    _say("tuned", t)
+    assert t["block_threads"] in (256, 512, 1024)
+    z, info = csl.minres_solve(p, f)
+    assert info["status"] == 0
+
+
+@pytest.mark.timeout(900)
+def test_c3_plane_full_size(csl):
+    w = WL.workload("c3")
+    s = w.systems[0]
+    p = csl.Problem(cuda(s.a), s.lam.real, s.lam.imag, pinv_fp32=True, dst="fft")
+    p.set_schedule(0, 65536, 1024)
+    z, info = csl.minres_solve(p, cuda(s.f), timeout_ms=60000)
+    _say("c3 plane", info)
+    assert info["status"] == 0 and info["relres_true"] <= 1e-8
+    po = O.Problem(s.a, s.lam.real, s.lam.imag)
+    zx, _ = po.solve(s.f, fixed_iters=info["iters"])
+    e = rel(z.cpu().numpy(), zx)
+    _say("c3 plane vs oracle", e)
+    assert e <= 1e-6
