@@ -226,6 +226,78 @@ __device__ __forceinline__ void fft_lines(Cx<R> *buf, int nl, int lg, const Cx<R
 }
 
 // ---------------------------------------------------------------------------
+// Per-wave FFT of lines of at most 256 points: a line of L = 2^lg points
+// takes Q = L/4 lanes, one radix-4 Stockham butterfly per lane and stage (a
+// radix-2 stage first when lg is odd), so a wave holds 256/L lines and needs
+// no workgroup barrier.  A stage computes exactly what fft_lines computes
+// for the same butterfly.
+// ---------------------------------------------------------------------------
+// Order the wave's own LDS accesses around an exchange between its lanes:
+// LDS operations of one wave complete in issue order, so only the compiler
+// has to be kept from moving them.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Lane j enters with a[q] = x[j + q Q] and leaves with a[q] = X[j + q Q];
+// the line occupies elements lo .. lo + L - 1 of wb, which holds the
+// intermediate stages (written only when wr).  Reads of a stage precede its
+// writes in issue order, so the line may be transformed in place.
+template <typename R>
+__device__ __forceinline__ void wave_fft_line(Cx<R> a[4], Cx<R> *wb, int lo, int j, int lg,
+                                              const Cx<R> *twl, bool wr) {
+  const int L = 1 << lg, Q = L >> 2;
+  int Ns = 1;
+  if (lg & 1) {
+    // radix-2 stage: butterflies j and j + Q, of (x[b], x[b + L/2])
+    wave_lds_sync();
+    if (wr) {
+      wb[lo + 2 * j] = cadd(a[0], a[2]);
+      wb[lo + 2 * j + 1] = csub(a[0], a[2]);
+      wb[lo + 2 * (j + Q)] = cadd(a[1], a[3]);
+      wb[lo + 2 * (j + Q) + 1] = csub(a[1], a[3]);
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) a[q] = wb[lo + j + q * Q];
+    Ns = 2;
+  }
+  for (;; Ns <<= 2) {
+    const int k = j & (Ns - 1);
+    Cx<R> x0 = a[0], x1 = a[1], x2 = a[2], x3 = a[3];
+    if (Ns > 1) {
+      const Cx<R> w1 = twl[k * (L / (4 * Ns))];
+      const Cx<R> w2 = cmul(w1, w1);
+      const Cx<R> w3 = cmul(w2, w1);
+      x1 = cmul(x1, w1);
+      x2 = cmul(x2, w2);
+      x3 = cmul(x3, w3);
+    }
+    const Cx<R> t0 = cadd(x0, x2), t1 = csub(x0, x2);
+    const Cx<R> t2 = cadd(x1, x3), t3 = csub(x1, x3);
+    const Cx<R> mt3 = {t3.y, -t3.x};   // -i t3
+    a[0] = cadd(t0, t2);
+    a[1] = cadd(t1, mt3);
+    a[2] = csub(t0, t2);
+    a[3] = csub(t1, mt3);
+    // the last stage (Ns = Q) leaves output j + q Q in a[q]
+    if (4 * Ns == L) break;
+    const int base = lo + ((j - k) << 2) + k;
+    wave_lds_sync();
+    if (wr) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) wb[base + q * Ns] = a[q];
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) a[q] = wb[lo + j + q * Q];
+  }
+  wave_lds_sync();
+}
+
+// ---------------------------------------------------------------------------
 // A tile of lines of one sine-transform pass.
 // Element r of line l lives at global index base + l*lstride + r*stride.
 // ---------------------------------------------------------------------------

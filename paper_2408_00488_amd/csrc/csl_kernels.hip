@@ -370,72 +370,11 @@ __device__ __forceinline__ void tile_PR(const SysDesc &S, const IOPtr &io, int t
 // The values are those of the three strided phases (K_Y1, K_Y, K_Y1I) with
 // their FP32 intermediate kept in LDS instead of T.
 //
-// Each wave transforms whole lines on its own: a line of the odd extension
-// (L = 2^lg points) takes L/4 lanes, one radix-4 butterfly per lane and
-// Stockham stage (a radix-2 stage first when lg is odd), so a wave holds
-// 256/L lines and exchanges values between stages through its own 2 KiB of
-// LDS with no workgroup barrier.  A stage computes exactly what the
-// workgroup-wide transform computes for the same butterfly.
+// Each wave transforms whole lines on its own (wave_fft_line): a wave holds
+// 256/L lines of the odd extension and exchanges values between stages
+// through its own 2 KiB of LDS with no workgroup barrier.
 // ---------------------------------------------------------------------------
 constexpr int kPlaneWaveElts = 256;   // complex FP32 values per wave buffer
-
-// Order the wave's own LDS accesses around an exchange between its lanes:
-// LDS operations of one wave complete in issue order, so only the compiler
-// has to be kept from moving them.
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// FFT of one line of L = 2^lg points (lg >= 2) by Q = L/4 lanes.  Lane j
-// enters with a[q] = x[j + q Q] and leaves with a[q] = X[j + q Q]; the line
-// occupies elements lo .. lo + L - 1 of the wave buffer wb.
-__device__ __forceinline__ void wave_fft_line(Cx<float> a[4], Cx<float> *wb, int lo, int j, int lg,
-                                              const Cx<float> *twl) {
-  const int L = 1 << lg, Q = L >> 2;
-  int Ns = 1;
-  if (lg & 1) {
-    // radix-2 stage: butterflies j and j + Q, of (x[b], x[b + L/2])
-    wb[lo + 2 * j] = cadd(a[0], a[2]);
-    wb[lo + 2 * j + 1] = csub(a[0], a[2]);
-    wb[lo + 2 * (j + Q)] = cadd(a[1], a[3]);
-    wb[lo + 2 * (j + Q) + 1] = csub(a[1], a[3]);
-    wave_lds_sync();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) a[q] = wb[lo + j + q * Q];
-    Ns = 2;
-  }
-  for (;; Ns <<= 2) {
-    const int k = j & (Ns - 1);
-    Cx<float> x0 = a[0], x1 = a[1], x2 = a[2], x3 = a[3];
-    if (Ns > 1) {
-      const Cx<float> w1 = twl[k * (L / (4 * Ns))];
-      const Cx<float> w2 = cmul(w1, w1);
-      const Cx<float> w3 = cmul(w2, w1);
-      x1 = cmul(x1, w1);
-      x2 = cmul(x2, w2);
-      x3 = cmul(x3, w3);
-    }
-    const Cx<float> t0 = cadd(x0, x2), t1 = csub(x0, x2);
-    const Cx<float> t2 = cadd(x1, x3), t3 = csub(x1, x3);
-    const Cx<float> mt3 = {t3.y, -t3.x};   // -i t3
-    a[0] = cadd(t0, t2);
-    a[1] = cadd(t1, mt3);
-    a[2] = csub(t0, t2);
-    a[3] = csub(t1, mt3);
-    // the last stage (Ns = Q) leaves output j + q Q in a[q]
-    if (4 * Ns == L) break;
-    const int base = lo + ((j - k) << 2) + k;
-    wave_lds_sync();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) wb[base + q * Ns] = a[q];
-    wave_lds_sync();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) a[q] = wb[lo + j + q * Q];
-  }
-  wave_lds_sync();
-}
 
 // Odd extension of a line of n = L/2 - 1 points read from the plane: x[m] =
 // v[m-1] below L/2, -v[L-1-m] above it, zero at 0 and L/2.
@@ -465,7 +404,7 @@ __device__ __forceinline__ void plane_dst_lines(Cx<float> *plane, Cx<float> *wbu
     Cx<float> a[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) a[q] = plane_ext(line, ldp, j + q * Q, L, act);
-    wave_fft_line(a, wb, lo, j, lg, twl);
+    wave_fft_line<float>(a, wb, lo, j, lg, twl, true);
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int k = j + q * Q;
@@ -566,7 +505,7 @@ __device__ __forceinline__ void tile_YP(const SysDesc &S, int iter, int tile, ch
       Cx<R> a[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) a[q] = plane_ext(line, n1, jl + q * Q, L, act);
-      wave_fft_line(a, wb, lo, jl, lg0, tw0);
+      wave_fft_line<float>(a, wb, lo, jl, lg0, tw0, true);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         Cx<R> v = dst_out(a[q], cf0);
@@ -583,7 +522,7 @@ __device__ __forceinline__ void tile_YP(const SysDesc &S, int iter, int tile, ch
         }
         a[q] = v;
       }
-      wave_fft_line(a, wb, lo, jl, lg0, tw0);
+      wave_fft_line<float>(a, wb, lo, jl, lg0, tw0, true);
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         const int k = jl + q * Q;
