@@ -54,6 +54,7 @@ struct alignas(64) Ctl {
   int zmode;                 // what the K_Z phase does (ZM_*)
   int pend;                  // 1: the previous step's update is deferred
   int fin_status, fin_iters; // finish after a ZM_FLUSH phase
+  unsigned int fills;        // plane phase: planes read into LDS so far (atomic)
 };
 
 // K_Z phase modes.  The w/x updates of MINRES run two steps at a time: a
@@ -130,6 +131,11 @@ constexpr int kLanczosCap = 4096;
 // plane (FP32, padded to 128 bytes), 16 staged lines of up to 256 points, the
 // twiddles of both lengths.
 constexpr int kPlaneLdsBytes = 163840 - 512;
+// The plane phase also carries the deferred w/x update of the previous step,
+// on tiles of this many grid points after the plane tiles (the workgroups
+// without a plane run them).
+constexpr int kSidePoints = 16384;
+__host__ __device__ inline int plane_side_tiles(int M) { return (M + kSidePoints - 1) / kSidePoints; }
 __host__ __device__ inline int plane_lds_bytes(int n0, int n1, int lg0, int lg1) {
   const int pb = (n0 * n1 * 8 + 127) & ~127;
   return pb + 16 * 256 * 8 + ((1 << lg0) / 4 + (1 << lg1) / 4) * 8;

@@ -468,6 +468,8 @@ __device__ __forceinline__ void tile_YP(const SysDesc &S, int iter, int tile, ch
     }
   }
   __syncthreads();
+  if (threadIdx.x == 0)
+    __hip_atomic_fetch_add(&S.ctl->fills, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   // axis 1 forward: n0 lines of n1 points, contiguous in the plane
   plane_dst_lines(plane, wbuf, tw1, n0, lg1, n1, 1);
   __syncthreads();
@@ -539,6 +541,67 @@ __device__ __forceinline__ void tile_YP(const SysDesc &S, int iter, int tile, ch
   const double sg = wg_sum(gacc, red);
   if (threadIdx.x == 0) S.part[tile] = sg;
 }
+
+// Update tile s of the plane phase at iteration j: the update of step j - 1,
+// deferred by the K_Z phase before it (which then only formed zhat_j), on
+// grid points [s kSidePoints, (s + 1) kSidePoints):
+//   w_j = (zhat_{j-1} - e3 w_{j-2} - e2 w_{j-1}) / e1,  x_{j-1} = x_{j-2} + ceta w_j
+// with step j - 1's coefficients, still the current ones until this phase's
+// epilogue forms step j's.  The same arithmetic as the single update of
+// K_Z; the workgroups without a plane run these tiles while the planes are
+// transformed.
+__device__ __forceinline__ void tile_side(const SysDesc &S, const IOPtr &io, int iter, int tile) {
+  const Ctl *C = S.ctl;
+  if (threadIdx.x == 0) S.part[tile] = 0.0;   // no share of gamma^2
+  if (iter < 1 || ld_ctl(&C->pend) == 0) return;
+  // start once every plane is in LDS (their fills keep HBM busy; the
+  // transforms that follow leave it idle).  Every plane tile was claimed
+  // before this one and never waits, so the count completes; the wait is
+  // bounded all the same.
+  if (threadIdx.x == 0) {
+    const unsigned int np = (unsigned int)S.n[2];
+    for (int k = 0; k < 512; ++k) {
+      if (__hip_atomic_load(&S.ctl->fills, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= np) break;
+      __builtin_amdgcn_s_sleep(8);
+    }
+  }
+  __syncthreads();
+  const int j = iter;
+  const double e1 = ld_ctl(&C->e1), e2 = ld_ctl(&C->e2), e3 = ld_ctl(&C->e3);
+  const double ceta = ld_ctl(&C->ceta);
+  const double ie1 = 1.0 / e1;
+  const CSL_G double2 *__restrict__ zm = gbl(S.Z[(j + 1) & 1]);   // zhat_{j-1}
+  CSL_G double2 *__restrict__ wa = gbl(S.W[j & 1]);                // w_{j-2} -> w_j
+  const CSL_G double2 *__restrict__ wb = gbl(S.W[(j + 1) & 1]);    // w_{j-1}
+  CSL_G double2 *__restrict__ X = gbl(io.x);
+  const bool use_a = j > 3, use_b = j > 2, use_x = j > 2;
+  const int p0 = (tile - S.n[2]) * kSidePoints;
+  const int p1 = min(S.M, p0 + kSidePoints);
+  constexpr int U = 2;
+  for (int e0 = p0; e0 < p1; e0 += NT * U) {
+    double2 z[U], w0[U], w1[U], x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = e0 + u * NT + (int)threadIdx.x;
+      if (p < p1) {
+        z[u] = ldg(zm + p);
+        w0[u] = use_a ? ldg(wa + p) : make_double2(0.0, 0.0);
+        w1[u] = use_b ? ldg(wb + p) : make_double2(0.0, 0.0);
+        x[u] = use_x ? ldg(X + p) : make_double2(0.0, 0.0);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = e0 + u * NT + (int)threadIdx.x;
+      if (p < p1) {
+        const double wx = (z[u].x - e3 * w0[u].x - e2 * w1[u].x) * ie1;
+        const double wy = (z[u].y - e3 * w0[u].y - e2 * w1[u].y) * ie1;
+        st_nt(wa + p, wx, wy);
+        st_nt(X + p, x[u].x + ceta * wx, x[u].y - ceta * wy);
+      }
+    }
+  }
+}
 #endif  // CSL_PLANE
 
 template <int LDSB>
@@ -576,7 +639,8 @@ __device__ __forceinline__ void process_tile(const SysDesc &S, const IOPtr &io, 
 #endif
 #if CSL_PLANE
   if (kind == K_Y && S.plane) {
-    tile_YP(S, iter, tile, smem, red);
+    if (tile < S.n[2]) tile_YP(S, iter, tile, smem, red);
+    else tile_side(S, io, iter, tile);
     return;
   }
 #endif
@@ -698,6 +762,7 @@ __device__ __forceinline__ void tile_pinv(const SysDesc &S, int pass, const doub
 // fence beyond the one the protocol needs is issued.
 __device__ __forceinline__ void publish(Ctl *C, int iter, int kind) {
   __hip_atomic_store(&C->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&C->fills, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __hip_atomic_exchange(&C->word, (unsigned long long)make_word(iter, kind), __ATOMIC_RELEASE,
                         __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -776,6 +841,9 @@ __device__ __forceinline__ void epilogue(const SysDesc &S, const SolveParams &P,
     return;
   }
   if (last_strided) {
+    // the plane phase has applied the update deferred by the K_Z phase
+    // before it (its update tiles), so no step is pending any more
+    if (S.plane) C->pend = 0;
     const double g2 = sum;
     if (!isfinite(g2)) {
       S.info->relres_est = nan;

@@ -168,12 +168,13 @@ bool plane_ok(const SysDesc &h) {
          plane_lds_bytes(h.n[0], h.n[1], h.lg[0], h.lg[1]) <= kPlaneLdsBytes;
 }
 // Rewrite a tiling for the plane phase: block width one (the plane of
-// contiguous-axis index c contiguous in Tq, Tv, T), one K_Y chunk per plane,
-// no separate strided phases.
+// contiguous-axis index c contiguous in Tq, Tv, T), one K_Y chunk per plane
+// followed by the chunks of the deferred w/x update, no separate strided
+// phases.
 void plane_tiling(SysDesc &h) {
   h.plane = 1;
   h.lgB = 0;
-  h.nchunk[K_Y] = h.n[2];
+  h.nchunk[K_Y] = h.n[2] + plane_side_tiles(h.M);
   h.nchunk[K_Y1] = h.nchunk[K_Y1I] = 0;
   int mx = 0;
   for (int k = 0; k < K_NKINDS; ++k) {
@@ -823,8 +824,8 @@ static csl_status create_problem_impl(const csl_grid *grid, const double *a_noda
   // smallest chunks problem_tune may choose for the problem's own solves
   int part_cap = std::max(1, h.maxtile);
   // the plane phase's tiling (3-D): one tile per plane of the contiguous
-  // axis, its row phases on chunks no smaller than these
-  if (h.d == 3) part_cap = std::max(part_cap, h.n[2]);
+  // axis and the update tiles, its row phases on chunks no smaller than these
+  if (h.d == 3) part_cap = std::max(part_cap, h.n[2] + plane_side_tiles(h.M));
   if (h.M <= kSmallChunkPoints) {
     SysDesc t = h;
     size_t sm_t = 0;
