@@ -176,8 +176,14 @@ csl_status problem_info(csl_problem p, double *abar, double *a_min,
  * workgroup and phase, which lets a single solve fill the device; 1 = one
  * LDS chunk per tile), the LDS line budget (0 or 32768 = default, 65536
  * = 64 KiB) and the workgroup size of the persistent solver, block_threads:
- * 0 = 512 where allowed, else 256; 256; or 512, which is allowed for
- * problems whose sine transforms all run on the FFT (CSL_ERR_ARG otherwise);
+ * 0 = 512 where allowed, else 256; 256; 512, which is allowed for problems
+ * whose sine transforms all run on the FFT (CSL_ERR_ARG otherwise); or 1024,
+ * the plane phase, for 3-D problems with the FP32 preconditioner, the FFT
+ * on every axis and n0, n1 <= 127 (CSL_ERR_ARG otherwise): one workgroup
+ * per CU holds a whole plane of axes 0 and 1 in LDS and applies the
+ * transforms of P^{-1} along both of them (Section 2.3) in one phase, which
+ * also carries the previous step's w/x update on the CUs without a plane;
+ * tile_points and lds_bytes then apply to the contiguous-axis phases;
  * tile_elems, the LDS elements of a chunk (0 = the creation-time tiling;
  * chunks smaller than that are accepted while every tile keeps a partial-sum
  * slot, on grids of at most 65536 points down to 512 elements; CSL_ERR_ARG
@@ -210,8 +216,8 @@ csl_status problem_ritz(csl_problem p, double *theta, int cap, int *count, hipSt
  * problem_ritz uses.  k >= 0; pointers may be NULL when k = 0. */
 csl_status csl_tridiagonal_eigenvalues(const double *d, const double *e, int k, double *theta);
 
-/* Sine-transform engine in use along each axis (CSL_DST_FFT or
- * CSL_DST_GEMM; entries past the grid's dimension are CSL_DST_FFT). */
+/* Sine-transform engine in use along each axis (CSL_DST_FFT, CSL_DST_GEMM or
+ * CSL_DST_GEMM16; entries past the grid's dimension are CSL_DST_FFT). */
 csl_status problem_dst_engines(csl_problem p, int engines[3]);
 
 /* y = A x for the block matrix of Eq. (2); in complex storage
@@ -289,7 +295,8 @@ typedef struct csl_batch_opts {
     int block_threads;      /* workgroup size of the persistent solver: 0 =
                                512 if every problem allows it (the FFT on
                                every axis), else 256; 256; 512 (CSL_ERR_ARG
-                               unless every problem allows it)             */
+                               unless every problem allows it); the plane
+                               phase (1024) is for single solves only      */
 } csl_batch_opts;
 
 /* Schedule chosen by batch_tune or problem_tune, or in use
