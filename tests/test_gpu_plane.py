@@ -142,6 +142,37 @@ def test_plane_rules(csl):
     assert info["status"] == 0
 
 
+def test_plane_adjoint(csl):
+    # the adjoint solve on the plane schedule, whose update tiles write the
+    # adjoint's own output vector: gradients against the oracle's direct
+    # solves (1e-9, both solves at tol 1e-12) and against the five-phase
+    # solver's
+    shape = (15, 31, 15)
+    a = _coef(shape, 71)
+    f = _crand(shape, 72)
+    zt = _crand(shape, 73)
+    lam = complex(-20.0, 45.0)
+    p = csl.Problem(cuda(a), lam.real, lam.imag, pinv_fp32=True, dst="fft")
+    p.set_schedule(0, 65536, 1024)
+    z, _ = csl.minres_solve(p, cuda(f), tol=1e-12)
+    g, info = csl.minres_adjoint(p, z, 2.0 * (z - cuda(zt)), tol=1e-12)
+    _say("plane adjoint", info)
+    po = O.Problem(a, lam.real, lam.imag)
+    zo = po.direct(f)
+    yo, _ = O.adjoint_solve(po, 2.0 * (zo - zt), direct=True)
+    go = O.adjoint_gradients(a, lam.real, lam.imag, zo, yo)
+    assert rel(g["f"].cpu().numpy(), go["f"]) <= 1e-9
+    assert rel(g["a"].cpu().numpy(), go["a"]) <= 1e-9
+    assert g["alpha"].item() == pytest.approx(go["alpha"], rel=1e-9)
+    assert g["beta"].item() == pytest.approx(go["beta"], rel=1e-9)
+    p.set_schedule(0, 0, 512)
+    z5, _ = csl.minres_solve(p, cuda(f), tol=1e-12)
+    g5, _ = csl.minres_adjoint(p, z5, 2.0 * (z5 - cuda(zt)), tol=1e-12)
+    _say("  vs five phases", rel(g["a"].cpu().numpy(), g5["a"].cpu().numpy()))
+    assert rel(g["a"].cpu().numpy(), g5["a"].cpu().numpy()) <= 1e-9
+    p.close()
+
+
 @pytest.mark.timeout(900)
 def test_c3_plane_full_size(csl):
     w = WL.workload("c3")
