@@ -971,6 +971,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(CSL_WAVES_PE
   int cur = blockIdx.x % nsys;
   const long long t0 = wall_clock64();
   int backoff = 0;
+  // Longest back-off, in rounds of s_sleep(8): a single system leaves every
+  // workgroup idle between its phases, and a short cap (about 0.9 us) takes
+  // up the next phase sooner; a batch keeps workgroups busy with other
+  // systems, and polls less (about 14 us).
+  const int bcap = nsys > 1 ? 64 : 4;
   for (;;) {
     if (tid < 64) {
       // Wave 0 looks at up to 64 systems per round trip: each lane loads one
@@ -1020,7 +1025,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(CSL_WAVES_PE
         backoff = 0;
       } else {
         // nothing ready: stop when every system is done or on error / time
-        // limit, else back off exponentially (up to ~14 us) before looking again
+        // limit, else back off exponentially (up to bcap rounds) before looking again
         if (__hip_atomic_load(&G->active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= 0 ||
             __hip_atomic_load(&G->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
           found = -2;
@@ -1029,7 +1034,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(CSL_WAVES_PE
             __hip_atomic_fetch_or(&G->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           found = -2;
         } else {
-          backoff = backoff < 64 ? backoff * 2 + 1 : 64;
+          backoff = backoff < bcap ? backoff * 2 + 1 : bcap;
           for (int i = 0; i < backoff; ++i) __builtin_amdgcn_s_sleep(8);
         }
       }
