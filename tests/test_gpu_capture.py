@@ -1,7 +1,7 @@
 """GPU: the solve path allocates nothing and synchronises nothing when no
 result record is asked for, so a caller can capture it in a graph.
 
-minres_solve (want_info=False) and batch_solve of a batch without its own
+minres_solve (want_info=False; also on the plane schedule) and batch_solve of a batch without its own
 graph (want_info=False, vectors already uploaded) are captured in a torch
 CUDA graph; the graph is replayed several times with eager work and
 synchronisations in between, and every replay is checked bitwise against
@@ -33,9 +33,13 @@ def _coef(shape, seed):
     return torch.from_numpy(np.random.default_rng(seed).uniform(0.5, 2.0, shape)).cuda()
 
 
-@pytest.mark.parametrize("shape,fp32", [((63, 63), False), ((15, 31, 15), True)])
-def test_minres_solve_captured(csl, shape, fp32):
-    p = csl.Problem(_coef(shape, 1), 10.0, 40.0, pinv_fp32=fp32)
+@pytest.mark.parametrize("shape,fp32,threads", [((63, 63), False, 0), ((15, 31, 15), True, 0),
+                                               # the plane phase with its update tiles
+                                               ((15, 31, 15), True, 1024)])
+def test_minres_solve_captured(csl, shape, fp32, threads):
+    p = csl.Problem(_coef(shape, 1), 10.0, 40.0, pinv_fp32=fp32, dst="fft")
+    if threads:
+        p.set_schedule(0, 65536, threads)
     f = _crand(shape, 2)
     z_ref, info = csl.minres_solve(p, f)
     assert info["status"] == 0
