@@ -112,12 +112,14 @@ def test_batch_more_than_64_systems(csl, block_threads):
         p.close()
 
 
-@pytest.mark.parametrize("block_threads", [256, 512])
+# 1024: the plane phase (FP32 preconditioner), whose update tiles wait for the
+# planes' fills with a bounded poll
+@pytest.mark.parametrize("block_threads", [256, 512, 1024])
 def test_time_limit_single(csl, block_threads):
     n = 127
     a = _coef((n, n, n), 7, 1.0, 3.0)
     f = cuda(_crand((n, n, n), 8))
-    p = csl.Problem(cuda(a), 10.0, 100.0, dst="fft")
+    p = csl.Problem(cuda(a), 10.0, 100.0, dst="fft", pinv_fp32=(block_threads == 1024))
     p.set_schedule(0, 0, block_threads)
     _say("time limit, 3-D", n, "block_threads", block_threads)
     z_full, info_full = csl.minres_solve(p, f, timeout_ms=30000)
