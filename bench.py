@@ -77,6 +77,9 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run device-to-device copies of 1 GiB, the reference for the "
                          "HBM byte counters")
+    ap.add_argument("--hbm-rates", action="store_true",
+                    help="time plain device copies, fills and sums of 1 and 4 GiB: the HBM "
+                         "rates that simple streaming kernels reach on this GPU")
     return ap.parse_args()
 
 
@@ -91,6 +94,41 @@ def copy_calibration():
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30, "copies": 3}))
+
+
+def hbm_rates():
+    """HBM rates of plain streaming work (torch's own kernels, FP64 vectors of
+    1 and 4 GiB, 20 timed calls each after 3 untimed): a copy (read + write), a
+    fill (write only) and a sum (read only).  The scale against which the
+    solver's measured traffic rate is read: 8 TB/s is the published peak, not
+    what a streaming kernel reaches."""
+    import torch
+    out = {}
+    for gib in (1, 4):
+        n = (gib << 30) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        cases = (("copy", lambda: b.copy_(a), 2 * n * 8), ("fill", lambda: b.fill_(1.5), n * 8),
+                 ("sum", lambda: a.sum(), n * 8))
+        for name, fn, nbytes in cases:
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            reps = 20
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            tbs = nbytes / ms / 1e9
+            out[f"{name}_{gib}GiB"] = {"ms": round(ms, 4), "TB/s": round(tbs, 3),
+                                       "frac_of_8TBs": round(tbs * 1e3 / PEAK_HBM_GBS, 3)}
+        del a, b
+        torch.cuda.empty_cache()
+    print(json.dumps(out))
 
 
 KERNEL_SOURCES = ["paper_2408_00488_amd/csrc/csl_kernels.hip",
@@ -429,6 +467,9 @@ def main():
         sys.exit(1)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.hbm_rates:
+        hbm_rates()
         return
     import paper_2408_00488_amd as C
     from paper_2408_00488_amd import workloads as WL
