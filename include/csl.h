@@ -180,10 +180,10 @@ csl_status problem_info(csl_problem p, double *abar, double *a_min,
  * whose sine transforms all run on the FFT (CSL_ERR_ARG otherwise); or 1024,
  * the plane phase, for 3-D problems with the FP32 preconditioner, the FFT
  * on every axis and n0, n1 <= 127 (CSL_ERR_ARG otherwise): one workgroup
- * per CU holds a whole plane of axes 0 and 1 in LDS and applies the
- * transforms of P^{-1} along both of them (Section 2.3) in one phase, which
- * also carries the previous step's w/x update on the CUs without a plane;
- * tile_points and lds_bytes then apply to the contiguous-axis phases;
+ * per CU holds the real or the imaginary part of a plane of axes 0 and 1
+ * in LDS and applies the transforms of P^{-1} along both of them (Section
+ * 2.3) in one phase; tile_points and lds_bytes then apply to the
+ * contiguous-axis phases;
  * tile_elems, the LDS elements of a chunk (0 = the creation-time tiling;
  * chunks smaller than that are accepted while every tile keeps a partial-sum
  * slot, on grids of at most 65536 points down to 512 elements; CSL_ERR_ARG

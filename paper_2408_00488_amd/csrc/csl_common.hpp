@@ -54,7 +54,6 @@ struct alignas(64) Ctl {
   int zmode;                 // what the K_Z phase does (ZM_*)
   int pend;                  // 1: the previous step's update is deferred
   int fin_status, fin_iters; // finish after a ZM_FLUSH phase
-  unsigned int fills;        // plane phase: planes read into LDS so far (atomic)
 };
 
 // K_Z phase modes.  The w/x updates of MINRES run two steps at a time: a
@@ -91,8 +90,10 @@ struct SysDesc {
                   // tile's lines are one contiguous block
   int rpt;        // rows per tile of the residual pass
   int plane;      // 3-D: the transforms along axes 1 and 0 in one phase (K_Y), on
-                  // one plane of those axes at a time held in LDS (lgB = 0: the
-                  // plane of contiguous-axis index c is contiguous in Tq, Tv, T)
+                  // the real or the imaginary part of one plane of those axes at
+                  // a time held in LDS (lgB = 0; Tq, Tv and T hold all real
+                  // parts, then all imaginary parts, each with the plane of
+                  // contiguous-axis index c contiguous)
   int nchunk[K_NKINDS];  // LDS-sized chunks of each phase kind
   int cpt[K_NKINDS];     // chunks per tile (one scheduling unit)
   int ntile[K_NKINDS];   // ceil(nchunk / cpt)
@@ -127,17 +128,12 @@ struct SysDesc {
 
 constexpr int kLanczosCap = 4096;
 // Dynamic LDS of the plane-phase solver instance (the whole 160 KiB of a CU
-// less a margin for its static variables), and what a plane needs of it: the
-// plane (FP32, padded to 128 bytes), 16 staged lines of up to 256 points, the
-// twiddles of both lengths.
+// less a margin for its static variables), and what a plane tile needs of it:
+// one part of the plane (FP32, padded to 128 bytes), 16 staged lines of up to
+// 256 complex points, the twiddles of both lengths.
 constexpr int kPlaneLdsBytes = 163840 - 512;
-// The plane phase also carries the deferred w/x update of the previous step,
-// on tiles of this many grid points after the plane tiles (the workgroups
-// without a plane run them).
-constexpr int kSidePoints = 16384;
-__host__ __device__ inline int plane_side_tiles(int M) { return (M + kSidePoints - 1) / kSidePoints; }
 __host__ __device__ inline int plane_lds_bytes(int n0, int n1, int lg0, int lg1) {
-  const int pb = (n0 * n1 * 8 + 127) & ~127;
+  const int pb = (n0 * n1 * 4 + 127) & ~127;
   return pb + 16 * 256 * 8 + ((1 << lg0) / 4 + (1 << lg1) / 4) * 8;
 }
 // The FP16 split-product engine stores the sine matrix scaled by 2^8, so that

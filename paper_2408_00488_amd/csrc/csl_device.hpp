@@ -94,6 +94,12 @@ __device__ __forceinline__ void st_nt(CSL_G double2 *p, double x, double y) {
   const nt_d2 v = {x, y};
   __builtin_nontemporal_store(v, (CSL_G nt_d2 *)p);
 }
+__device__ __forceinline__ void st_nt(CSL_G double *p, double v) {
+  __builtin_nontemporal_store(v, p);
+}
+__device__ __forceinline__ void st_nt(CSL_G float *p, float v) {
+  __builtin_nontemporal_store(v, p);
+}
 __device__ __forceinline__ void st_nt(CSL_G Cx<double> *p, Cx<double> c) {
   const nt_d2 v = {c.x, c.y};
   __builtin_nontemporal_store(v, (CSL_G nt_d2 *)p);

@@ -94,6 +94,18 @@ __device__ __forceinline__ void tile_X(const SysDesc &S, const IOPtr &io, int it
       out = gbl(reinterpret_cast<Cx<double> *>(S.Tq));
     }
     const Cx<double> *o = E::transform(buf, t, twl, Wm);
+#if CSL_PLANE
+    if (S.plane) {
+      // plane layout: all real parts, then all imaginary parts
+      CSL_G double *od = reinterpret_cast<CSL_G double *>(out);
+      const int M = S.M;
+      E::store_blk(o, t, [&](int, int, int q, Cx<double> v) {
+        st_nt(od + q, v.x);
+        st_nt(od + M + q, v.y);
+      });
+      continue;
+    }
+#endif
     E::store_blk(o, t, [&](int, int, int q, Cx<double> v) { st_nt(out + q, v); });
   }
   const double s = wg_sum(acc, red);
@@ -249,6 +261,14 @@ __device__ __forceinline__ void tile_Z(const SysDesc &S, const IOPtr &io, int it
   CSL_G double2 *__restrict__ znew = gbl(S.Z[(j + 1) & 1]);
   for (int chunk = tile * S.cpt[K_Z]; chunk < c1; ++chunk) {
   const LineTile t = line_tile(S, D - 1, S.lpt_z, chunk);
+#if CSL_PLANE
+  if (S.plane) {
+    // plane layout: all real parts, then all imaginary parts
+    const CSL_G R *Tr = reinterpret_cast<const CSL_G R *>(T);
+    const int M = S.M;
+    E::template fill_blk<CSL_U(8)>(buf, t, [&](int, int, int q) { return Cx<R>{Tr[q], Tr[M + q]}; });
+  } else
+#endif
   E::template fill_blk<CSL_U(8)>(buf, t, [&](int, int, int q) { return ldg(T + q); });
   const Cx<R> *o = E::transform(buf, t, twl, Wm);
   if (mode == ZM_DEFER) {
@@ -357,70 +377,86 @@ __device__ __forceinline__ void tile_PR(const SysDesc &S, const IOPtr &io, int t
 
 #if CSL_PLANE
 // ---------------------------------------------------------------------------
-// Plane phase (3-D, FP32 preconditioner, FFT on axes 0 and 1): tile c is the
-// plane of contiguous-axis index c, contiguous in Tq, Tv and T (block width
-// one).  In one pass over it:
+// Plane phase (3-D, FP32 preconditioner, FFT on axes 0 and 1): tile 2c +
+// comp is the real (comp 0) or the imaginary (comp 1) part of the plane of
+// contiguous-axis index c, a real FP32 plane held in LDS.  Tq, Tv and T hold
+// all real parts, then all imaginary parts, each with plane c contiguous
+// (block width one).  In one pass over it:
 //   Tv_{j+1} = Tq - (delta_j/gamma_j) Tv_j - (gamma_j/gamma_{j-1}) Tv_{j-1}
-//     (FP64, stored; Tv_1 at iteration 0), rounded to FP32 into the plane
-//     held in LDS;
+//     (FP64, stored; Tv_1 at iteration 0), rounded to FP32 into the plane;
 //   the forward transforms of the axis-1 lines, then of the axis-0 lines
 //     with the per-mode factor and the partial of gamma_{j+1}^2, their
 //     inverses, then the inverses of the axis-1 lines;
 //   T' written once.
-// The values are those of the three strided phases (K_Y1, K_Y, K_Y1I) with
-// their FP32 intermediate kept in LDS instead of T.
+// The sine transforms and the per-mode factors are real, so the two parts
+// of a plane are transformed independently, and every CU has a plane tile
+// (2 n2 of them).  Inside a tile two real lines make one complex line (the
+// first its real part, the second its imaginary part); the transformed
+// complex line holds their two results the same way.  The values are those
+// of the three strided phases (K_Y1, K_Y, K_Y1I) with their FP32
+// intermediate kept in LDS instead of T.
 //
 // Each wave transforms whole lines on its own (wave_fft_line): a wave holds
-// 256/L lines of the odd extension and exchanges values between stages
-// through its own 2 KiB of LDS with no workgroup barrier.
+// 256/L complex lines of the odd extension and exchanges values between
+// stages through its own 2 KiB of LDS with no workgroup barrier.
 // ---------------------------------------------------------------------------
 constexpr int kPlaneWaveElts = 256;   // complex FP32 values per wave buffer
 
-// Odd extension of a line of n = L/2 - 1 points read from the plane: x[m] =
-// v[m-1] below L/2, -v[L-1-m] above it, zero at 0 and L/2.
-__device__ __forceinline__ Cx<float> plane_ext(const Cx<float> *line, int ldp, int m, int L, bool act) {
+// Odd extension of the complex line made of real lines la and lb (lb absent:
+// zero imaginary part), n = L/2 - 1 points at stride ldp.
+__device__ __forceinline__ Cx<float> pair_ext(const float *la, const float *lb, bool hasb, int ldp,
+                                              int m, int L, bool act) {
   const int N = L >> 1;
   if (!act || m == 0 || m == N) return Cx<float>{0.f, 0.f};
-  if (m < N) return line[(m - 1) * ldp];
-  const Cx<float> v = line[(L - 1 - m) * ldp];
-  return Cx<float>{-v.x, -v.y};
+  const int r = m < N ? m - 1 : L - 1 - m;
+  const float re = la[r * ldp];
+  const float im = hasb ? lb[r * ldp] : 0.f;
+  return m < N ? Cx<float>{re, im} : Cx<float>{-re, -im};
 }
 
-// Sine transform, in place, of the nlines lines of the plane (line l at
-// plane[l ldl + r ldp], n = 2^(lg-1) - 1 points).
-__device__ __forceinline__ void plane_dst_lines(Cx<float> *plane, Cx<float> *wbuf, const Cx<float> *twl,
+// Sine transform, in place, of the nlines real lines of a real plane (line l
+// at pl[l ldl + r ldp]), lines 2p and 2p + 1 as one complex line.
+__device__ __forceinline__ void plane_dst_pairs(float *pl, Cx<float> *wbuf, const Cx<float> *twl,
                                                 int nlines, int lg, int ldl, int ldp) {
   const int L = 1 << lg, Q = L >> 2, N = L >> 1;
-  const int G = 64 >> (lg - 2);   // lines per wave
+  const int G = 64 >> (lg - 2);   // complex lines per wave
   const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
   const int g = t >> (lg - 2), j = t & (Q - 1);
   Cx<float> *wb = wbuf + w * kPlaneWaveElts;
   const int lo = g * L;
   const float cf = 1.0f / sqrtf((float)L);
-  for (int l0 = w * G; l0 < nlines; l0 += (NT / 64) * G) {
-    const int l = l0 + g;
-    const bool act = l < nlines;
-    Cx<float> *line = plane + (size_t)(act ? l : 0) * ldl;
+  const int npairs = (nlines + 1) >> 1;
+  for (int p0 = w * G; p0 < npairs; p0 += (NT / 64) * G) {
+    const int p = p0 + g;
+    const bool act = p < npairs;
+    const bool hasb = act && 2 * p + 1 < nlines;
+    float *la = pl + (size_t)(act ? 2 * p : 0) * ldl;
+    float *lb = la + ldl;
     Cx<float> a[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) a[q] = plane_ext(line, ldp, j + q * Q, L, act);
+    for (int q = 0; q < 4; ++q) a[q] = pair_ext(la, lb, hasb, ldp, j + q * Q, L, act);
     wave_fft_line<float>(a, wb, lo, j, lg, twl, true);
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int k = j + q * Q;
-      if (act && k >= 1 && k < N) line[(k - 1) * ldp] = dst_out(a[q], cf);
+      if (act && k >= 1 && k < N) {
+        const Cx<float> v = dst_out(a[q], cf);
+        la[(k - 1) * ldp] = v.x;
+        if (hasb) lb[(k - 1) * ldp] = v.y;
+      }
     }
   }
 }
 
+// The plane tile: one part of one plane.
 __device__ __forceinline__ void tile_YP(const SysDesc &S, int iter, int tile, char *smem,
                                         double *red) {
   typedef float R;
   const int n0 = S.n[0], n1 = S.n[1];
-  const int rows = S.rows;   // n0 n1: the plane
-  const int c = tile;
-  Cx<R> *plane = reinterpret_cast<Cx<R> *>(smem);
-  const size_t pb = ((size_t)rows * sizeof(Cx<R>) + 127) & ~(size_t)127;
+  const int rows = S.rows;
+  const int c = tile >> 1, comp = tile & 1;
+  float *pl = reinterpret_cast<float *>(smem);
+  const size_t pb = ((size_t)rows * sizeof(float) + 127) & ~(size_t)127;
   Cx<R> *wbuf = reinterpret_cast<Cx<R> *>(smem + pb);
   const int lg0 = S.lg[0], lg1 = S.lg[1];
   Cx<R> *tw0 = wbuf + (NT / 64) * kPlaneWaveElts;
@@ -429,54 +465,53 @@ __device__ __forceinline__ void tile_YP(const SysDesc &S, int iter, int tile, ch
   if (threadIdx.x == 0) s_twkey = -1;
   load_twiddles<R>(tw0, lg0);
   load_twiddles<R>(tw1, lg1);
-  const size_t off = (size_t)c * rows;   // element (row, c) at c rows + row
+  const size_t off = (size_t)comp * S.M + (size_t)c * rows;
   const int j = iter;
   if (j == 0) {
-    const CSL_G double2 *__restrict__ v1 = gbl(S.Tv[1]) + off;
-    for (int e = threadIdx.x; e < rows; e += NT) plane[e] = to_cx<R>(ldg(v1 + e));
+    const CSL_G double *__restrict__ v1 = reinterpret_cast<const CSL_G double *>(gbl(S.Tv[1])) + off;
+    for (int e = threadIdx.x; e < rows; e += NT) pl[e] = (float)v1[e];
   } else {
     const Ctl *C = S.ctl;
     const double g = ld_ctl(&C->gamma), go = ld_ctl(&C->gamma_old);
     const double dl = ld_ctl(&C->delta);
     const double cd = dl / g, cg = g / go;
-    const CSL_G double2 *__restrict__ tq = gbl(S.Tq) + off;
-    const CSL_G double2 *__restrict__ vj = gbl(S.Tv[j & 1]) + off;
-    CSL_G double2 *__restrict__ vout = gbl(S.Tv[(j + 1) & 1]) + off;   // holds Tv_{j-1}
+    const CSL_G double *__restrict__ tq = reinterpret_cast<const CSL_G double *>(gbl(S.Tq)) + off;
+    const CSL_G double *__restrict__ vj = reinterpret_cast<const CSL_G double *>(gbl(S.Tv[j & 1])) + off;
+    // holds Tv_{j-1}
+    CSL_G double *__restrict__ vout = reinterpret_cast<CSL_G double *>(gbl(S.Tv[(j + 1) & 1])) + off;
     const bool has_vm1 = j >= 2;
-    constexpr int U = 4;
+    constexpr int U = 8;
     for (int e0 = 0; e0 < rows; e0 += NT * U) {
-      double2 q[U], a1[U], a0[U];
+      double q[U], a1[U], a0[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int e = e0 + u * NT + (int)threadIdx.x;
         if (e < rows) {
-          q[u] = ldg(tq + e);
-          a1[u] = ldg(vj + e);
-          a0[u] = has_vm1 ? ldg(vout + e) : make_double2(0.0, 0.0);
+          q[u] = tq[e];
+          a1[u] = vj[e];
+          a0[u] = has_vm1 ? vout[e] : 0.0;
         }
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int e = e0 + u * NT + (int)threadIdx.x;
         if (e < rows) {
-          const double vx = q[u].x - cd * a1[u].x - cg * a0[u].x;
-          const double vy = q[u].y - cd * a1[u].y - cg * a0[u].y;
-          st_nt(vout + e, vx, vy);
-          plane[e] = Cx<R>{(R)vx, (R)vy};
+          const double v = q[u] - cd * a1[u] - cg * a0[u];
+          st_nt(vout + e, v);
+          pl[e] = (R)v;
         }
       }
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0)
-    __hip_atomic_fetch_add(&S.ctl->fills, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   // axis 1 forward: n0 lines of n1 points, contiguous in the plane
-  plane_dst_lines(plane, wbuf, tw1, n0, lg1, n1, 1);
+  plane_dst_pairs(pl, wbuf, tw1, n0, lg1, n1, 1);
   __syncthreads();
-  // axis 0: n1 lines of n0 points at stride n1; forward transform, the
-  // per-mode factor with the partial of gamma^2, and the inverse, the
-  // scaled modes staying in registers as the inverse's input (the factor of
-  // mode k applied to output k and, by the odd symmetry, to output L - k)
+  // axis 0: n1 lines of n0 points at stride n1, neighbouring columns in
+  // pairs; forward transform, the per-mode factor of each column's own mode
+  // with the partial of gamma^2, and the inverse, the scaled modes staying
+  // in registers as the inverse's input (the factor of mode k applied to
+  // output k and, by the odd symmetry, to output L - k)
   double gacc = 0.0;
   {
     const int L = 1 << lg0, Q = L >> 2, N = L >> 1;
@@ -490,7 +525,6 @@ __device__ __forceinline__ void tile_YP(const SysDesc &S, int iter, int tile, ch
     const CSL_G R *mu1 = gbl(S.mu_f[1]);
     const R m2 = gbl(S.mu_f[2])[c];
     const float cf0 = 1.0f / sqrtf((float)L);
-    // mode (0-based) of output k, and its axis-0 eigenvalue: fixed per lane
     int md[4];
     R m0[4];
 #pragma unroll
@@ -499,14 +533,18 @@ __device__ __forceinline__ void tile_YP(const SysDesc &S, int iter, int tile, ch
       md[q] = (k == 0 || k == N) ? -1 : (k < N ? k - 1 : L - 1 - k);
       m0[q] = md[q] >= 0 ? mu0[md[q]] : (R)0;
     }
-    for (int l0 = w * G; l0 < n1; l0 += (NT / 64) * G) {
-      const int l = l0 + g;
-      const bool act = l < n1;
-      Cx<R> *line = plane + (act ? l : 0);
-      const R m1 = mu1[act ? l : 0];
+    const int np = (n1 + 1) >> 1;
+    for (int p0 = w * G; p0 < np; p0 += (NT / 64) * G) {
+      const int p = p0 + g;
+      const bool act = p < np;
+      const bool hasb = act && 2 * p + 1 < n1;
+      float *la = pl + (act ? 2 * p : 0);
+      float *lb = la + 1;
+      const R m1a = mu1[act ? 2 * p : 0];
+      const R m1b = mu1[hasb ? 2 * p + 1 : 0];
       Cx<R> a[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) a[q] = plane_ext(line, n1, jl + q * Q, L, act);
+      for (int q = 0; q < 4; ++q) a[q] = pair_ext(la, lb, hasb, n1, jl + q * Q, L, act);
       wave_fft_line<float>(a, wb, lo, jl, lg0, tw0, true);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -514,13 +552,16 @@ __device__ __forceinline__ void tile_YP(const SysDesc &S, int iter, int tile, ch
         if (md[q] < 0) {
           v = Cx<R>{0, 0};
         } else {
-          const R lam = (m0[q] + m1) + m2;
-          const R sh = ab * lam + al;
-          const R sc = (R)1 / sqrt(sh * sh + be * be);
-          if (act && q < 2)
-            gacc += (double)sc * ((double)v.x * (double)v.x + (double)v.y * (double)v.y);
-          v.x *= sc;
-          v.y *= sc;
+          const R sha = ab * ((m0[q] + m1a) + m2) + al;
+          const R shb = ab * ((m0[q] + m1b) + m2) + al;
+          const R sa = (R)1 / sqrt(sha * sha + be * be);
+          const R sb = (R)1 / sqrt(shb * shb + be * be);
+          if (act && q < 2) {
+            gacc += (double)sa * ((double)v.x * (double)v.x);
+            if (hasb) gacc += (double)sb * ((double)v.y * (double)v.y);
+          }
+          v.x *= sa;
+          v.y *= sb;
         }
         a[q] = v;
       }
@@ -528,79 +569,22 @@ __device__ __forceinline__ void tile_YP(const SysDesc &S, int iter, int tile, ch
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         const int k = jl + q * Q;
-        if (act && k >= 1 && k < N) line[(k - 1) * n1] = dst_out(a[q], cf0);
+        if (act && k >= 1 && k < N) {
+          const Cx<R> v = dst_out(a[q], cf0);
+          la[(k - 1) * n1] = v.x;
+          if (hasb) lb[(k - 1) * n1] = v.y;
+        }
       }
     }
   }
   __syncthreads();
   // axis 1 inverse
-  plane_dst_lines(plane, wbuf, tw1, n0, lg1, n1, 1);
+  plane_dst_pairs(pl, wbuf, tw1, n0, lg1, n1, 1);
   __syncthreads();
-  CSL_G Cx<R> *T = gbl(reinterpret_cast<Cx<R> *>(S.T)) + off;
-  for (int e = threadIdx.x; e < rows; e += NT) st_nt(T + e, plane[e]);
+  CSL_G float *Tr = reinterpret_cast<CSL_G float *>(gbl(S.T)) + off;
+  for (int e = threadIdx.x; e < rows; e += NT) st_nt(Tr + e, pl[e]);
   const double sg = wg_sum(gacc, red);
   if (threadIdx.x == 0) S.part[tile] = sg;
-}
-
-// Update tile s of the plane phase at iteration j: the update of step j - 1,
-// deferred by the K_Z phase before it (which then only formed zhat_j), on
-// grid points [s kSidePoints, (s + 1) kSidePoints):
-//   w_j = (zhat_{j-1} - e3 w_{j-2} - e2 w_{j-1}) / e1,  x_{j-1} = x_{j-2} + ceta w_j
-// with step j - 1's coefficients, still the current ones until this phase's
-// epilogue forms step j's.  The same arithmetic as the single update of
-// K_Z; the workgroups without a plane run these tiles while the planes are
-// transformed.
-__device__ __forceinline__ void tile_side(const SysDesc &S, const IOPtr &io, int iter, int tile) {
-  const Ctl *C = S.ctl;
-  if (threadIdx.x == 0) S.part[tile] = 0.0;   // no share of gamma^2
-  if (iter < 1 || ld_ctl(&C->pend) == 0) return;
-  // start once every plane is in LDS (their fills keep HBM busy; the
-  // transforms that follow leave it idle).  Every plane tile was claimed
-  // before this one and never waits, so the count completes; the wait is
-  // bounded all the same.
-  if (threadIdx.x == 0) {
-    const unsigned int np = (unsigned int)S.n[2];
-    for (int k = 0; k < 512; ++k) {
-      if (__hip_atomic_load(&S.ctl->fills, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= np) break;
-      __builtin_amdgcn_s_sleep(8);
-    }
-  }
-  __syncthreads();
-  const int j = iter;
-  const double e1 = ld_ctl(&C->e1), e2 = ld_ctl(&C->e2), e3 = ld_ctl(&C->e3);
-  const double ceta = ld_ctl(&C->ceta);
-  const double ie1 = 1.0 / e1;
-  const CSL_G double2 *__restrict__ zm = gbl(S.Z[(j + 1) & 1]);   // zhat_{j-1}
-  CSL_G double2 *__restrict__ wa = gbl(S.W[j & 1]);                // w_{j-2} -> w_j
-  const CSL_G double2 *__restrict__ wb = gbl(S.W[(j + 1) & 1]);    // w_{j-1}
-  CSL_G double2 *__restrict__ X = gbl(io.x);
-  const bool use_a = j > 3, use_b = j > 2, use_x = j > 2;
-  const int p0 = (tile - S.n[2]) * kSidePoints;
-  const int p1 = min(S.M, p0 + kSidePoints);
-  constexpr int U = 2;
-  for (int e0 = p0; e0 < p1; e0 += NT * U) {
-    double2 z[U], w0[U], w1[U], x[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int p = e0 + u * NT + (int)threadIdx.x;
-      if (p < p1) {
-        z[u] = ldg(zm + p);
-        w0[u] = use_a ? ldg(wa + p) : make_double2(0.0, 0.0);
-        w1[u] = use_b ? ldg(wb + p) : make_double2(0.0, 0.0);
-        x[u] = use_x ? ldg(X + p) : make_double2(0.0, 0.0);
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int p = e0 + u * NT + (int)threadIdx.x;
-      if (p < p1) {
-        const double wx = (z[u].x - e3 * w0[u].x - e2 * w1[u].x) * ie1;
-        const double wy = (z[u].y - e3 * w0[u].y - e2 * w1[u].y) * ie1;
-        st_nt(wa + p, wx, wy);
-        st_nt(X + p, x[u].x + ceta * wx, x[u].y - ceta * wy);
-      }
-    }
-  }
 }
 #endif  // CSL_PLANE
 
@@ -639,8 +623,7 @@ __device__ __forceinline__ void process_tile(const SysDesc &S, const IOPtr &io, 
 #endif
 #if CSL_PLANE
   if (kind == K_Y && S.plane) {
-    if (tile < S.n[2]) tile_YP(S, iter, tile, smem, red);
-    else tile_side(S, io, iter, tile);
+    tile_YP(S, iter, tile, smem, red);
     return;
   }
 #endif
@@ -762,7 +745,6 @@ __device__ __forceinline__ void tile_pinv(const SysDesc &S, int pass, const doub
 // fence beyond the one the protocol needs is issued.
 __device__ __forceinline__ void publish(Ctl *C, int iter, int kind) {
   __hip_atomic_store(&C->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(&C->fills, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __hip_atomic_exchange(&C->word, (unsigned long long)make_word(iter, kind), __ATOMIC_RELEASE,
                         __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -841,9 +823,6 @@ __device__ __forceinline__ void epilogue(const SysDesc &S, const SolveParams &P,
     return;
   }
   if (last_strided) {
-    // the plane phase has applied the update deferred by the K_Z phase
-    // before it (its update tiles), so no step is pending any more
-    if (S.plane) C->pend = 0;
     const double g2 = sum;
     if (!isfinite(g2)) {
       S.info->relres_est = nan;

@@ -167,14 +167,14 @@ bool plane_ok(const SysDesc &h) {
   return h.d == 3 && h.prec == 1 && fft_everywhere(h) && h.n[0] <= 127 && h.n[1] <= 127 &&
          plane_lds_bytes(h.n[0], h.n[1], h.lg[0], h.lg[1]) <= kPlaneLdsBytes;
 }
-// Rewrite a tiling for the plane phase: block width one (the plane of
-// contiguous-axis index c contiguous in Tq, Tv, T), one K_Y chunk per plane
-// followed by the chunks of the deferred w/x update, no separate strided
-// phases.
+// Rewrite a tiling for the plane phase: block width one (Tq, Tv and T hold
+// all real parts, then all imaginary parts, each with the plane of
+// contiguous-axis index c contiguous), one K_Y chunk per part of each plane,
+// no separate strided phases.
 void plane_tiling(SysDesc &h) {
   h.plane = 1;
   h.lgB = 0;
-  h.nchunk[K_Y] = h.n[2] + plane_side_tiles(h.M);
+  h.nchunk[K_Y] = 2 * h.n[2];
   h.nchunk[K_Y1] = h.nchunk[K_Y1I] = 0;
   int mx = 0;
   for (int k = 0; k < K_NKINDS; ++k) {
@@ -383,7 +383,7 @@ void set_tile_points(SysDesc &h, int points) {
     if (h.d == 3) cpts[K_Y1] = cpts[K_Y1I] = per(h.lpt_s[1] * h.n[1]);
     cpts[K_PR] = per(h.rpt * nlast);
   }
-  if (h.plane) cpts[K_Y] = 1;   // one plane (all of LDS) per tile
+  if (h.plane) cpts[K_Y] = 1;   // one part of one plane (held in LDS) per tile
   // ntile <= nchunk, so the partials buffer sized by the chunk counts (maxtile)
   // holds every tile's partial
   for (int k = 0; k < K_NKINDS; ++k) {
@@ -823,9 +823,10 @@ static csl_status create_problem_impl(const csl_grid *grid, const double *a_noda
   // partial-sum slots: the creation-time chunking, and on small grids the
   // smallest chunks problem_tune may choose for the problem's own solves
   int part_cap = std::max(1, h.maxtile);
-  // the plane phase's tiling (3-D): one tile per plane of the contiguous
-  // axis and the update tiles, its row phases on chunks no smaller than these
-  if (h.d == 3) part_cap = std::max(part_cap, h.n[2] + plane_side_tiles(h.M));
+  // the plane phase's tiling (3-D): one tile per part (real, imaginary) of
+  // each plane of the contiguous axis, its row phases on chunks no smaller
+  // than these
+  if (h.d == 3) part_cap = std::max(part_cap, 2 * h.n[2]);
   if (h.M <= kSmallChunkPoints) {
     SysDesc t = h;
     size_t sm_t = 0;

@@ -34,7 +34,7 @@ def _coef(shape, seed):
 
 
 @pytest.mark.parametrize("shape,fp32,threads", [((63, 63), False, 0), ((15, 31, 15), True, 0),
-                                               # the plane phase with its update tiles
+                                               # the plane phase
                                                ((15, 31, 15), True, 1024)])
 def test_minres_solve_captured(csl, shape, fp32, threads):
     p = csl.Problem(_coef(shape, 1), 10.0, 40.0, pinv_fp32=fp32, dst="fft")

@@ -1,7 +1,10 @@
 """GPU parity of the 3-D plane phase (block_threads 1024: one workgroup per
-CU holding a plane of the two leading axes in LDS, so an FP32-preconditioner
-iteration is X, plane, Z instead of five phases) against the CPU oracle and
-against the five-phase solver, through the C ABI.
+CU holding the real or the imaginary part of a plane of the two leading axes
+in LDS, so an FP32-preconditioner iteration is X, plane, Z instead of five
+phases) against the CPU oracle and against the five-phase solver, through the
+C ABI.  Every plane axis has an odd number of lines (n + 1 a power of two),
+so the last line of each pass, transformed as a pair with the line after
+it, has no partner.
 
 Tolerances (relative 2-norm): against the FP64 oracle's iterate after the
 GPU's number of steps 1e-6 (the FP32 preconditioner form).  Against the
@@ -11,8 +14,9 @@ convergence (about 1e-5 relative at k = 1 on the indefinite shift used), the
 plane solver must lie within twice the five-phase solver's own distance from
 the oracle, both from the oracle and from the five-phase iterate: the plane
 phase forms the upper half of each odd extension from its own FFT outputs
-instead of mirroring the lower half, so the two are different FP32
-roundings of the same operator, neither closer to FP64 by construction.
+instead of mirroring the lower half, and transforms two real lines as one
+complex line, so the two are different FP32 roundings of the same operator,
+neither closer to FP64 by construction.
 """
 import sys
 
@@ -143,10 +147,9 @@ def test_plane_rules(csl):
 
 
 def test_plane_adjoint(csl):
-    # the adjoint solve on the plane schedule, whose update tiles write the
-    # adjoint's own output vector: gradients against the oracle's direct
-    # solves (1e-9, both solves at tol 1e-12) and against the five-phase
-    # solver's
+    # the adjoint solve on the plane schedule (its own right-hand side and
+    # output vectors): gradients against the oracle's direct solves (1e-9,
+    # both solves at tol 1e-12) and against the five-phase solver's
     shape = (15, 31, 15)
     a = _coef(shape, 71)
     f = _crand(shape, 72)

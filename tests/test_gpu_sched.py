@@ -112,8 +112,7 @@ def test_batch_more_than_64_systems(csl, block_threads):
         p.close()
 
 
-# 1024: the plane phase (FP32 preconditioner), whose update tiles wait for the
-# planes' fills with a bounded poll
+# 1024: the plane phase (FP32 preconditioner)
 @pytest.mark.parametrize("block_threads", [256, 512, 1024])
 def test_time_limit_single(csl, block_threads):
     n = 127
