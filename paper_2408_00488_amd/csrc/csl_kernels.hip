@@ -43,6 +43,95 @@ __device__ __forceinline__ Cx<R> to_cx(double2 v) {
   return Cx<R>{(R)v.x, (R)v.y};
 }
 
+#if CSL_PLANE
+// ---------------------------------------------------------------------------
+// Staged stencil rows of phase X (plane instance, 3-D).  The plane phase
+// leaves the LDS beyond the row phases' line buffer and twiddles free, so
+// phase X copies the rows of zhat_j that a chunk's stencil reads along axes
+// 1 and 2 (its rows and the one on either side) into it with the LDS DMA,
+// the next chunk's while the current one is transformed and stored; the
+// fill loads only zhat's neighbours along axis 0 and the coefficient from
+// memory.  The values are the same, so the result is too.
+// ---------------------------------------------------------------------------
+#define CSL_LDS __attribute__((address_space(3)))
+
+struct XStage {
+  int s0, s1;   // staged rows [s0, s1)
+};
+
+template <int LDSB>
+__device__ __forceinline__ int x_stage_offset() {
+  return LDSB + tw_lds_bytes(LDSB);
+}
+
+// zhat entries of the staging area: a chunk's rows and one on either side
+__device__ __forceinline__ int x_stage_cap(const SysDesc &S) { return (S.lpt_x + 2) * S.n[2]; }
+
+template <int LDSB>
+__device__ __forceinline__ bool x_stage_fits(const SysDesc &S) {
+  return x_stage_offset<LDSB>() + (long long)x_stage_cap(S) * 16 <= kPlaneLdsBytes;
+}
+
+__device__ __forceinline__ XStage x_stage_rows(const SysDesc &S, const LineTile &t) {
+  XStage g;
+  g.s0 = max(0, t.row0 - 1);
+  g.s1 = min(S.rows, t.row0 + t.nl + 1);
+  return g;
+}
+
+// Start the copy of rows [g.s0, g.s1) of zhat: instruction i of a wave
+// moves 16-byte entries 64 i .. 64 i + 63, one per lane, to consecutive LDS
+// slots.  Completion is awaited with the vector-memory counter.
+__device__ __forceinline__ void x_stage_issue(const SysDesc &S, const CSL_G double2 *zj, char *stage,
+                                              XStage g) {
+  const int n2 = S.n[2];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nz = (g.s1 - g.s0) * n2;
+  double2 *lz = reinterpret_cast<double2 *>(stage);
+  const CSL_G double2 *gz = zj + (size_t)g.s0 * n2;
+  for (int i = w; i * 64 < nz; i += NT / 64) {
+    const int u = i * 64 + lane;
+    if (u < nz)
+      __builtin_amdgcn_global_load_lds((CSL_G void *)(gz + u), (CSL_LDS void *)(lz + i * 64), 16, 0, 0);
+  }
+}
+
+// stencil_load<3> with zhat at the point and along axes 1 and 2 read from
+// the staged rows; q is the point's entry in them
+__device__ __forceinline__ StencilIn<3> stencil_load_staged(const SysDesc &S,
+                                                           const CSL_G double2 *__restrict__ u,
+                                                           int p, const int (&idx)[3],
+                                                           const double2 *lz, int q) {
+  StencilIn<3> in;
+  const CSL_G double *__restrict__ A = gbl(S.a);
+  const int n2 = S.n[2];
+  in.c = lz[q];
+  in.ap = A[p];
+  in.inb = 0u;
+  in.ina = 0u;
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    const bool lo = idx[ax] > 0, hi = idx[ax] < S.n[ax] - 1;
+    in.inb |= (lo ? 1u : 0u) << ax;
+    in.ina |= (hi ? 1u : 0u) << ax;
+    if (ax == 0) {
+      const int st = S.st[0];
+      in.b[0] = lo ? ldg(u + (p - st)) : make_double2(0.0, 0.0);
+      in.a[0] = hi ? ldg(u + (p + st)) : make_double2(0.0, 0.0);
+      in.ab[0] = lo ? A[p - st] : 0.0;
+      in.aa[0] = hi ? A[p + st] : 0.0;
+    } else {
+      const int sq = (ax == 1) ? n2 : 1;
+      in.b[ax] = lo ? lz[q - sq] : make_double2(0.0, 0.0);
+      in.a[ax] = hi ? lz[q + sq] : make_double2(0.0, 0.0);
+      in.ab[ax] = lo ? A[p - sq] : 0.0;
+      in.aa[ax] = hi ? A[p + sq] : 0.0;
+    }
+  }
+  return in;
+}
+#endif  // CSL_PLANE
+
 // ---------------------------------------------------------------------------
 // K_X, rows of the contiguous axis, always FP64 (it transforms Lanczos
 // vectors, not preconditioner data).
@@ -60,9 +149,50 @@ __device__ __forceinline__ void tile_X(const SysDesc &S, const IOPtr &io, int it
   load_twiddles_cached<double>(twl, S.lg[D - 1]);
   double acc = 0.0;
   const int c1 = min(S.nchunk[K_X], (tile + 1) * S.cpt[K_X]);
+#if CSL_PLANE
+  // staged rows (plane instance): the first chunk's copy starts here
+  const bool stg = (D == 3) && S.plane && iter > 0 && x_stage_fits<LDSB>(S);
+  char *stage = smem + x_stage_offset<LDSB>();
+  if (stg) {
+    x_stage_issue(S, gbl(S.Z[iter & 1]), stage,
+                  x_stage_rows(S, line_tile(S, D - 1, S.lpt_x, tile * S.cpt[K_X])));
+  }
+#endif
   for (int chunk = tile * S.cpt[K_X]; chunk < c1; ++chunk) {
     const LineTile t = line_tile(S, D - 1, S.lpt_x, chunk);
     CSL_G Cx<double> *out;
+#if CSL_PLANE
+    if (stg) {
+      const CSL_G double2 *__restrict__ zj = gbl(S.Z[iter & 1]);
+      const double al = S.alpha, be = S.beta;
+      const XStage g = x_stage_rows(S, t);
+      const double2 *lz = reinterpret_cast<const double2 *>(stage);
+      const int n2 = S.n[2];
+      // this wave's copies (and stores) done, then every wave's
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      E::template fill2<1>(
+          buf, t,
+          [&](int l, int r, int p) {
+            int idx[3];
+            row_index<3>(S, t.row0 + l, r, idx);
+            return stencil_load_staged(S, zj, p, idx, lz, (t.row0 + l - g.s0) * n2 + r);
+          },
+          [&](int, int, int, const StencilIn<3> &in) {
+            const double2 kz = stencil_apply<3>(S, in);
+            const double2 zz = in.c;
+            const double qx = kz.x + al * zz.x + be * zz.y;
+            const double qy = -(kz.y + al * zz.y - be * zz.x);
+            acc += zz.x * qx + zz.y * qy;
+            return Cx<double>{qx, qy};
+          });
+      // the fill ended with a barrier: the staging area is free for the
+      // next chunk's rows, which arrive while this chunk is transformed
+      if (chunk + 1 < c1)
+        x_stage_issue(S, zj, stage, x_stage_rows(S, line_tile(S, D - 1, S.lpt_x, chunk + 1)));
+      out = gbl(reinterpret_cast<Cx<double> *>(S.Tq));
+    } else
+#endif
     if (iter == 0) {
       const CSL_G double2 *__restrict__ f = gbl(io.f);
       CSL_G double2 *__restrict__ X = gbl(io.x);

@@ -67,7 +67,10 @@ def rel(a, b):
 SHAPES = [((15, 15, 15), None), ((7, 15, 31), [0.5, 1.0, 2.0]), ((31, 31, 31), None),
           ((63, 31, 15), None), ((31, 63, 3), None), ((127, 127, 7), None),
           # 3-point plane axes: lines of 8 points (a radix-2 stage, 32 lines per wave)
-          ((3, 7, 15), None), ((15, 3, 31), [1.0, 2.0, 1.0]), ((127, 3, 3), None)]
+          ((3, 7, 15), None), ((15, 3, 31), [1.0, 2.0, 1.0]), ((127, 3, 3), None),
+          # a long contiguous axis: phase X on chunks of two rows, staged with
+          # their neighbours along axis 1
+          ((7, 15, 1023), None)]
 
 
 @pytest.mark.parametrize("shape,lengths", SHAPES)
