@@ -295,8 +295,10 @@ typedef struct csl_batch_opts {
     int block_threads;      /* workgroup size of the persistent solver: 0 =
                                512 if every problem allows it (the FFT on
                                every axis), else 256; 256; 512 (CSL_ERR_ARG
-                               unless every problem allows it); the plane
-                               phase (1024) is for single solves only      */
+                               unless every problem allows it); 1024, the
+                               plane phase (CSL_ERR_ARG unless every problem
+                               is 3-D with the FP32 preconditioner, the FFT
+                               on every axis and n0, n1 <= 127)            */
 } csl_batch_opts;
 
 /* Schedule chosen by batch_tune or problem_tune, or in use

@@ -273,6 +273,7 @@ struct csl_batch_s {
   int block_threads = 256;
   bool wg512_ok = false; // every problem allows the 512-thread solver
   bool all2d = true;     // every problem is 2-D (the 2-D-only 512-thread instance)
+  bool plane_ok = false; // every problem allows the plane phase (block_threads 1024)
   bool g16 = false;      // some problem has an axis on the FP16 split-product engine
 };
 
@@ -629,11 +630,18 @@ csl_status configure_batch(csl_batch b, int tile_points, int lds_bytes, int bloc
   b->graph = nullptr;
   std::vector<SysDesc> descs(b->count);
   size_t smem = 0;
+  const bool plane = resolve_wg(block_threads, b->wg512_ok) == 1024;
   for (int i = 0; i < b->count; ++i) {
     const csl_problem p = b->probs[i];
     descs[i] = p->h0;
     size_t sm = p->smem0;
-    if (lds_bytes > 32768 && p->smem0 <= 32768) {
+    if (plane) {
+      // the row phases on a 64 KiB line buffer, then the plane layout
+      choose_tiles(descs[i], p->tile_elems, 65536, &sm);
+      plane_tiling(descs[i]);
+      if (descs[i].maxtile > p->part_cap)
+        return fail(CSL_ERR_ARG, "chunking exceeds the partial-sum slots");
+    } else if (lds_bytes > 32768 && p->smem0 <= 32768) {
       // a larger budget only lengthens the chunks: chunk counts (and with
       // them the partial-sum slots each problem allocated) can only shrink
       choose_tiles(descs[i], p->tile_elems, lds_bytes, &sm);
@@ -1587,17 +1595,22 @@ csl_status batch_create(const csl_problem *problems, int count, const csl_batch_
   if (o.lds_bytes != 0 && o.lds_bytes != 32768 && o.lds_bytes != 65536)
     return cleanup(CSL_ERR_ARG, "lds_bytes must be 0, 32768 or 65536");
   if (o.tile_points < 0) return cleanup(CSL_ERR_ARG, "tile_points must be >= 0");
-  if (!valid_block_threads(o.block_threads) || o.block_threads == 1024)
-    return cleanup(CSL_ERR_ARG, "block_threads must be 0, 256 or 512 for a batch");
+  if (!valid_block_threads(o.block_threads))
+    return cleanup(CSL_ERR_ARG, "block_threads must be 0, 256, 512 or 1024");
   b->wg512_ok = true;
   b->all2d = true;
+  b->plane_ok = true;
   for (int i = 0; i < count; ++i) {
     b->wg512_ok = b->wg512_ok && problems[i]->wg512_ok;
     b->all2d = b->all2d && problems[i]->h.d == 2;
     b->g16 = b->g16 || has_gemm16(problems[i]->h);
+    b->plane_ok = b->plane_ok && plane_ok(problems[i]->h0);
   }
   if (o.block_threads == 512 && !b->wg512_ok)
     return cleanup(CSL_ERR_ARG, "block_threads 512 needs the FFT engine on every axis of every problem");
+  if (o.block_threads == 1024 && !b->plane_ok)
+    return cleanup(CSL_ERR_ARG, "block_threads 1024 (the plane phase) needs 3-D problems with the "
+                                "FP32 preconditioner, the FFT on every axis and n0, n1 <= 127");
   {
     // the adjoint solves read conj(G) from each problem's gtmp and write
     // conj(y) to its ytmp
@@ -1746,11 +1759,14 @@ csl_status batch_tune(csl_batch b, const double *const *f, double *const *z,
   };
   std::vector<Cand> cands;
   cands.push_back({tp0, lds0, wg0});
-  for (int wg : {256, 512}) {
+  for (int wg : {256, 512, 1024}) {
     if (wg == 512 && !b->wg512_ok) continue;
-    for (int lds : {32768, 65536})
+    if (wg == 1024 && !b->plane_ok) continue;
+    for (int lds : {32768, 65536}) {
+      if (wg == 1024 && lds != 65536) continue;   // the plane instance's own budget
       for (int tp : {6144, 8192, 12288, 16384, 24576})
         if (!(tp == tp0 && lds == lds0 && wg == wg0)) cands.push_back({tp, lds, wg});
+    }
   }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(hipEventCreate(&e0));

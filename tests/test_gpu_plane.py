@@ -138,8 +138,9 @@ def test_plane_rules(csl):
         with pytest.raises(csl.CSLError, match="ERR_ARG"):
             p.set_schedule(0, 65536, 1024)
     p = csl.Problem(a3, 1.0, 5.0, pinv_fp32=True, dst="fft")
+    # a batch takes the plane phase only when every problem allows it
     with pytest.raises(csl.CSLError, match="ERR_ARG"):
-        csl.Batch([p], block_threads=1024)
+        csl.Batch([p, csl.Problem(a3, 1.0, 5.0, pinv_fp32=False, dst="fft")], block_threads=1024)
     # the tuner may pick the plane phase; the tuned problem still solves
     f = cuda(_crand((15, 15, 15), 4))
     t = p.tune(f)
@@ -177,6 +178,61 @@ def test_plane_adjoint(csl):
     _say("  vs five phases", rel(g["a"].cpu().numpy(), g5["a"].cpu().numpy()))
     assert rel(g["a"].cpu().numpy(), g5["a"].cpu().numpy()) <= 1e-9
     p.close()
+
+
+def test_plane_batch(csl):
+    # a batch of 3-D systems of different sizes and shifts on the plane
+    # phase: each system against the FP64 oracle's iterate after the GPU's
+    # number of steps (1e-6), with the schedule kept by the batch
+    cases = [((15, 31, 15), -20.0 + 45.0j, None), ((31, 15, 7), 10.0 + 100.0j, None),
+             ((7, 7, 63), 5.0 + 20.0j, [1.0, 0.5, 2.0])]
+    probs, fs, olds = [], [], []
+    for i, (shape, lam, lengths) in enumerate(cases):
+        a = _coef(shape, 81 + i)
+        f = _crand(shape, 91 + i)
+        probs.append(csl.Problem(cuda(a), lam.real, lam.imag, pinv_fp32=True, lengths=lengths,
+                                 dst="fft"))
+        fs.append(cuda(f))
+        olds.append((O.Problem(a, lam.real, lam.imag, lengths=lengths), f))
+    b = csl.Batch(probs, block_threads=1024)
+    assert b.schedule["block_threads"] == 1024
+    zs, infos = b.solve(fs)
+    for (po, f), z, info in zip(olds, zs, infos):
+        _say("plane batch", info)
+        assert info["status"] == 0 and info["relres_true"] <= 1e-8
+        zx, _ = po.solve(f, fixed_iters=info["iters"])
+        assert rel(z.cpu().numpy(), zx) <= 1e-6
+    b.close()
+    for p in probs:
+        p.close()
+
+
+def test_plane_batch_adjoint(csl):
+    # the batched adjoint on the plane phase (one grid, two shifts) against
+    # each problem's own adjoint on the plane schedule, all at tol 1e-12:
+    # per-system gradients in f and alpha, the summed one in a (1e-9)
+    shape = (15, 31, 15)
+    a = _coef(shape, 95)
+    probs = [csl.Problem(cuda(a), lam.real, lam.imag, pinv_fp32=True, dst="fft")
+             for lam in (-20.0 + 45.0j, 10.0 + 100.0j)]
+    fs = [cuda(_crand(shape, 96 + i)) for i in range(2)]
+    b = csl.Batch(probs, tol=1e-12, block_threads=1024)
+    zs, _ = b.solve(fs)
+    gzs = [2.0 * z for z in zs]
+    g, _ = b.adjoint(zs, gzs, tol=1e-12)
+    ga = None
+    for i, (p, z, gz) in enumerate(zip(probs, zs, gzs)):
+        p.set_schedule(0, 65536, 1024)
+        g1, _ = csl.minres_adjoint(p, z, gz, tol=1e-12)
+        _say("  system", i, rel(g["f"][i].cpu().numpy(), g1["f"].cpu().numpy()))
+        assert rel(g["f"][i].cpu().numpy(), g1["f"].cpu().numpy()) <= 1e-9
+        assert g["alpha"][i].item() == pytest.approx(g1["alpha"].item(), rel=1e-9)
+        assert g["beta"][i].item() == pytest.approx(g1["beta"].item(), rel=1e-9)
+        ga = g1["a"] if ga is None else ga + g1["a"]
+    assert rel(g["a"].cpu().numpy(), ga.cpu().numpy()) <= 1e-9
+    b.close()
+    for p in probs:
+        p.close()
 
 
 @pytest.mark.timeout(900)
