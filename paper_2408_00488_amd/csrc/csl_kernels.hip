@@ -873,10 +873,18 @@ __device__ __forceinline__ void tile_pinv(const SysDesc &S, int pass, const doub
 // completion count, the scalars) before the new ticket word; on gfx950 an
 // agent-scope release writes back the L2, an acquire invalidates it, so no
 // fence beyond the one the protocol needs is issued.
-__device__ __forceinline__ void publish(Ctl *C, int iter, int kind) {
+// Tiles of a phase that the workgroups of a single-system solve own from the
+// start (sg = the grid size; 0 for a batch): workgroup b takes tile b <
+// min(sg, tiles) the first time it sees the phase, without a claim, and the
+// claim counter of the published phase starts after them.
+__device__ __forceinline__ int static_tiles(const SysDesc &S, int kind, int sg) {
+  return kind < K_NKINDS ? min(sg, S.ntile[kind]) : 0;
+}
+
+__device__ __forceinline__ void publish(const SysDesc &S, Ctl *C, int iter, int kind, int sg) {
   __hip_atomic_store(&C->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_exchange(&C->word, (unsigned long long)make_word(iter, kind), __ATOMIC_RELEASE,
-                        __HIP_MEMORY_SCOPE_AGENT);
+  const uint64_t w = make_word(iter, kind) + (uint64_t)static_tiles(S, kind, sg);
+  __hip_atomic_exchange(&C->word, (unsigned long long)w, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ void finish(const SysDesc &S, Glob *G, int iter, int status, int iters, double rt) {
@@ -896,20 +904,20 @@ enum { ST_OK = 0, ST_NOT_CONVERGED = 3, ST_BREAKDOWN = 4, ST_NONFINITE = 5 };
 // update of step iter - 1 is still deferred, run one K_Z phase that applies
 // it alone (ZM_FLUSH) and finish from its epilogue.
 __device__ __forceinline__ void end_solve(const SysDesc &S, Glob *G, Ctl *C, int iter, int status,
-                                          int iters) {
+                                          int iters, int sg) {
   if (C->pend) {
     C->pend = 0;
     C->zmode = ZM_FLUSH;
     C->fin_status = status;
     C->fin_iters = iters;
-    publish(C, iter, K_Z);
+    publish(S, C, iter, K_Z, sg);
   } else {
     finish(S, G, iter, status, iters, __longlong_as_double(0x7ff8000000000000ll));
   }
 }
 
 __device__ __forceinline__ void epilogue(const SysDesc &S, const SolveParams &P, int kind, int iter, Glob *G,
-                         double *red) {
+                         double *red, int sg) {
   const int nt = S.ntile[kind];
   const bool last_strided = (kind == K_Y);   // carries the gamma^2 partials
   const bool need_sum = (kind == K_X) || (kind == K_PR) || last_strided;
@@ -934,22 +942,22 @@ __device__ __forceinline__ void epilogue(const SysDesc &S, const SolveParams &P,
         S.info->relres_est = 0.0;
         finish(S, G, iter, ST_OK, 0, 0.0);
       } else {
-        publish(C, 0, first_strided);
+        publish(S, C, 0, first_strided, sg);
       }
     } else if (!isfinite(sum)) {
-      end_solve(S, G, C, iter, ST_NONFINITE, iter - 1);
+      end_solve(S, G, C, iter, ST_NONFINITE, iter - 1, sg);
     } else {
       C->delta = sum;
-      publish(C, iter, first_strided);
+      publish(S, C, iter, first_strided, sg);
     }
     return;
   }
   if (kind == K_Y1) {
-    publish(C, iter, K_Y);
+    publish(S, C, iter, K_Y, sg);
     return;
   }
   if (kind == K_Y1I) {
-    publish(C, iter, K_Z);
+    publish(S, C, iter, K_Z, sg);
     return;
   }
   if (last_strided) {
@@ -957,7 +965,7 @@ __device__ __forceinline__ void epilogue(const SysDesc &S, const SolveParams &P,
     if (!isfinite(g2)) {
       S.info->relres_est = nan;
       if (iter == 0) finish(S, G, iter, ST_NONFINITE, 0, nan);
-      else end_solve(S, G, C, iter, ST_NONFINITE, iter - 1);
+      else end_solve(S, G, C, iter, ST_NONFINITE, iter - 1, sg);
       return;
     }
     if (iter == 0) {
@@ -977,11 +985,11 @@ __device__ __forceinline__ void epilogue(const SysDesc &S, const SolveParams &P,
       C->s_old = 0.0;
       C->after_z = 0;
       C->pend = 0;
-      publish(C, 0, five ? K_Y1I : K_Z);
+      publish(S, C, 0, five ? K_Y1I : K_Z, sg);
       return;
     }
     if (g2 < 0.0) {
-      end_solve(S, G, C, iter, ST_BREAKDOWN, iter - 1);
+      end_solve(S, G, C, iter, ST_BREAKDOWN, iter - 1, sg);
       return;
     }
     // Givens rotations of column j of the Lanczos tridiagonal (step j)
@@ -1034,13 +1042,13 @@ __device__ __forceinline__ void epilogue(const SysDesc &S, const SolveParams &P,
     const int zm = C->pend ? ZM_PAIR : (C->after_z != 0 ? ZM_SINGLE : ZM_DEFER);
     C->zmode = zm;
     C->pend = (zm == ZM_DEFER);
-    publish(C, iter, five ? K_Y1I : K_Z);
+    publish(S, C, iter, five ? K_Y1I : K_Z, sg);
     return;
   }
   if (kind == K_Z) {
     if (iter > 0 && C->zmode == ZM_FLUSH) finish(S, G, iter, C->fin_status, C->fin_iters, nan);
-    else if (iter == 0 || C->after_z == 0) publish(C, iter + 1, K_X);
-    else publish(C, iter, K_PR);
+    else if (iter == 0 || C->after_z == 0) publish(S, C, iter + 1, K_X, sg);
+    else publish(S, C, iter, K_PR, sg);
     return;
   }
   if (kind == K_PR) {
@@ -1053,7 +1061,7 @@ __device__ __forceinline__ void epilogue(const SysDesc &S, const SolveParams &P,
     } else if (k >= P.maxit) {
       finish(S, G, iter, ST_NOT_CONVERGED, k, rt);
     } else {
-      publish(C, iter + 1, K_X);
+      publish(S, C, iter + 1, K_X, sg);
     }
     return;
   }
@@ -1085,14 +1093,53 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(CSL_WAVES_PE
   // up the next phase sooner; a batch keeps workgroups busy with other
   // systems, and polls less (about 14 us).
   const int bcap = nsys > 1 ? 64 : 4;
+  // a single system: every phase but the first is published with tiles
+  // 0 .. min(grid, tiles) - 1 owned by the workgroups of those indices
+  const int sg = nsys == 1 ? (int)gridDim.x : 0;
+  unsigned seen = 0xffffffffu;   // [iter | kind] of the last owned tile taken
   for (;;) {
     if (tid < 64) {
-      // Wave 0 looks at up to 64 systems per round trip: each lane loads one
-      // ticket word, a ballot lists the systems with a tile ready, and lanes
-      // try to claim one in order, starting from the last system served.
       const int lane = tid;
       int found = -1;
-      for (int base = 0; base < nsys && found == -1; base += 64) {
+      if (sg > 0) {
+        // single system: the workgroup's own tile of a phase it has not
+        // served yet, else a tile past the owned ones from the counter
+        if (lane == 0) {
+          const uint64_t w = __hip_atomic_load(&sys[0].ctl->word, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+          const int kd = word_kind(w);
+          if (kd < K_NKINDS) {
+            const int it = word_iter(w);
+            const unsigned key = (unsigned)(w >> 32);
+            const bool owned = !(it == 0 && kd == K_X);   // the first phase has no owners
+            if (owned && key != seen && (int)blockIdx.x < static_tiles(sys[0], kd, sg)) {
+              seen = key;
+              sh_tile = (int)blockIdx.x;
+              sh_kind = kd;
+              sh_iter = it;
+              found = 0;
+              __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            } else if (word_next(w) < (uint32_t)sys[0].ntile[kd]) {
+              const uint64_t w2 = __hip_atomic_fetch_add(&sys[0].ctl->word, 1ull, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+              const int kd2 = word_kind(w2);
+              if (kd2 < K_NKINDS && word_next(w2) < (uint32_t)sys[0].ntile[kd2]) {
+                sh_tile = (int)word_next(w2);
+                sh_kind = kd2;
+                sh_iter = word_iter(w2);
+                found = 0;
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+              }
+            }
+          }
+        }
+        found = __shfl(found, 0, 64);
+      }
+      // Otherwise wave 0 looks at up to 64 systems per round trip: each lane
+      // loads one ticket word, a ballot lists the systems with a tile ready,
+      // and lanes try to claim one in order, starting from the last system
+      // served.
+      for (int base = 0; sg == 0 && base < nsys && found == -1; base += 64) {
         const int k = base + lane;
         int sl = cur + k;
         while (sl >= nsys) sl -= nsys;
@@ -1178,7 +1225,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(CSL_WAVES_PE
         sh_last = last;
       }
       __syncthreads();
-      if (sh_last) epilogue(S, P, kind, iter, G, red);
+      if (sh_last) epilogue(S, P, kind, iter, G, red, sg);
     }
     __syncthreads();
   }
