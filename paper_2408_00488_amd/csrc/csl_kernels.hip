@@ -874,11 +874,22 @@ __device__ __forceinline__ void tile_pinv(const SysDesc &S, int pass, const doub
 // agent-scope release writes back the L2, an acquire invalidates it, so no
 // fence beyond the one the protocol needs is issued.
 // Tiles of a phase that the workgroups of a single-system solve own from the
-// start (sg = the grid size; 0 for a batch): workgroup b takes tile b <
-// min(sg, tiles) the first time it sees the phase, without a claim, and the
-// claim counter of the published phase starts after them.
+// start (sg = the grid size; 0 for a batch): each tile below min(sg, tiles)
+// has one owner, which takes it the first time it sees the phase, without a
+// claim, and the claim counter of the published phase starts after them.
 __device__ __forceinline__ int static_tiles(const SysDesc &S, int kind, int sg) {
   return kind < K_NKINDS ? min(sg, S.ntile[kind]) : 0;
+}
+
+// Owned tile of workgroup b in a grid of g: workgroups are dealt to the 8
+// XCDs round robin (b mod 8), and the workgroups of XCD x own tiles
+// [start_x, start_x + count_x) in order, a bijection of [0, g).  The
+// stencil's neighbouring rows then mostly come from tiles on the same XCD,
+// whose L2 already holds them.
+__device__ __forceinline__ int xcd_tile(int b, int g) {
+  const int x = b & 7, i = b >> 3;
+  const int q = g >> 3, r = g & 7;   // XCDs below r hold q + 1 workgroups
+  return x * q + min(x, r) + i;
 }
 
 __device__ __forceinline__ void publish(const SysDesc &S, Ctl *C, int iter, int kind, int sg) {
@@ -1094,7 +1105,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(CSL_WAVES_PE
   // systems, and polls less (about 14 us).
   const int bcap = nsys > 1 ? 64 : 4;
   // a single system: every phase but the first is published with tiles
-  // 0 .. min(grid, tiles) - 1 owned by the workgroups of those indices
+  // 0 .. min(grid, tiles) - 1 owned by workgroups, one each (xcd_tile)
   const int sg = nsys == 1 ? (int)gridDim.x : 0;
   unsigned seen = 0xffffffffu;   // [iter | kind] of the last owned tile taken
   for (;;) {
@@ -1112,9 +1123,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(CSL_WAVES_PE
             const int it = word_iter(w);
             const unsigned key = (unsigned)(w >> 32);
             const bool owned = !(it == 0 && kd == K_X);   // the first phase has no owners
-            if (owned && key != seen && (int)blockIdx.x < static_tiles(sys[0], kd, sg)) {
+            // workgroup b (on XCD b mod 8) owns tile xcd_tile(b): each XCD a
+            // contiguous run of tiles, so neighbouring tiles share an L2
+            const int own = xcd_tile((int)blockIdx.x, sg);
+            if (owned && key != seen && own < static_tiles(sys[0], kd, sg)) {
               seen = key;
-              sh_tile = (int)blockIdx.x;
+              sh_tile = own;
               sh_kind = kd;
               sh_iter = it;
               found = 0;
