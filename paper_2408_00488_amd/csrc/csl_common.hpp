@@ -29,12 +29,16 @@ enum Kind : int {
   K_DONE = 15
 };
 
-// Ticket word of a system: [iter:24 | kind:8 | next tile:32].
+// Ticket word of a system: [iter:24 | owned:1 | kind:7 | next tile:32]; owned
+// marks a phase whose first tiles belong to the workgroups of a fully
+// resident single-system grid (see the solver's scheduler).
 __host__ __device__ inline uint64_t make_word(int iter, int kind) {
   return ((uint64_t)(uint32_t)iter << 40) | ((uint64_t)(uint32_t)kind << 32);
 }
+constexpr uint64_t kWordOwned = 1ull << 39;
 __host__ __device__ inline int word_iter(uint64_t w) { return (int)(w >> 40); }
-__host__ __device__ inline int word_kind(uint64_t w) { return (int)((w >> 32) & 0xff); }
+__host__ __device__ inline int word_kind(uint64_t w) { return (int)((w >> 32) & 0x7f); }
+__host__ __device__ inline bool word_owned(uint64_t w) { return (w & kWordOwned) != 0; }
 __host__ __device__ inline uint32_t word_next(uint64_t w) { return (uint32_t)w; }
 
 // Per-system control block: scheduling state and MINRES scalars.
@@ -54,6 +58,7 @@ struct alignas(64) Ctl {
   int zmode;                 // what the K_Z phase does (ZM_*)
   int pend;                  // 1: the previous step's update is deferred
   int fin_status, fin_iters; // finish after a ZM_FLUSH phase
+  int owned_ok;              // every workgroup of the solver's grid has started
 };
 
 // K_Z phase modes.  The w/x updates of MINRES run two steps at a time: a
@@ -158,7 +163,8 @@ struct SolveParams {
 struct Glob {
   int active;          // systems not finished
   int error;           // nonzero: abort (time limit)
-  int pad[14];
+  int arrived;         // workgroups of the solver's grid that have started
+  int pad[13];
 };
 
 }  // namespace csl

@@ -874,9 +874,11 @@ __device__ __forceinline__ void tile_pinv(const SysDesc &S, int pass, const doub
 // agent-scope release writes back the L2, an acquire invalidates it, so no
 // fence beyond the one the protocol needs is issued.
 // Tiles of a phase that the workgroups of a single-system solve own from the
-// start (sg = the grid size; 0 for a batch): each tile below min(sg, tiles)
-// has one owner, which takes it the first time it sees the phase, without a
-// claim, and the claim counter of the published phase starts after them.
+// start (sg = the grid size; 0 for a batch or while some workgroup of the grid
+// has not started): each tile below min(sg, tiles) has one owner, which takes
+// it the first time it sees the phase, without a claim, and the claim counter
+// of the published phase starts after them.  Owners are used only once every
+// workgroup is resident, so that progress never waits on one that is not.
 __device__ __forceinline__ int static_tiles(const SysDesc &S, int kind, int sg) {
   return kind < K_NKINDS ? min(sg, S.ntile[kind]) : 0;
 }
@@ -894,7 +896,8 @@ __device__ __forceinline__ int xcd_tile(int b, int g) {
 
 __device__ __forceinline__ void publish(const SysDesc &S, Ctl *C, int iter, int kind, int sg) {
   __hip_atomic_store(&C->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const uint64_t w = make_word(iter, kind) + (uint64_t)static_tiles(S, kind, sg);
+  const int s0 = static_tiles(S, kind, sg);
+  const uint64_t w = make_word(iter, kind) + (s0 > 0 ? kWordOwned + (uint64_t)s0 : 0ull);
   __hip_atomic_exchange(&C->word, (unsigned long long)w, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -940,6 +943,14 @@ __device__ __forceinline__ void epilogue(const SysDesc &S, const SolveParams &P,
   if (threadIdx.x != 0) return;
   Ctl *C = S.ctl;
   const double nan = __longlong_as_double(0x7ff8000000000000ll);
+  // owners for the phases published here only once every workgroup has
+  // started (recorded in the control block, so the count is read until then)
+  if (sg > 0 && !C->owned_ok) {
+    if (__hip_atomic_load(&G->arrived, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= sg)
+      C->owned_ok = 1;
+    else
+      sg = 0;
+  }
   const bool five = (S.d == 3) && !S.plane;   // 3-D with the three strided phases
   const int first_strided = five ? K_Y1 : K_Y;
   if (kind == K_X) {
@@ -1104,9 +1115,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(CSL_WAVES_PE
   // up the next phase sooner; a batch keeps workgroups busy with other
   // systems, and polls less (about 14 us).
   const int bcap = nsys > 1 ? 64 : 4;
-  // a single system: every phase but the first is published with tiles
-  // 0 .. min(grid, tiles) - 1 owned by workgroups, one each (xcd_tile)
+  // a single system: once every workgroup has started, phases are published
+  // with tiles 0 .. min(grid, tiles) - 1 owned by workgroups, one each
+  // (xcd_tile)
   const int sg = nsys == 1 ? (int)gridDim.x : 0;
+  if (tid == 0) __hip_atomic_fetch_add(&G->arrived, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   unsigned seen = 0xffffffffu;   // [iter | kind] of the last owned tile taken
   for (;;) {
     if (tid < 64) {
@@ -1122,11 +1135,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(CSL_WAVES_PE
           if (kd < K_NKINDS) {
             const int it = word_iter(w);
             const unsigned key = (unsigned)(w >> 32);
-            const bool owned = !(it == 0 && kd == K_X);   // the first phase has no owners
             // workgroup b (on XCD b mod 8) owns tile xcd_tile(b): each XCD a
             // contiguous run of tiles, so neighbouring tiles share an L2
             const int own = xcd_tile((int)blockIdx.x, sg);
-            if (owned && key != seen && own < static_tiles(sys[0], kd, sg)) {
+            if (word_owned(w) && key != seen && own < static_tiles(sys[0], kd, sg)) {
               seen = key;
               sh_tile = own;
               sh_kind = kd;
@@ -1255,6 +1267,7 @@ __global__ void init_kernel(const SysDesc *__restrict__ sys, int nsys, Glob *G) 
     C->after_z = 0;
     C->pend = 0;
     C->zmode = ZM_DEFER;
+    C->owned_ok = 0;
     DevInfo *I = sys[s].info;
     I->status = -1;
     I->iters = 0;
@@ -1265,6 +1278,7 @@ __global__ void init_kernel(const SysDesc *__restrict__ sys, int nsys, Glob *G) 
   if (threadIdx.x == 0) {
     G->active = nsys;
     G->error = 0;
+    G->arrived = 0;
   }
 }
 

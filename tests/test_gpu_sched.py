@@ -260,6 +260,38 @@ def test_problems_from_several_threads(csl):
         assert i == ir and torch.equal(z, zr)
 
 
+def test_concurrent_whole_gpu_solves(csl):
+    # two single solves on the plane schedule (one 1024-thread workgroup per
+    # CU, 254 workgroups each) launched on two streams at once: the second
+    # kernel can start only part of its grid while the first runs, so its
+    # phases must go to whichever workgroups are resident (tiles are owned
+    # by workgroups only once the whole grid has started).  Both finish, and
+    # each result equals the same solve run alone, bit for bit.
+    shape = (127, 127, 127)
+    a = cuda(_coef(shape, 11, 1.0, 3.0))
+    fs = [cuda(_crand(shape, 12 + j)) for j in range(2)]
+    probs = [csl.Problem(a, 10.0 + 20.0 * j, 100.0, pinv_fp32=True, dst="fft") for j in range(2)]
+    for p in probs:
+        p.set_schedule(8128, 65536, 1024)
+    ref = []
+    for p, f in zip(probs, fs):
+        z, info = csl.minres_solve(p, f, timeout_ms=30000)
+        assert info["status"] == 0, info
+        ref.append((z.clone(), info))
+    streams = [torch.cuda.Stream() for _ in probs]
+    zs = [torch.empty_like(f) for f in fs]
+    torch.cuda.synchronize()
+    for p, f, z, st in zip(probs, fs, zs, streams):
+        with torch.cuda.stream(st):
+            csl.minres_solve(p, f, z, timeout_ms=30000, want_info=False)
+    torch.cuda.synchronize()
+    for z, (zr, ir) in zip(zs, ref):
+        _say("concurrent solve", ir["iters"], "iterations alone; equal:", torch.equal(z, zr))
+        assert torch.equal(z, zr)
+    for p in probs:
+        p.close()
+
+
 def test_chunk_size_schedule(csl):
     # small grids may run their own solves on 512- or 1024-element chunks;
     # a chunking with more tiles than partial-sum slots is refused and the
