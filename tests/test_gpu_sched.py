@@ -292,6 +292,28 @@ def test_concurrent_whole_gpu_solves(csl):
         p.close()
 
 
+@pytest.mark.parametrize("threads,fp32", [(1024, True), (512, False)])
+def test_owned_and_claimed_tiles(csl, threads, fp32):
+    # one LDS chunk per tile on a 127^3 grid: the row phases have about a
+    # thousand tiles for 254 or 512 workgroups, so each phase starts with
+    # the tiles the workgroups own and goes on with claimed ones.  The solve
+    # converges and agrees with the usual schedule's (1e-6 with the FP32
+    # preconditioner, 1e-10 in FP64).
+    shape = (127, 127, 127)
+    a = cuda(_coef(shape, 21, 1.0, 3.0))
+    f = cuda(_crand(shape, 22))
+    p = csl.Problem(a, 10.0, 100.0, pinv_fp32=fp32, dst="fft")
+    p.set_schedule(8128 if threads == 1024 else 8192, 65536, threads)
+    z0, i0 = csl.minres_solve(p, f, timeout_ms=30000)
+    p.set_schedule(1, 65536, threads)
+    z1, i1 = csl.minres_solve(p, f, timeout_ms=30000)
+    _say("owned and claimed", threads, p.schedule["grid_size"], i0["iters"], i1["iters"],
+         rel(z1.cpu().numpy(), z0.cpu().numpy()))
+    assert i1["status"] == 0 and i1["relres_true"] <= 1e-8
+    assert rel(z1.cpu().numpy(), z0.cpu().numpy()) <= (1e-6 if fp32 else 1e-10)
+    p.close()
+
+
 def test_chunk_size_schedule(csl):
     # small grids may run their own solves on 512- or 1024-element chunks;
     # a chunking with more tiles than partial-sum slots is refused and the
