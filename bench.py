@@ -38,14 +38,22 @@ PEAK_HBM_GBS = 8000.0
 # streams with one read of each operand and one write of each result per
 # step: stencil 40 (z 16 in, a 8, A z 16 out) + Lanczos recurrence and w / x
 # updates 160 (seven 16-byte reads, three writes) + p sine-transform passes
-# of 4 s bytes (read + write of a complex value of s-byte parts):
-#   2-D FP64 (p = 3, s = 8) 296, 2-D FP32 preconditioner (s = 4) 248,
-#   3-D FP64 (p = 5) 360, 3-D FP32 preconditioner (p = 3: the xy-plane of
-#   the two leading axes transformed in one pass) 248.
-BYTES_MODEL = {(2, False): 296.0, (2, True): 248.0, (3, False): 360.0, (3, True): 248.0}
+# of 4 s bytes (read + write of a complex value of s-byte parts; s = 8 FP64,
+# 4 FP32 preconditioner).  p = 3 in 2-D and in 3-D with the plane phase (the
+# plane of the two leading axes transformed in one pass), 5 in 3-D otherwise:
+#   2-D FP64 296, 2-D FP32 248, 3-D plane FP64 296 and FP32 248,
+#   3-D five-pass FP64 360 and FP32 280.
+
+
+def bytes_model(d: int, fp32: bool, plane: bool = False) -> float:
+    p = 3 if d == 2 or plane else 5
+    return 200.0 + p * 4.0 * (4 if fp32 else 8)
+
+
 # The same model with the w / x updates of two consecutive steps sharing one
 # pass (what the solver does): 32 bytes less per iteration.
-BYTES_MODEL_PAIRED = {k: v - 32.0 for k, v in BYTES_MODEL.items()}
+def bytes_model_paired(d: int, fp32: bool, plane: bool = False) -> float:
+    return bytes_model(d, fp32, plane) - 32.0
 
 
 def log(*a):
@@ -136,6 +144,7 @@ KERNEL_SOURCES = ["paper_2408_00488_amd/csrc/csl_kernels.hip",
                   "paper_2408_00488_amd/csrc/csl_kernels_wg512.hip",
                   "paper_2408_00488_amd/csrc/csl_kernels_wg512x.hip",
                   "paper_2408_00488_amd/csrc/csl_kernels_wg1024p.hip",
+                  "paper_2408_00488_amd/csrc/csl_kernels_wg512p.hip",
                   "paper_2408_00488_amd/csrc/csl_device.hpp",
                   "paper_2408_00488_amd/csrc/csl_common.hpp"]
 TRAFFIC_FILE = "profiles/solve_kernel_batch64_hbm_traffic.txt"
@@ -240,7 +249,7 @@ def other_configs(C, WL, dev):
             sched = p.tune(f, z)
             reps = 20 if s.a.size < 100000 else 3
             ms, info = time_solve(C, p, f, z, reps)
-            bpp = BYTES_MODEL[(s.a.ndim, fp32)]
+            bpp = bytes_model(s.a.ndim, fp32, sched["block_threads"] == 1024)
             out[f"{name}_{'fp32p' if fp32 else 'fp64'}"] = {
                 "points": int(s.a.size), "ms_per_solve": ms, "iters": info["iters"],
                 "relres_true": info["relres_true"], "status": info["status_name"],
@@ -524,8 +533,8 @@ def main():
     Zcpu = [z.cpu().numpy() for z in Z]
 
     # algorithmic bytes of one launch (per-iteration model x iterations)
-    alg_bytes = sum(it * s.a.size * BYTES_MODEL[(2, True)] for it, s in zip(iters, w.systems))
-    alg_bytes_paired = sum(it * s.a.size * BYTES_MODEL_PAIRED[(2, True)]
+    alg_bytes = sum(it * s.a.size * bytes_model(2, True) for it, s in zip(iters, w.systems))
+    alg_bytes_paired = sum(it * s.a.size * bytes_model_paired(2, True)
                            for it, s in zip(iters, w.systems))
     avg_launch_s = float(np.mean(launch_ms)) * 1e-3
     achieved = alg_bytes / avg_launch_s / 1e9
@@ -620,9 +629,9 @@ def main():
                      "frac": achieved / PEAK_HBM_GBS, "traffic": measured_traffic(),
                      "kernel": "solve_kernel", "avg_launch_ms": avg_launch_s * 1e3,
                      "alg_bytes_per_launch": alg_bytes,
-                     "bytes_per_point_iter": BYTES_MODEL[(2, True)],
+                     "bytes_per_point_iter": bytes_model(2, True),
                      "paired_update_model": {
-                         "bytes_per_point_iter": BYTES_MODEL_PAIRED[(2, True)],
+                         "bytes_per_point_iter": bytes_model_paired(2, True),
                          "alg_bytes_per_launch": alg_bytes_paired,
                          "achieved": alg_bytes_paired / avg_launch_s / 1e9,
                          "frac": alg_bytes_paired / avg_launch_s / 1e9 / PEAK_HBM_GBS}},

@@ -19,7 +19,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libcsl.so")
 SOURCES = ["csl_kernels.hip", "csl_kernels_wg256h.hip", "csl_kernels_wg512.hip",
-           "csl_kernels_wg512x.hip", "csl_kernels_wg1024p.hip", "csl_runtime.hip"]
+           "csl_kernels_wg512x.hip", "csl_kernels_wg1024p.hip", "csl_kernels_wg512p.hip",
+           "csl_runtime.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

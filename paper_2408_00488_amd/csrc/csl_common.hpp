@@ -132,14 +132,17 @@ struct SysDesc {
 };
 
 constexpr int kLanczosCap = 4096;
-// Dynamic LDS of the plane-phase solver instance (the whole 160 KiB of a CU
-// less a margin for its static variables), and what a plane tile needs of it:
-// one part of the plane (FP32, padded to 128 bytes), 16 staged lines of up to
-// 256 complex points, the twiddles of both lengths.
+// Dynamic LDS of the plane-phase solver instances (the whole 160 KiB of a CU
+// less a margin for their static variables), and what a plane tile needs of
+// it: one part of the plane in the preconditioner precision (eb bytes per
+// value, padded to 128 bytes), one line buffer of 256 complex values per wave
+// (nwaves of them), the twiddles of both lengths (one table when they are
+// equal).
 constexpr int kPlaneLdsBytes = 163840 - 512;
-__host__ __device__ inline int plane_lds_bytes(int n0, int n1, int lg0, int lg1) {
-  const int pb = (n0 * n1 * 4 + 127) & ~127;
-  return pb + 16 * 256 * 8 + ((1 << lg0) / 4 + (1 << lg1) / 4) * 8;
+__host__ __device__ inline int plane_lds_bytes(int n0, int n1, int lg0, int lg1, int eb, int nwaves) {
+  const int pb = (n0 * n1 * eb + 127) & ~127;
+  const int ntw = lg0 == lg1 ? (1 << lg0) / 4 : (1 << lg0) / 4 + (1 << lg1) / 4;
+  return pb + nwaves * 256 * 2 * eb + ntw * 2 * eb;
 }
 // The FP16 split-product engine stores the sine matrix scaled by 2^8, so that
 // the low parts of its entries stay normal FP16 numbers.

@@ -31,6 +31,9 @@
 #ifndef CSL_PLANE
 #define CSL_PLANE 0
 #endif
+#ifndef CSL_PLANE_F64
+#define CSL_PLANE_F64 0
+#endif
 #ifndef CSL_WAVES_PER_EU
 #define CSL_WAVES_PER_EU (CSL_NT / 128)
 #endif
@@ -534,43 +537,45 @@ constexpr int kPlaneWaveElts = 256;   // complex FP32 values per wave buffer
 
 // Odd extension of the complex line made of real lines la and lb (lb absent:
 // zero imaginary part), n = L/2 - 1 points at stride ldp.
-__device__ __forceinline__ Cx<float> pair_ext(const float *la, const float *lb, bool hasb, int ldp,
-                                              int m, int L, bool act) {
+template <typename R>
+__device__ __forceinline__ Cx<R> pair_ext(const R *la, const R *lb, bool hasb, int ldp, int m, int L,
+                                          bool act) {
   const int N = L >> 1;
-  if (!act || m == 0 || m == N) return Cx<float>{0.f, 0.f};
+  if (!act || m == 0 || m == N) return Cx<R>{(R)0, (R)0};
   const int r = m < N ? m - 1 : L - 1 - m;
-  const float re = la[r * ldp];
-  const float im = hasb ? lb[r * ldp] : 0.f;
-  return m < N ? Cx<float>{re, im} : Cx<float>{-re, -im};
+  const R re = la[r * ldp];
+  const R im = hasb ? lb[r * ldp] : (R)0;
+  return m < N ? Cx<R>{re, im} : Cx<R>{-re, -im};
 }
 
 // Sine transform, in place, of the nlines real lines of a real plane (line l
 // at pl[l ldl + r ldp]), lines 2p and 2p + 1 as one complex line.
-__device__ __forceinline__ void plane_dst_pairs(float *pl, Cx<float> *wbuf, const Cx<float> *twl,
-                                                int nlines, int lg, int ldl, int ldp) {
+template <typename R>
+__device__ __forceinline__ void plane_dst_pairs(R *pl, Cx<R> *wbuf, const Cx<R> *twl, int nlines, int lg,
+                                                int ldl, int ldp) {
   const int L = 1 << lg, Q = L >> 2, N = L >> 1;
   const int G = 64 >> (lg - 2);   // complex lines per wave
   const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
   const int g = t >> (lg - 2), j = t & (Q - 1);
-  Cx<float> *wb = wbuf + w * kPlaneWaveElts;
+  Cx<R> *wb = wbuf + w * kPlaneWaveElts;
   const int lo = g * L;
-  const float cf = 1.0f / sqrtf((float)L);
+  const R cf = (R)1 / sqrt((R)L);
   const int npairs = (nlines + 1) >> 1;
   for (int p0 = w * G; p0 < npairs; p0 += (NT / 64) * G) {
     const int p = p0 + g;
     const bool act = p < npairs;
     const bool hasb = act && 2 * p + 1 < nlines;
-    float *la = pl + (size_t)(act ? 2 * p : 0) * ldl;
-    float *lb = la + ldl;
-    Cx<float> a[4];
+    R *la = pl + (size_t)(act ? 2 * p : 0) * ldl;
+    R *lb = la + ldl;
+    Cx<R> a[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) a[q] = pair_ext(la, lb, hasb, ldp, j + q * Q, L, act);
-    wave_fft_line<float>(a, wb, lo, j, lg, twl, true);
+    for (int q = 0; q < 4; ++q) a[q] = pair_ext<R>(la, lb, hasb, ldp, j + q * Q, L, act);
+    wave_fft_line<R>(a, wb, lo, j, lg, twl, true);
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int k = j + q * Q;
       if (act && k >= 1 && k < N) {
-        const Cx<float> v = dst_out(a[q], cf);
+        const Cx<R> v = dst_out(a[q], cf);
         la[(k - 1) * ldp] = v.x;
         if (hasb) lb[(k - 1) * ldp] = v.y;
       }
@@ -578,28 +583,30 @@ __device__ __forceinline__ void plane_dst_pairs(float *pl, Cx<float> *wbuf, cons
   }
 }
 
-// The plane tile: one part of one plane.
+// The plane tile: one part of one plane, in the preconditioner precision R
+// (FP32 in the 1024-thread instance, FP64 in the 512-thread one).
+template <typename R>
 __device__ __forceinline__ void tile_YP(const SysDesc &S, int iter, int tile, char *smem,
                                         double *red) {
-  typedef float R;
   const int n0 = S.n[0], n1 = S.n[1];
   const int rows = S.rows;
   const int c = tile >> 1, comp = tile & 1;
-  float *pl = reinterpret_cast<float *>(smem);
-  const size_t pb = ((size_t)rows * sizeof(float) + 127) & ~(size_t)127;
+  R *pl = reinterpret_cast<R *>(smem);
+  const size_t pb = ((size_t)rows * sizeof(R) + 127) & ~(size_t)127;
   Cx<R> *wbuf = reinterpret_cast<Cx<R> *>(smem + pb);
   const int lg0 = S.lg[0], lg1 = S.lg[1];
   Cx<R> *tw0 = wbuf + (NT / 64) * kPlaneWaveElts;
-  Cx<R> *tw1 = tw0 + ((1 << lg0) >> 2);
+  // one table when both axes have the same length
+  Cx<R> *tw1 = lg1 == lg0 ? tw0 : tw0 + ((1 << lg0) >> 2);
   // the line buffer's twiddle cache lies inside the plane: restage later
   if (threadIdx.x == 0) s_twkey = -1;
   load_twiddles<R>(tw0, lg0);
-  load_twiddles<R>(tw1, lg1);
+  if (lg1 != lg0) load_twiddles<R>(tw1, lg1);
   const size_t off = (size_t)comp * S.M + (size_t)c * rows;
   const int j = iter;
   if (j == 0) {
     const CSL_G double *__restrict__ v1 = reinterpret_cast<const CSL_G double *>(gbl(S.Tv[1])) + off;
-    for (int e = threadIdx.x; e < rows; e += NT) pl[e] = (float)v1[e];
+    for (int e = threadIdx.x; e < rows; e += NT) pl[e] = (R)v1[e];
   } else {
     const Ctl *C = S.ctl;
     const double g = ld_ctl(&C->gamma), go = ld_ctl(&C->gamma_old);
@@ -635,7 +642,7 @@ __device__ __forceinline__ void tile_YP(const SysDesc &S, int iter, int tile, ch
   }
   __syncthreads();
   // axis 1 forward: n0 lines of n1 points, contiguous in the plane
-  plane_dst_pairs(pl, wbuf, tw1, n0, lg1, n1, 1);
+  plane_dst_pairs<R>(pl, wbuf, tw1, n0, lg1, n1, 1);
   __syncthreads();
   // axis 0: n1 lines of n0 points at stride n1, neighbouring columns in
   // pairs; forward transform, the per-mode factor of each column's own mode
@@ -650,11 +657,26 @@ __device__ __forceinline__ void tile_YP(const SysDesc &S, int iter, int tile, ch
     const int g = t >> (lg0 - 2), jl = t & (Q - 1);
     Cx<R> *wb = wbuf + w * kPlaneWaveElts;
     const int lo = g * L;
-    const R ab = (R)S.abar_f, al = (R)S.alpha_f, be = (R)S.beta_f;
-    const CSL_G R *mu0 = gbl(S.mu_f[0]);
-    const CSL_G R *mu1 = gbl(S.mu_f[1]);
-    const R m2 = gbl(S.mu_f[2])[c];
-    const float cf0 = 1.0f / sqrtf((float)L);
+    R ab, al, be;
+    const CSL_G R *mu0;
+    const CSL_G R *mu1;
+    R m2;
+    if constexpr (sizeof(R) == 8) {
+      ab = (R)S.abar;
+      al = (R)S.alpha;
+      be = (R)S.beta;
+      mu0 = gbl(reinterpret_cast<const R *>(S.mu[0]));
+      mu1 = gbl(reinterpret_cast<const R *>(S.mu[1]));
+      m2 = gbl(reinterpret_cast<const R *>(S.mu[2]))[c];
+    } else {
+      ab = (R)S.abar_f;
+      al = (R)S.alpha_f;
+      be = (R)S.beta_f;
+      mu0 = gbl(reinterpret_cast<const R *>(S.mu_f[0]));
+      mu1 = gbl(reinterpret_cast<const R *>(S.mu_f[1]));
+      m2 = gbl(reinterpret_cast<const R *>(S.mu_f[2]))[c];
+    }
+    const R cf0 = (R)1 / sqrt((R)L);
     int md[4];
     R m0[4];
 #pragma unroll
@@ -668,14 +690,14 @@ __device__ __forceinline__ void tile_YP(const SysDesc &S, int iter, int tile, ch
       const int p = p0 + g;
       const bool act = p < np;
       const bool hasb = act && 2 * p + 1 < n1;
-      float *la = pl + (act ? 2 * p : 0);
-      float *lb = la + 1;
+      R *la = pl + (act ? 2 * p : 0);
+      R *lb = la + 1;
       const R m1a = mu1[act ? 2 * p : 0];
       const R m1b = mu1[hasb ? 2 * p + 1 : 0];
       Cx<R> a[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) a[q] = pair_ext(la, lb, hasb, n1, jl + q * Q, L, act);
-      wave_fft_line<float>(a, wb, lo, jl, lg0, tw0, true);
+      for (int q = 0; q < 4; ++q) a[q] = pair_ext<R>(la, lb, hasb, n1, jl + q * Q, L, act);
+      wave_fft_line<R>(a, wb, lo, jl, lg0, tw0, true);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         Cx<R> v = dst_out(a[q], cf0);
@@ -695,7 +717,7 @@ __device__ __forceinline__ void tile_YP(const SysDesc &S, int iter, int tile, ch
         }
         a[q] = v;
       }
-      wave_fft_line<float>(a, wb, lo, jl, lg0, tw0, true);
+      wave_fft_line<R>(a, wb, lo, jl, lg0, tw0, true);
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         const int k = jl + q * Q;
@@ -709,9 +731,9 @@ __device__ __forceinline__ void tile_YP(const SysDesc &S, int iter, int tile, ch
   }
   __syncthreads();
   // axis 1 inverse
-  plane_dst_pairs(pl, wbuf, tw1, n0, lg1, n1, 1);
+  plane_dst_pairs<R>(pl, wbuf, tw1, n0, lg1, n1, 1);
   __syncthreads();
-  CSL_G float *Tr = reinterpret_cast<CSL_G float *>(gbl(S.T)) + off;
+  CSL_G R *Tr = reinterpret_cast<CSL_G R *>(gbl(S.T)) + off;
   for (int e = threadIdx.x; e < rows; e += NT) st_nt(Tr + e, pl[e]);
   const double sg = wg_sum(gacc, red);
   if (threadIdx.x == 0) S.part[tile] = sg;
@@ -753,7 +775,12 @@ __device__ __forceinline__ void process_tile(const SysDesc &S, const IOPtr &io, 
 #endif
 #if CSL_PLANE
   if (kind == K_Y && S.plane) {
-    tile_YP(S, iter, tile, smem, red);
+    // one precision per instance (the runtime launches the one of S.prec)
+#if CSL_PLANE_F64
+    tile_YP<double>(S, iter, tile, smem, red);
+#else
+    tile_YP<float>(S, iter, tile, smem, red);
+#endif
     return;
   }
 #endif

@@ -1,11 +1,12 @@
 // Host-callable launch wrappers of the gfx950 kernels.  The device code is
-// built five times: csl::wg256 (256-thread workgroups; every kernel),
+// built six times: csl::wg256 (256-thread workgroups; every kernel),
 // csl::wg256h (the 256-thread persistent solver with the FP16 split-product
 // sine-matrix engine), csl::wg512 (512-thread workgroups; the persistent
 // solver for 2-D systems whose transforms all run on the LDS FFT),
-// csl::wg512x (the same for FFT systems of either dimension) and
-// csl::wg1024p (one 1024-thread workgroup per CU: the 3-D solver with the
-// plane phase).
+// csl::wg512x (the same for FFT systems of either dimension), csl::wg1024p
+// (one 1024-thread workgroup per CU: the 3-D solver with the plane phase,
+// FP32 preconditioner) and csl::wg512p (one 512-thread workgroup per CU: the
+// same with the FP64 preconditioner).
 #pragma once
 #include "csl_common.hpp"
 
@@ -69,6 +70,15 @@ hipError_t launch_solve(const SysDesc *dsys, const IOPtr *dio, IOPtr io0, int ns
 hipError_t solve_occupancy(size_t smem, int *blocks_per_cu);
 
 }  // namespace wg1024p
+
+namespace wg512p {
+
+hipError_t upload_twiddles(const double2 *tw64, const float2 *tw32);
+hipError_t launch_solve(const SysDesc *dsys, const IOPtr *dio, IOPtr io0, int nsys,
+                        const SolveParams &P, Glob *G, int grid, size_t smem, hipStream_t s);
+hipError_t solve_occupancy(size_t smem, int *blocks_per_cu);
+
+}  // namespace wg512p
 
 namespace wg512x {
 

@@ -67,6 +67,7 @@ csl_status ensure_twiddles(int dev) {
   HIPCHK(wg512x::upload_twiddles(t64.data(), t32.data()));
   HIPCHK(wg256h::upload_twiddles(t64.data(), t32.data()));
   HIPCHK(wg1024p::upload_twiddles(t64.data(), t32.data()));
+  HIPCHK(wg512p::upload_twiddles(t64.data(), t32.data()));
   g_tw_ready[dev] = true;
   return CSL_OK;
 }
@@ -132,23 +133,28 @@ void sine_matrix(int n, std::vector<double> &W) {
     }
 }
 
-// The persistent solver instance of a workgroup size: 1024 threads for a 3-D
-// problem's own solves with the plane phase (csl::wg1024p), 512 for systems
-// with the FFT on every axis (csl::wg512 when every system is 2-D,
+// The persistent solver instance of a workgroup size: 1024 for 3-D systems
+// with the plane phase (csl::wg1024p with the FP32 preconditioner; with the
+// FP64 one, p64, csl::wg512p, whose workgroups have 512 threads), 512 for
+// systems with the FFT on every axis (csl::wg512 when every system is 2-D,
 // csl::wg512x otherwise) or 256 (csl::wg256h when a system has an axis on the
 // FP16 split-product engine, csl::wg256 otherwise).
-hipError_t solve_launch(int wg, bool all2d, bool g16, const SysDesc *dsys, const IOPtr *dio,
+hipError_t solve_launch(int wg, bool all2d, bool g16, bool p64, const SysDesc *dsys, const IOPtr *dio,
                         IOPtr io0, int nsys, const SolveParams &P, Glob *G, int grid, size_t smem,
                         hipStream_t s) {
-  if (wg == 1024) return wg1024p::launch_solve(dsys, dio, io0, nsys, P, G, grid, smem, s);
+  if (wg == 1024)
+    return p64 ? wg512p::launch_solve(dsys, dio, io0, nsys, P, G, grid, smem, s)
+               : wg1024p::launch_solve(dsys, dio, io0, nsys, P, G, grid, smem, s);
   if (wg != 512)
     return g16 ? wg256h::launch_solve(dsys, dio, io0, nsys, P, G, grid, smem, s)
                : wg256::launch_solve(dsys, dio, io0, nsys, P, G, grid, smem, s);
   return all2d ? wg512::launch_solve(dsys, dio, io0, nsys, P, G, grid, smem, s)
                : wg512x::launch_solve(dsys, dio, io0, nsys, P, G, grid, smem, s);
 }
-hipError_t solve_occupancy_wg(int wg, bool all2d, bool g16, size_t smem, int *blocks_per_cu) {
-  if (wg == 1024) return wg1024p::solve_occupancy(smem, blocks_per_cu);
+hipError_t solve_occupancy_wg(int wg, bool all2d, bool g16, bool p64, size_t smem, int *blocks_per_cu) {
+  if (wg == 1024)
+    return p64 ? wg512p::solve_occupancy(smem, blocks_per_cu)
+               : wg1024p::solve_occupancy(smem, blocks_per_cu);
   if (wg != 512)
     return g16 ? wg256h::solve_occupancy(smem, blocks_per_cu)
                : wg256::solve_occupancy(smem, blocks_per_cu);
@@ -160,12 +166,14 @@ bool has_gemm16(const SysDesc &h) { return h.gemm[0] == 2 || h.gemm[1] == 2 || h
 // The 512-thread solver applies: the FFT on every axis.
 bool fft_everywhere(const SysDesc &h) { return !h.gemm[0] && !h.gemm[1] && !h.gemm[2]; }
 bool fft_everywhere_mask(int m) { return (m & 7) == 0; }
-// The plane phase applies: 3-D, FP32 preconditioner, the FFT on every axis,
-// lines of at most 127 points along the two leading axes and their plane
-// (with the staged lines and twiddles) inside the instance's LDS.
+// The plane phase applies: 3-D, the FFT on every axis, lines of at most 127
+// points along the two leading axes and their plane (with the per-wave line
+// buffers and the twiddles) inside the instance's LDS: 16 waves with FP32
+// values (csl::wg1024p), 8 waves with FP64 values (csl::wg512p).
 bool plane_ok(const SysDesc &h) {
-  return h.d == 3 && h.prec == 1 && fft_everywhere(h) && h.n[0] <= 127 && h.n[1] <= 127 &&
-         plane_lds_bytes(h.n[0], h.n[1], h.lg[0], h.lg[1]) <= kPlaneLdsBytes;
+  const int eb = h.prec ? 4 : 8, nw = h.prec ? 16 : 8;
+  return h.d == 3 && fft_everywhere(h) && h.n[0] <= 127 && h.n[1] <= 127 &&
+         plane_lds_bytes(h.n[0], h.n[1], h.lg[0], h.lg[1], eb, nw) <= kPlaneLdsBytes;
 }
 // Rewrite a tiling for the plane phase: block width one (Tq, Tv and T hold
 // all real parts, then all imaginary parts, each with the plane of
@@ -274,6 +282,8 @@ struct csl_batch_s {
   bool wg512_ok = false; // every problem allows the 512-thread solver
   bool all2d = true;     // every problem is 2-D (the 2-D-only 512-thread instance)
   bool plane_ok = false; // every problem allows the plane phase (block_threads 1024)
+                         // and all have the same preconditioner precision
+  bool p64 = false;      // ... the FP64 one (the 512-thread plane instance)
   bool g16 = false;      // some problem has an axis on the FP16 split-product engine
 };
 
@@ -522,7 +532,7 @@ csl_status configure_single(csl_problem p, int tile_points, int lds_bytes, int b
   if (plane) {
     if (!plane_ok(h))
       return fail(CSL_ERR_ARG, "block_threads 1024 (the plane phase) needs a 3-D problem with the "
-                               "FP32 preconditioner, the FFT on every axis and n0, n1 <= 127");
+                               "FFT on every axis and n0, n1 <= 127 (n0 n1 <= 16129 with FP64)");
     // the row phases on a 64 KiB line buffer, then the plane layout
     choose_tiles(h, p->single_te > 0 ? p->single_te : p->tile_elems, 65536, &sm);
     plane_tiling(h);
@@ -535,7 +545,7 @@ csl_status configure_single(csl_problem p, int tile_points, int lds_bytes, int b
   if (h.maxtile > p->part_cap) return fail(CSL_ERR_ARG, "chunking exceeds the partial-sum slots");
   const int wg = resolve_wg(block_threads, p->wg512_ok);
   int bpc = 0;
-  HIPCHK(solve_occupancy_wg(wg, p->h0.d == 2, has_gemm16(p->h0), sm, &bpc));
+  HIPCHK(solve_occupancy_wg(wg, p->h0.d == 2, has_gemm16(p->h0), p->h0.prec == 0, sm, &bpc));
   const int cap = std::max(1, bpc) * p->cus;
   const int tp = tile_points > 0 ? tile_points : (int)std::min<long long>(1 << 30, h.M / cap);
   set_tile_points(h, tp);
@@ -595,7 +605,8 @@ csl_status tune_engines(csl_problem p, int elig, int req, hipStream_t s, int *be
       if (r == 1) err = hipEventRecord(e0, s);   // the first solve is a warm-up
       if (err == hipSuccess) err = wg256::launch_init(p->d_desc, 1, p->glob, s);
       if (err == hipSuccess)
-        err = solve_launch(p->block_threads, h.d == 2, has_gemm16(h), p->d_desc, nullptr, io0, 1,
+        err = solve_launch(p->block_threads, h.d == 2, has_gemm16(h), h.prec == 0, p->d_desc, nullptr,
+                           io0, 1,
                            P, p->glob,
                            p->grid1,
                            p->smem, s);
@@ -656,7 +667,7 @@ csl_status configure_batch(csl_batch b, int tile_points, int lds_bytes, int bloc
   b->lds_bytes = smem <= 32768 ? 32768 : 65536;
   b->block_threads = resolve_wg(block_threads, b->wg512_ok);
   int bpc = 0;
-  HIPCHK(solve_occupancy_wg(b->block_threads, b->all2d, b->g16, smem, &bpc));
+  HIPCHK(solve_occupancy_wg(b->block_threads, b->all2d, b->g16, b->p64, smem, &bpc));
   // tiles are claimed dynamically, so a full-occupancy grid keeps every CU
   // busy whatever the mix of systems
   const int cap = std::max(1, bpc) * b->probs[0]->cus;
@@ -668,7 +679,7 @@ csl_status configure_batch(csl_batch b, int tile_points, int lds_bytes, int bloc
   if (ok) {
     ok = wg256::launch_init(b->d_desc, b->count, b->glob, cs) == hipSuccess;
     IOPtr none{nullptr, nullptr};
-    ok = ok && solve_launch(b->block_threads, b->all2d, b->g16, b->d_desc, b->d_io, none, b->count,
+    ok = ok && solve_launch(b->block_threads, b->all2d, b->g16, b->p64, b->d_desc, b->d_io, none, b->count,
                             b->params,
                             b->glob, b->grid, b->smem, cs) == hipSuccess;
     hipGraph_t g = nullptr;
@@ -1142,7 +1153,8 @@ static csl_status run_single(csl_problem p, const double2 *f, double2 *x, const 
                              hipStream_t s) {
   HIPCHK(wg256::launch_init(p->d_desc, 1, p->glob, s));
   IOPtr io0{f, x};
-  HIPCHK(solve_launch(p->block_threads, p->h.d == 2, has_gemm16(p->h), p->d_desc, nullptr, io0, 1,
+  HIPCHK(solve_launch(p->block_threads, p->h.d == 2, has_gemm16(p->h), p->h.prec == 0, p->d_desc,
+                      nullptr, io0, 1,
                       P, p->glob,
                       p->grid1, p->smem,
                       s));
@@ -1340,7 +1352,7 @@ csl_status minres_solve_noalloc(const csl_grid *grid, const double *a_nodal, dou
   // on every axis), about one tile per workgroup and phase
   const int wg = 512;
   int bpc = 0;
-  HIPCHK(solve_occupancy_wg(wg, h.d == 2, false, smem, &bpc));
+  HIPCHK(solve_occupancy_wg(wg, h.d == 2, false, false, smem, &bpc));
   const int cap = std::max(1, bpc) * sd.cus;
   set_tile_points(h, (int)std::min<long long>(1 << 30, h.M / cap));
   int mt = 1;
@@ -1350,7 +1362,7 @@ csl_status minres_solve_noalloc(const csl_grid *grid, const double *a_nodal, dou
                                     sd.wall_khz);
   HIPCHK(wg256::launch_init(d_desc, 1, glob, s));
   IOPtr io0{(const double2 *)f, (double2 *)z};
-  HIPCHK(solve_launch(wg, h.d == 2, false, d_desc, nullptr, io0, 1, P, glob, std::max(1, std::min(mt, cap)),
+  HIPCHK(solve_launch(wg, h.d == 2, false, false, d_desc, nullptr, io0, 1, P, glob, std::max(1, std::min(mt, cap)),
                       smem, s));
   if (!info) return CSL_OK;
   DevInfo di;
@@ -1600,17 +1612,19 @@ csl_status batch_create(const csl_problem *problems, int count, const csl_batch_
   b->wg512_ok = true;
   b->all2d = true;
   b->plane_ok = true;
+  b->p64 = problems[0]->h0.prec == 0;
   for (int i = 0; i < count; ++i) {
     b->wg512_ok = b->wg512_ok && problems[i]->wg512_ok;
     b->all2d = b->all2d && problems[i]->h.d == 2;
     b->g16 = b->g16 || has_gemm16(problems[i]->h);
-    b->plane_ok = b->plane_ok && plane_ok(problems[i]->h0);
+    b->plane_ok = b->plane_ok && plane_ok(problems[i]->h0) && (problems[i]->h0.prec == 0) == b->p64;
   }
   if (o.block_threads == 512 && !b->wg512_ok)
     return cleanup(CSL_ERR_ARG, "block_threads 512 needs the FFT engine on every axis of every problem");
   if (o.block_threads == 1024 && !b->plane_ok)
-    return cleanup(CSL_ERR_ARG, "block_threads 1024 (the plane phase) needs 3-D problems with the "
-                                "FP32 preconditioner, the FFT on every axis and n0, n1 <= 127");
+    return cleanup(CSL_ERR_ARG, "block_threads 1024 (the plane phase) needs 3-D problems with one "
+                                "preconditioner precision, the FFT on every axis and n0, n1 <= 127 "
+                                "(n0 n1 <= 16129 with FP64)");
   {
     // the adjoint solves read conj(G) from each problem's gtmp and write
     // conj(y) to its ytmp
@@ -1663,7 +1677,7 @@ csl_status batch_solve(csl_batch b, const double *const *f, double *const *z,
   } else {
     HIPCHK(wg256::launch_init(b->d_desc, b->count, b->glob, s));
     IOPtr none{nullptr, nullptr};
-    HIPCHK(solve_launch(b->block_threads, b->all2d, b->g16, b->d_desc, b->d_io, none, b->count, b->params,
+    HIPCHK(solve_launch(b->block_threads, b->all2d, b->g16, b->p64, b->d_desc, b->d_io, none, b->count, b->params,
                         b->glob, b->grid, b->smem, s));
   }
   if (!infos) return CSL_OK;
@@ -1721,7 +1735,7 @@ csl_status batch_adjoint(csl_batch b, const double *const *z, const double *cons
   }
   HIPCHK(wg256::launch_init(b->d_desc, b->count, b->glob, s));
   IOPtr none{nullptr, nullptr};
-  HIPCHK(solve_launch(b->block_threads, b->all2d, b->g16, b->d_desc, b->d_io_adj, none, b->count, P,
+  HIPCHK(solve_launch(b->block_threads, b->all2d, b->g16, b->p64, b->d_desc, b->d_io_adj, none, b->count, P,
                       b->glob, b->grid, b->smem, s));
   // gradients system by system, in order: ga accumulates the systems'
   // coefficient gradients in a fixed order

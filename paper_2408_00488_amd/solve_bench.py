@@ -5,9 +5,9 @@ kernel traces and HBM counters on one system at a time.
 
 Algorithmic bytes per grid point and MINRES iteration: stencil 40 + Lanczos
 recurrence and w / x updates 160 + 4 s bytes per sine-transform pass (s = 8
-FP64, 4 FP32 preconditioner): 2-D FP64 296 and FP32 248 (3 passes); 3-D
-FP64 360 (5 passes) and FP32 248 (3 passes: the two leading axes' plane
-transformed in one pass).
+FP64, 4 FP32 preconditioner): 3 passes in 2-D and in 3-D with the plane phase
+(the two leading axes' plane transformed in one pass: 296 FP64, 248 FP32), 5
+in 3-D otherwise (360 FP64, 280 FP32).
 
   python -m paper_2408_00488_amd.solve_bench [--cases c3,c3_fp32] [--reps 5] [--dst fft]
                                              [--tile-points P --lds L --threads T]
@@ -17,7 +17,10 @@ from __future__ import annotations
 import argparse
 import json
 
-BYTES = {(2, False): 296.0, (2, True): 248.0, (3, False): 360.0, (3, True): 248.0}
+
+
+def bytes_per_point_iter(d: int, fp32: bool, plane: bool) -> float:
+    return 200.0 + (3 if d == 2 or plane else 5) * 4.0 * (4 if fp32 else 8)
 
 
 def main():
@@ -58,7 +61,7 @@ def main():
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / args.reps
-        bpp = BYTES[(s.a.ndim, fp32)]
+        bpp = bytes_per_point_iter(s.a.ndim, fp32, p.schedule["block_threads"] == 1024)
         alg = info["iters"] * s.a.size * bpp
         print(json.dumps({"case": case, "points": int(s.a.size), "iters": info["iters"],
                           "relres_true": info["relres_true"], "ms_per_solve": round(ms, 4),
