@@ -178,12 +178,13 @@ csl_status problem_info(csl_problem p, double *abar, double *a_min,
  * = 64 KiB) and the workgroup size of the persistent solver, block_threads:
  * 0 = 512 where allowed, else 256; 256; 512, which is allowed for problems
  * whose sine transforms all run on the FFT (CSL_ERR_ARG otherwise); or 1024,
- * the plane phase, for 3-D problems with the FP32 preconditioner, the FFT
- * on every axis and n0, n1 <= 127 (CSL_ERR_ARG otherwise): one workgroup
- * per CU holds the real or the imaginary part of a plane of axes 0 and 1
- * in LDS and applies the transforms of P^{-1} along both of them (Section
- * 2.3) in one phase; tile_points and lds_bytes then apply to the
- * contiguous-axis phases;
+ * the plane phase, for 3-D problems with the FFT on every axis and n0, n1
+ * <= 127 (CSL_ERR_ARG otherwise): one workgroup per CU holds the real or
+ * the imaginary part of a plane of axes 0 and 1 in LDS and applies the
+ * transforms of P^{-1} along both of them (Section 2.3) in one phase; its
+ * workgroups have 1024 threads with the FP32 preconditioner and 512 with
+ * the FP64 one, whose FP64 plane leaves LDS for eight waves' line buffers
+ * only; tile_points and lds_bytes then apply to the contiguous-axis phases;
  * tile_elems, the LDS elements of a chunk (0 = the creation-time tiling;
  * chunks smaller than that are accepted while every tile keeps a partial-sum
  * slot, on grids of at most 65536 points down to 512 elements; CSL_ERR_ARG
@@ -297,8 +298,9 @@ typedef struct csl_batch_opts {
                                every axis), else 256; 256; 512 (CSL_ERR_ARG
                                unless every problem allows it); 1024, the
                                plane phase (CSL_ERR_ARG unless every problem
-                               is 3-D with the FP32 preconditioner, the FFT
-                               on every axis and n0, n1 <= 127)            */
+                               is 3-D with the FFT on every axis and n0, n1
+                               <= 127, all with one preconditioner
+                               precision)                                  */
 } csl_batch_opts;
 
 /* Schedule chosen by batch_tune or problem_tune, or in use

@@ -510,13 +510,15 @@ __device__ __forceinline__ void tile_PR(const SysDesc &S, const IOPtr &io, int t
 
 #if CSL_PLANE
 // ---------------------------------------------------------------------------
-// Plane phase (3-D, FP32 preconditioner, FFT on axes 0 and 1): tile 2c +
-// comp is the real (comp 0) or the imaginary (comp 1) part of the plane of
-// contiguous-axis index c, a real FP32 plane held in LDS.  Tq, Tv and T hold
+// Plane phase (3-D, FFT on axes 0 and 1): tile 2c + comp is the real (comp
+// 0) or the imaginary (comp 1) part of the plane of contiguous-axis index c,
+// a real plane held in LDS in the preconditioner precision (FP32 here on
+// 1024 threads, FP64 on 512: an FP64 plane of 127 x 127 leaves LDS for the
+// line buffers of eight waves only).  Tq, Tv and T hold
 // all real parts, then all imaginary parts, each with plane c contiguous
 // (block width one).  In one pass over it:
 //   Tv_{j+1} = Tq - (delta_j/gamma_j) Tv_j - (gamma_j/gamma_{j-1}) Tv_{j-1}
-//     (FP64, stored; Tv_1 at iteration 0), rounded to FP32 into the plane;
+//     (FP64, stored; Tv_1 at iteration 0), rounded into the plane;
 //   the forward transforms of the axis-1 lines, then of the axis-0 lines
 //     with the per-mode factor and the partial of gamma_{j+1}^2, their
 //     inverses, then the inverses of the axis-1 lines;
@@ -526,14 +528,15 @@ __device__ __forceinline__ void tile_PR(const SysDesc &S, const IOPtr &io, int t
 // (2 n2 of them).  Inside a tile two real lines make one complex line (the
 // first its real part, the second its imaginary part); the transformed
 // complex line holds their two results the same way.  The values are those
-// of the three strided phases (K_Y1, K_Y, K_Y1I) with their FP32
-// intermediate kept in LDS instead of T.
+// of the three strided phases (K_Y1, K_Y, K_Y1I) with their intermediate
+// kept in LDS instead of T.
 //
 // Each wave transforms whole lines on its own (wave_fft_line): a wave holds
 // 256/L complex lines of the odd extension and exchanges values between
-// stages through its own 2 KiB of LDS with no workgroup barrier.
+// stages through its own 2 KiB (FP64: 4 KiB) of LDS with no workgroup
+// barrier.
 // ---------------------------------------------------------------------------
-constexpr int kPlaneWaveElts = 256;   // complex FP32 values per wave buffer
+constexpr int kPlaneWaveElts = 256;   // complex values per wave buffer
 
 // Odd extension of the complex line made of real lines la and lb (lb absent:
 // zero imaginary part), n = L/2 - 1 points at stride ldp.
