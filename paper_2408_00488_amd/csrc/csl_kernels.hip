@@ -1610,7 +1610,13 @@ __global__ __launch_bounds__(NT) void step_transform_kernel(const double2 *__res
   const int L = 1 << lg;
   const int lgp = ilog2i(MAXE) - lg;   // log2 of the points per workgroup
   const int P = 1 << lgp;
-  const long long p0 = (long long)blockIdx.x * P;
+  // block of points by XCD (xcd_tile): a step's run of P points rarely starts
+  // on a 128-byte line (M is odd), so neighbouring blocks share a line at
+  // every step; dealt by XCD, the two blocks run on one XCD one after the
+  // other, the shared line is fetched once into its L2, and the outputs use
+  // plain (write-back) stores, so that the two halves of a shared line meet
+  // in that L2 and leave it as one line
+  const long long p0 = (long long)xcd_tile((int)blockIdx.x, (int)gridDim.x) * P;
   const CSL_G double2 *__restrict__ X = gbl(x);
   CSL_G double2 *__restrict__ Y = gbl(y);
   load_twiddles<double>(twl, lg);
@@ -1648,9 +1654,9 @@ __global__ __launch_bounds__(NT) void step_transform_kernel(const double2 *__res
       const Cx<double> v = buf[pl * L + k];
       if (inverse) {
         const double g = exp(-ln_alpha_l * k) / L;
-        st_nt(Y + (long long)k * M + p, v.x * g, -v.y * g);
+        *(CSL_G nt_d2 *)(Y + (long long)k * M + p) = nt_d2{v.x * g, -v.y * g};
       } else {
-        st_nt(Y + (long long)k * M + p, v.x, v.y);
+        *(CSL_G nt_d2 *)(Y + (long long)k * M + p) = nt_d2{v.x, v.y};
       }
     }
   }
