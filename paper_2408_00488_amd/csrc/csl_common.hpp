@@ -136,12 +136,14 @@ constexpr int kLanczosCap = 4096;
 // less a margin for their static variables), and what a plane tile needs of
 // it: one part of the plane in the preconditioner precision (eb bytes per
 // value, padded to 128 bytes), one line buffer of 256 complex values per wave
-// (nwaves of them), the twiddles of both lengths (one table when they are
-// equal).
+// (nwaves of them), the twiddles of both FFT lengths (one table when they
+// are equal; the FFTs have 2 (n + 1) points in FP32, n + 1 in FP64).
 constexpr int kPlaneLdsBytes = 163840 - 512;
 __host__ __device__ inline int plane_lds_bytes(int n0, int n1, int lg0, int lg1, int eb, int nwaves) {
   const int pb = (n0 * n1 * eb + 127) & ~127;
-  const int ntw = lg0 == lg1 ? (1 << lg0) / 4 : (1 << lg0) / 4 + (1 << lg1) / 4;
+  const int h = eb == 8 ? 1 : 0;
+  const int t0 = (1 << (lg0 - h)) / 4, t1 = (1 << (lg1 - h)) / 4;
+  const int ntw = lg0 == lg1 ? t0 : t0 + t1;
   return pb + nwaves * 256 * 2 * eb + ntw * 2 * eb;
 }
 // The FP16 split-product engine stores the sine matrix scaled by 2^8, so that

@@ -586,6 +586,123 @@ __device__ __forceinline__ void plane_dst_pairs(R *pl, Cx<R> *wbuf, const Cx<R> 
   }
 }
 
+// FP64 plane: each sine transform of n = N - 1 points runs as a complex FFT
+// of N points instead of the 2N points of the odd extension.  With
+// S_k = sum_j x_j sin(pi j k / N) and the FFT Y of
+//   y_j = sin(pi j / N) (x_j + x_{N-j}) + (x_j - x_{N-j}) / 2   (y_0 = 0),
+// Y_m = (S_{2m+1} - S_{2m-1}) - i S_{2m}, and Y_{N-m} the same with +i; so
+//   S_{2m}   = i (Y_m - Y_{N-m}) / 2,
+//   S_{2m+1} = S_{2m-1} + (Y_m + Y_{N-m}) / 2,   S_1 = Y_0 / 2,
+// which holds for complex x as well (every step is linear with real
+// coefficients apart from the factor i).  The odd outputs are a running sum
+// over m; in FP64 its rounding stays at the level of the FFT's (a few units
+// in the last place over 64 terms), while in FP32 it would not, so the FP32
+// plane keeps the odd extension.  A line takes Q = N/4 lanes of the wave,
+// lane j holding inputs and FFT outputs j + q Q, and after the combination
+// the four orthonormal outputs X_{4j} .. X_{4j+3} (X_k = sqrt(2/N) S_k).
+
+// sin(pi i / N) for the lane's inputs i = j + q Q, from the FP64 twiddle
+// table (-Im exp(-2 pi i m / TWN) at m = i TWN / (2N))
+__device__ __forceinline__ void half_sines(double (&sn)[4], int j, int lgN) {
+  const CSL_G Cx<double> *tw = gbl(twiddles<double>());
+  const int Q = (1 << lgN) >> 2, step = TWN >> (lgN + 1);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) sn[q] = -tw[(j + q * Q) * step].y;
+}
+
+// y_i of the complex line made of real lines la and lb (lb absent: zero
+// imaginary part), x_i at row i - 1 with stride ldp
+__device__ __forceinline__ Cx<double> half_in(const double *la, const double *lb, bool hasb, int ldp,
+                                              int i, int N, bool act, double sn) {
+  if (!act || i == 0) return Cx<double>{0.0, 0.0};
+  const int r = i - 1, rr = N - 1 - i;
+  const double pa = la[r * ldp], qa = la[rr * ldp];
+  const double pb = hasb ? lb[r * ldp] : 0.0, qb = hasb ? lb[rr * ldp] : 0.0;
+  return Cx<double>{sn * (pa + qa) + 0.5 * (pa - qa), sn * (pb + qb) + 0.5 * (pb - qb)};
+}
+
+// The same from a line held in natural order in the wave buffer (x_i at
+// wb[lo + i], i = 1 .. N - 1)
+__device__ __forceinline__ Cx<double> half_in_buf(const Cx<double> *wb, int lo, int i, int N, double sn) {
+  if (i == 0) return Cx<double>{0.0, 0.0};
+  const Cx<double> p = wb[lo + i], q = wb[lo + N - i];
+  return Cx<double>{sn * (p.x + q.x) + 0.5 * (p.x - q.x), sn * (p.y + q.y) + 0.5 * (p.y - q.y)};
+}
+
+// From the FFT outputs (a[q] = Y_{j + q Q}) to the orthonormal outputs
+// x[u] = X_{4j+u} (x[0] is no output for j = 0): the outputs pass through
+// the wave buffer to meet Y_{N-m}, and the running sum of the odd outputs is
+// a scan over the Q lanes of the line.
+__device__ __forceinline__ void half_out(const Cx<double> (&a)[4], Cx<double> *wb, int lo, int j, int lgN,
+                                         double cf, Cx<double> (&x)[4]) {
+  const int N = 1 << lgN, Q = N >> 2;
+  wave_lds_sync();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) wb[lo + j + q * Q] = a[q];
+  wave_lds_sync();
+  const Cx<double> ya = wb[lo + 2 * j], yb = wb[lo + 2 * j + 1];
+  const Cx<double> za = wb[lo + ((N - 2 * j) & (N - 1))], zb = wb[lo + N - 2 * j - 1];
+  // (Y_m + Y_{N-m}) / 2 and i (Y_m - Y_{N-m}) / 2 for m = 2j, 2j + 1, times 2 cf
+  const Cx<double> ba = j == 0 ? Cx<double>{cf * ya.x, cf * ya.y}
+                               : Cx<double>{cf * (ya.x + za.x), cf * (ya.y + za.y)};
+  const Cx<double> bb = {cf * (yb.x + zb.x), cf * (yb.y + zb.y)};
+  const Cx<double> ea = {-cf * (ya.y - za.y), cf * (ya.x - za.x)};
+  const Cx<double> eb = {-cf * (yb.y - zb.y), cf * (yb.x - zb.x)};
+  const Cx<double> c = {ba.x + bb.x, ba.y + bb.y};
+  // inclusive scan of c over the line's lanes
+  Cx<double> in = c;
+  for (int d = 1; d < Q; d <<= 1) {
+    const double ux = __shfl_up(in.x, (unsigned)d, Q), uy = __shfl_up(in.y, (unsigned)d, Q);
+    if (j >= d) {
+      in.x += ux;
+      in.y += uy;
+    }
+  }
+  const Cx<double> e = {in.x - c.x, in.y - c.y};   // sum over the lanes before this one
+  x[0] = ea;
+  x[1] = Cx<double>{e.x + ba.x, e.y + ba.y};
+  x[2] = eb;
+  x[3] = in;
+}
+
+// Sine transform, in place, of the nlines real FP64 lines of a plane (line l
+// at pl[l ldl + r ldp]) through FFTs of N = 2^lgN points, lines 2p and 2p + 1
+// as one complex line.
+__device__ __forceinline__ void plane_dst_pairs_half(double *pl, Cx<double> *wbuf, const Cx<double> *twl,
+                                                     int nlines, int lgN, int ldl, int ldp) {
+  const int N = 1 << lgN, Q = N >> 2;
+  const int G = 64 >> (lgN - 2);   // complex lines per wave
+  const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
+  const int g = t >> (lgN - 2), j = t & (Q - 1);
+  Cx<double> *wb = wbuf + w * kPlaneWaveElts;
+  const int lo = g * N;
+  const double cf = 1.0 / sqrt((double)(2 * N));
+  double sn[4];
+  half_sines(sn, j, lgN);
+  const int npairs = (nlines + 1) >> 1;
+  for (int p0 = w * G; p0 < npairs; p0 += (NT / 64) * G) {
+    const int p = p0 + g;
+    const bool act = p < npairs;
+    const bool hasb = act && 2 * p + 1 < nlines;
+    double *la = pl + (size_t)(act ? 2 * p : 0) * ldl;
+    double *lb = la + ldl;
+    Cx<double> a[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) a[q] = half_in(la, lb, hasb, ldp, j + q * Q, N, act, sn[q]);
+    wave_fft_line<double>(a, wb, lo, j, lgN, twl, true);
+    Cx<double> x[4];
+    half_out(a, wb, lo, j, lgN, cf, x);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = 4 * j + u;
+      if (act && k >= 1) {
+        la[(k - 1) * ldp] = x[u].x;
+        if (hasb) lb[(k - 1) * ldp] = x[u].y;
+      }
+    }
+  }
+}
+
 // The plane tile: one part of one plane, in the preconditioner precision R
 // (FP32 in the 1024-thread instance, FP64 in the 512-thread one).
 template <typename R>
@@ -597,7 +714,9 @@ __device__ __forceinline__ void tile_YP(const SysDesc &S, int iter, int tile, ch
   R *pl = reinterpret_cast<R *>(smem);
   const size_t pb = ((size_t)rows * sizeof(R) + 127) & ~(size_t)127;
   Cx<R> *wbuf = reinterpret_cast<Cx<R> *>(smem + pb);
-  const int lg0 = S.lg[0], lg1 = S.lg[1];
+  // FFT lengths: the odd extension (2 (n + 1)) in FP32, n + 1 in FP64
+  constexpr bool kHalf = sizeof(R) == 8;
+  const int lg0 = S.lg[0] - (kHalf ? 1 : 0), lg1 = S.lg[1] - (kHalf ? 1 : 0);
   Cx<R> *tw0 = wbuf + (NT / 64) * kPlaneWaveElts;
   // one table when both axes have the same length
   Cx<R> *tw1 = lg1 == lg0 ? tw0 : tw0 + ((1 << lg0) >> 2);
@@ -645,7 +764,8 @@ __device__ __forceinline__ void tile_YP(const SysDesc &S, int iter, int tile, ch
   }
   __syncthreads();
   // axis 1 forward: n0 lines of n1 points, contiguous in the plane
-  plane_dst_pairs<R>(pl, wbuf, tw1, n0, lg1, n1, 1);
+  if constexpr (kHalf) plane_dst_pairs_half(pl, wbuf, tw1, n0, lg1, n1, 1);
+  else plane_dst_pairs<R>(pl, wbuf, tw1, n0, lg1, n1, 1);
   __syncthreads();
   // axis 0: n1 lines of n0 points at stride n1, neighbouring columns in
   // pairs; forward transform, the per-mode factor of each column's own mode
@@ -653,32 +773,89 @@ __device__ __forceinline__ void tile_YP(const SysDesc &S, int iter, int tile, ch
   // in registers as the inverse's input (the factor of mode k applied to
   // output k and, by the odd symmetry, to output L - k)
   double gacc = 0.0;
-  {
+  if constexpr (kHalf) {
+    // FP64: forward transform of a column pair, the factor of each column's
+    // mode with the partial of gamma^2 on the lane's four modes 4 jl .. 4 jl
+    // + 3, the scaled modes back through the wave buffer in natural order as
+    // the inverse's input, the inverse
+    const int N = 1 << lg0, Q = N >> 2;
+    const int G = 64 >> (lg0 - 2);
+    const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
+    const int g = t >> (lg0 - 2), jl = t & (Q - 1);
+    Cx<double> *wb = reinterpret_cast<Cx<double> *>(wbuf) + w * kPlaneWaveElts;
+    const int lo = g * N;
+    const double ab = S.abar, al = S.alpha, be = S.beta;
+    const CSL_G double *mu0 = gbl(S.mu[0]);
+    const CSL_G double *mu1 = gbl(S.mu[1]);
+    const double m2 = gbl(S.mu[2])[c];
+    const double cf = 1.0 / sqrt((double)(2 * N));
+    const Cx<double> *twl = reinterpret_cast<const Cx<double> *>(tw0);
+    double sn[4], m0[4];
+    half_sines(sn, jl, lg0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) m0[u] = 4 * jl + u >= 1 ? mu0[4 * jl + u - 1] : 0.0;
+    double *pd = reinterpret_cast<double *>(pl);
+    const int np = (n1 + 1) >> 1;
+    for (int p0 = w * G; p0 < np; p0 += (NT / 64) * G) {
+      const int p = p0 + g;
+      const bool act = p < np;
+      const bool hasb = act && 2 * p + 1 < n1;
+      double *la = pd + (act ? 2 * p : 0);
+      double *lb = la + 1;
+      const double m1a = mu1[act ? 2 * p : 0];
+      const double m1b = mu1[hasb ? 2 * p + 1 : 0];
+      Cx<double> a[4], x[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[q] = half_in(la, lb, hasb, n1, jl + q * Q, N, act, sn[q]);
+      wave_fft_line<double>(a, wb, lo, jl, lg0, twl, true);
+      half_out(a, wb, lo, jl, lg0, cf, x);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = 4 * jl + u;
+        if (k >= 1) {
+          const double sha = ab * ((m0[u] + m1a) + m2) + al;
+          const double shb = ab * ((m0[u] + m1b) + m2) + al;
+          const double sa = rsqrt(sha * sha + be * be);
+          const double sb = rsqrt(shb * shb + be * be);
+          if (act) {
+            gacc += sa * (x[u].x * x[u].x);
+            if (hasb) gacc += sb * (x[u].y * x[u].y);
+          }
+          x[u].x *= sa;
+          x[u].y *= sb;
+        } else {
+          x[u] = Cx<double>{0.0, 0.0};
+        }
+      }
+      // the scaled modes in natural order, then the inverse's input
+      wave_lds_sync();
+#pragma unroll
+      for (int u = 0; u < 4; ++u) wb[lo + 4 * jl + u] = x[u];
+      wave_lds_sync();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[q] = half_in_buf(wb, lo, jl + q * Q, N, sn[q]);
+      wave_fft_line<double>(a, wb, lo, jl, lg0, twl, true);
+      half_out(a, wb, lo, jl, lg0, cf, x);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = 4 * jl + u;
+        if (act && k >= 1) {
+          la[(k - 1) * n1] = x[u].x;
+          if (hasb) lb[(k - 1) * n1] = x[u].y;
+        }
+      }
+    }
+  } else {
     const int L = 1 << lg0, Q = L >> 2, N = L >> 1;
     const int G = 64 >> (lg0 - 2);
     const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
     const int g = t >> (lg0 - 2), jl = t & (Q - 1);
     Cx<R> *wb = wbuf + w * kPlaneWaveElts;
     const int lo = g * L;
-    R ab, al, be;
-    const CSL_G R *mu0;
-    const CSL_G R *mu1;
-    R m2;
-    if constexpr (sizeof(R) == 8) {
-      ab = (R)S.abar;
-      al = (R)S.alpha;
-      be = (R)S.beta;
-      mu0 = gbl(reinterpret_cast<const R *>(S.mu[0]));
-      mu1 = gbl(reinterpret_cast<const R *>(S.mu[1]));
-      m2 = gbl(reinterpret_cast<const R *>(S.mu[2]))[c];
-    } else {
-      ab = (R)S.abar_f;
-      al = (R)S.alpha_f;
-      be = (R)S.beta_f;
-      mu0 = gbl(reinterpret_cast<const R *>(S.mu_f[0]));
-      mu1 = gbl(reinterpret_cast<const R *>(S.mu_f[1]));
-      m2 = gbl(reinterpret_cast<const R *>(S.mu_f[2]))[c];
-    }
+    const R ab = (R)S.abar_f, al = (R)S.alpha_f, be = (R)S.beta_f;
+    const CSL_G R *mu0 = gbl(reinterpret_cast<const R *>(S.mu_f[0]));
+    const CSL_G R *mu1 = gbl(reinterpret_cast<const R *>(S.mu_f[1]));
+    const R m2 = gbl(reinterpret_cast<const R *>(S.mu_f[2]))[c];
     const R cf0 = (R)1 / sqrt((R)L);
     int md[4];
     R m0[4];
@@ -734,7 +911,8 @@ __device__ __forceinline__ void tile_YP(const SysDesc &S, int iter, int tile, ch
   }
   __syncthreads();
   // axis 1 inverse
-  plane_dst_pairs<R>(pl, wbuf, tw1, n0, lg1, n1, 1);
+  if constexpr (kHalf) plane_dst_pairs_half(pl, wbuf, tw1, n0, lg1, n1, 1);
+  else plane_dst_pairs<R>(pl, wbuf, tw1, n0, lg1, n1, 1);
   __syncthreads();
   CSL_G R *Tr = reinterpret_cast<CSL_G R *>(gbl(S.T)) + off;
   for (int e = threadIdx.x; e < rows; e += NT) st_nt(Tr + e, pl[e]);
