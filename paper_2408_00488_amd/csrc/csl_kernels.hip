@@ -703,6 +703,88 @@ __device__ __forceinline__ void plane_dst_pairs_half(double *pl, Cx<double> *wbu
   }
 }
 
+// Phase X of a plane solve after its first iteration, with rows of n2 = N - 1
+// <= 127 points: every row is formed and transformed by one wave on its own
+// (G = 256 / N rows a wave, the FP64 transform of N points above), so the
+// stencil loads of some waves run under the transforms of others; the
+// round's outputs pass through the wave buffers to be stored row-fastest in
+// the plane layout.  (Staging a round's rows of zhat by the LDS DMA, as
+// tile_X does, changed its time by less than 0.5%.)  Same values as tile_X
+// up to the transform's rounding.
+template <int LDSB>
+__device__ __forceinline__ void tile_XW(const SysDesc &S, int iter, int tile, char *smem, double *red) {
+  constexpr int W = NT / 64;
+  const int n2 = S.n[2], N = n2 + 1, lgN = S.lg[2] - 1, Q = N >> 2;
+  const int G = 64 >> (lgN - 2);
+  const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
+  const int g = t >> (lgN - 2), j = t & (Q - 1);
+  Cx<double> *wbase = reinterpret_cast<Cx<double> *>(smem);
+  Cx<double> *wb = wbase + w * kPlaneWaveElts;
+  Cx<double> *twl = reinterpret_cast<Cx<double> *>(smem + LDSB);
+  load_twiddles_cached<double>(twl, lgN);
+  const int lo = g * N;
+  const double cf = 1.0 / sqrt((double)(2 * N));
+  double sn[4];
+  half_sines(sn, j, lgN);
+  const CSL_G double2 *__restrict__ zj = gbl(S.Z[iter & 1]);
+  const double al = S.alpha, be = S.beta;
+  CSL_G double *__restrict__ od = reinterpret_cast<CSL_G double *>(gbl(S.Tq));
+  const int M = S.M, rows = S.rows;
+  const int r_begin = tile * S.cpt[K_X] * S.lpt_x;
+  const int r_end = min(rows, (tile + 1) * S.cpt[K_X] * S.lpt_x);
+  double acc = 0.0;
+  for (int rb = r_begin; rb < r_end; rb += G * W) {
+    const int row = rb + w * G + g;
+    const bool act = row < r_end;
+    Cx<double> x[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = j + q * Q;
+      x[q] = Cx<double>{0.0, 0.0};
+      if (act && i >= 1) {
+        int idx[3];
+        row_index<3>(S, row, i - 1, idx);
+        const int p = row * n2 + i - 1;
+        const StencilIn<3> in = stencil_load<3>(S, zj, p, idx);
+        const double2 kz = stencil_apply<3>(S, in);
+        const double2 zz = in.c;
+        const double qx = kz.x + al * zz.x + be * zz.y;
+        const double qy = -(kz.y + al * zz.y - be * zz.x);
+        acc += zz.x * qx + zz.y * qy;
+        x[q] = Cx<double>{qx, qy};
+      }
+    }
+    // the line in natural order, then its combined input
+#pragma unroll
+    for (int q = 0; q < 4; ++q) wb[lo + j + q * Q] = x[q];
+    wave_lds_sync();
+    Cx<double> a[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) a[q] = half_in_buf(wb, lo, j + q * Q, N, sn[q]);
+    wave_fft_line<double>(a, wb, lo, j, lgN, twl, true);
+    half_out(a, wb, lo, j, lgN, cf, x);
+    wave_lds_sync();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = 4 * j + u;
+      if (k >= 1) wb[g * n2 + k - 1] = x[u];
+    }
+    __syncthreads();
+    // rows fastest: for each output k the round's rows are consecutive
+    const int R = min(G * W, r_end - rb);
+    for (int e = threadIdx.x; e < R * n2; e += NT) {
+      const int k = e / R, rr = e - k * R;
+      const Cx<double> v = wbase[(rr / G) * kPlaneWaveElts + (rr % G) * n2 + k];
+      const int q = k * rows + rb + rr;
+      st_nt(od + q, v.x);
+      st_nt(od + M + q, v.y);
+    }
+    __syncthreads();
+  }
+  const double s = wg_sum(acc, red);
+  if (threadIdx.x == 0) S.part[tile] = s;
+}
+
 // The plane tile: one part of one plane, in the preconditioner precision R
 // (FP32 in the 1024-thread instance, FP64 in the 512-thread one).
 template <typename R>
@@ -955,6 +1037,10 @@ __device__ __forceinline__ void process_tile(const SysDesc &S, const IOPtr &io, 
   }
 #endif
 #if CSL_PLANE
+  if (kind == K_X && S.plane && iter > 0 && S.lg[2] <= 8) {
+    tile_XW<LDSB>(S, iter, tile, smem, red);
+    return;
+  }
   if (kind == K_Y && S.plane) {
     // one precision per instance (the runtime launches the one of S.prec)
 #if CSL_PLANE_F64
