@@ -785,6 +785,159 @@ __device__ __forceinline__ void tile_XW(const SysDesc &S, int iter, int tile, ch
   if (threadIdx.x == 0) S.part[tile] = s;
 }
 
+// Phase Z of a plane solve with rows of n2 = N - 1 <= 127 points, per wave as
+// tile_XW: a round's rows of T' (plane layout) are read rows-fastest into LDS,
+// then every wave transforms its rows (FP32: the odd extension, one row a
+// wave; FP64: FFTs of N points, two rows a wave) and applies the step's
+// update to its outputs itself, so the update's loads and stores of some
+// waves run under the transforms of others.  Same values as tile_Z up to the
+// transform's rounding; the flush of a deferred step (no transform) is
+// tile_Z's.
+template <typename R, int LDSB>
+__device__ __forceinline__ void tile_ZW(const SysDesc &S, const IOPtr &io, int iter, int tile, char *smem) {
+  constexpr int W = NT / 64;
+  constexpr bool kHalf = sizeof(R) == 8;
+  const Ctl *C = S.ctl;
+  const int j = iter;
+  const int mode = j == 0 ? ZM_DEFER : ld_ctl(&C->zmode);
+  if (mode == ZM_FLUSH) {
+    tile_Z<R, 3, LDSB, FftEng<R, LDSB>>(S, io, iter, tile, smem);
+    return;
+  }
+  const int n2 = S.n[2], N = n2 + 1;
+  const int lgF = kHalf ? S.lg[2] - 1 : S.lg[2];   // FFT of N (FP64) or 2N (FP32) points
+  const int F = 1 << lgF, Q = F >> 2;
+  const int G = 64 >> (lgF - 2);
+  const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
+  const int g = t >> (lgF - 2), jl = t & (Q - 1);
+  Cx<R> *wb = reinterpret_cast<Cx<R> *>(smem) + w * kPlaneWaveElts;
+  // the round's rows of T', row-major, after the wave buffers
+  Cx<R> *tin = reinterpret_cast<Cx<R> *>(smem) + W * kPlaneWaveElts;
+  Cx<R> *twl = reinterpret_cast<Cx<R> *>(smem + LDSB);
+  load_twiddles_cached<R>(twl, lgF);
+  const int lo = g * F;
+  const R cf = (R)1 / sqrt((R)(kHalf ? 2 * N : F));
+  double sn[4];
+  if constexpr (kHalf) half_sines(sn, jl, lgF);
+  const CSL_G R *__restrict__ Tr = reinterpret_cast<const CSL_G R *>(gbl(S.T));
+  const int M = S.M, rows = S.rows;
+  const int r_begin = tile * S.cpt[K_Z] * S.lpt_z;
+  const int r_end = min(rows, (tile + 1) * S.cpt[K_Z] * S.lpt_z);
+  const double g2 = ld_ctl(&C->gamma);
+  const bool store_z = (g2 != 0.0);
+  const double ig = store_z ? 1.0 / g2 : 0.0;
+  CSL_G double2 *__restrict__ X = gbl(io.x);
+  CSL_G double2 *__restrict__ znew = gbl(S.Z[(j + 1) & 1]);
+  const CSL_G double2 *__restrict__ zj = gbl(S.Z[j & 1]);
+  double e1 = 0, e2 = 0, e3 = 0, ceta = 0, ie1 = 0, e2p = 0, e3p = 0, cetap = 0, ie1p = 0;
+  if (mode != ZM_DEFER) {
+    e1 = ld_ctl(&C->e1);
+    e2 = ld_ctl(&C->e2);
+    e3 = ld_ctl(&C->e3);
+    ceta = ld_ctl(&C->ceta);
+    ie1 = 1.0 / e1;
+  }
+  if (mode == ZM_PAIR) {
+    e2p = ld_ctl(&C->e2p);
+    e3p = ld_ctl(&C->e3p);
+    cetap = ld_ctl(&C->cetap);
+    ie1p = 1.0 / ld_ctl(&C->e1p);
+  }
+  // ZM_SINGLE: wn holds w_{j-1} and receives w_{j+1}, wo holds w_j;
+  // ZM_PAIR: wo holds w_{j-2} and receives w_j, wn holds w_{j-1} and
+  // receives w_{j+1} (each entry read before the same lane overwrites it)
+  CSL_G double2 *__restrict__ wo = gbl(S.W[j & 1]);
+  CSL_G double2 *__restrict__ wn = gbl(S.W[(j + 1) & 1]);
+  auto update = [&](int p, Cx<R> v) {
+    if (mode == ZM_DEFER) {
+      st_nt(znew + p, (double)v.x * ig, (double)v.y * ig);
+    } else if (mode == ZM_SINGLE) {
+      const double2 z = ldg(zj + p);
+      const double2 w0 = j > 2 ? ldg(wn + p) : make_double2(0.0, 0.0);
+      const double2 w1 = j > 1 ? ldg(wo + p) : make_double2(0.0, 0.0);
+      const double2 x = j > 1 ? ldg(X + p) : make_double2(0.0, 0.0);
+      if (store_z) st_nt(znew + p, (double)v.x * ig, (double)v.y * ig);
+      const double wx = (z.x - e3 * w0.x - e2 * w1.x) * ie1;
+      const double wy = (z.y - e3 * w0.y - e2 * w1.y) * ie1;
+      st_nt(wn + p, wx, wy);
+      st_nt(X + p, x.x + ceta * wx, x.y - ceta * wy);
+    } else {
+      const double2 zm = ldg(znew + p);   // zhat_{j-1}
+      const double2 z = ldg(zj + p);
+      const double2 wa = j > 3 ? ldg(wo + p) : make_double2(0.0, 0.0);
+      const double2 wbv = j > 2 ? ldg(wn + p) : make_double2(0.0, 0.0);
+      const double2 x = j > 2 ? ldg(X + p) : make_double2(0.0, 0.0);
+      if (store_z) st_nt(znew + p, (double)v.x * ig, (double)v.y * ig);
+      const double ax = (zm.x - e3p * wa.x - e2p * wbv.x) * ie1p;
+      const double ay = (zm.y - e3p * wa.y - e2p * wbv.y) * ie1p;
+      const double bx = (z.x - e3 * wbv.x - e2 * ax) * ie1;
+      const double by = (z.y - e3 * wbv.y - e2 * ay) * ie1;
+      st_nt(wo + p, ax, ay);
+      st_nt(wn + p, bx, by);
+      const double xx = x.x + cetap * ax, xy = x.y - cetap * ay;
+      st_nt(X + p, xx + ceta * bx, xy - ceta * by);
+    }
+  };
+  for (int rb = r_begin; rb < r_end; rb += G * W) {
+    const int R_ = min(G * W, r_end - rb);
+    for (int e = threadIdx.x; e < R_ * n2; e += NT) {
+      const int k = e / R_, rr = e - k * R_;
+      const int q = k * rows + rb + rr;
+      tin[rr * n2 + k] = Cx<R>{Tr[q], Tr[M + q]};
+    }
+    __syncthreads();
+    const int rr = w * G + g;
+    const int row = rb + rr;
+    const bool act = row < r_end;
+    const Cx<R> *xl = tin + (act ? rr : 0) * n2;
+    Cx<R> a[4];
+    if constexpr (kHalf) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = jl + q * Q;
+        a[q] = Cx<R>{0, 0};
+        if (act && i >= 1) {
+          const Cx<R> u = xl[i - 1], v = xl[N - 1 - i];
+          a[q] = Cx<R>{sn[q] * (u.x + v.x) + 0.5 * (u.x - v.x), sn[q] * (u.y + v.y) + 0.5 * (u.y - v.y)};
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = jl + q * Q;
+        a[q] = Cx<R>{0, 0};
+        if (act && m != 0 && m != N) {
+          const Cx<R> u = xl[m < N ? m - 1 : F - 1 - m];
+          a[q] = m < N ? u : Cx<R>{-u.x, -u.y};
+        }
+      }
+    }
+    __syncthreads();   // every wave has its input: the next round may refill tin
+    wave_fft_line<R>(a, wb, lo, jl, lgF, twl, true);
+    if constexpr (kHalf) {
+      // a lane leaves half_out with four consecutive outputs: back through
+      // the wave buffer so that neighbouring lanes update neighbouring points
+      Cx<double> x[4];
+      half_out(a, wb, lo, jl, lgF, cf, x);
+      wave_lds_sync();
+#pragma unroll
+      for (int u = 0; u < 4; ++u) wb[lo + 4 * jl + u] = x[u];
+      wave_lds_sync();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = jl + q * Q;
+        if (act && k >= 1) update(row * n2 + k - 1, wb[lo + k]);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int k = jl + q * Q;
+        if (act && k >= 1 && k < N) update(row * n2 + k - 1, dst_out(a[q], cf));
+      }
+    }
+  }
+}
+
 // The plane tile: one part of one plane, in the preconditioner precision R
 // (FP32 in the 1024-thread instance, FP64 in the 512-thread one).
 template <typename R>
@@ -1039,6 +1192,14 @@ __device__ __forceinline__ void process_tile(const SysDesc &S, const IOPtr &io, 
 #if CSL_PLANE
   if (kind == K_X && S.plane && iter > 0 && S.lg[2] <= 8) {
     tile_XW<LDSB>(S, iter, tile, smem, red);
+    return;
+  }
+  if (kind == K_Z && S.plane && S.lg[2] <= 8) {
+#if CSL_PLANE_F64
+    tile_ZW<double, LDSB>(S, io, iter, tile, smem);
+#else
+    tile_ZW<float, LDSB>(S, io, iter, tile, smem);
+#endif
     return;
   }
   if (kind == K_Y && S.plane) {
