@@ -552,10 +552,18 @@ __device__ __forceinline__ Cx<R> pair_ext(const R *la, const R *lb, bool hasb, i
 }
 
 // Sine transform, in place, of the nlines real lines of a real plane (line l
-// at pl[l ldl + r ldp]), lines 2p and 2p + 1 as one complex line.
-template <typename R>
+// at pl[l ldl + r ldp]), lines 2p and 2p + 1 as one complex line.  With
+// contiguous lines (ldp = 1) a wave's lines of one round are the plane
+// elements [e0, e1): pre(e0, e1) runs before the wave reads them (it may
+// write them) and post(e0, e1) after it has written their transforms, each
+// on the wave's own lanes.
+struct PlaneNoHook {
+  __device__ __forceinline__ void operator()(int, int) const {}
+};
+template <typename R, class Pre = PlaneNoHook, class Post = PlaneNoHook>
 __device__ __forceinline__ void plane_dst_pairs(R *pl, Cx<R> *wbuf, const Cx<R> *twl, int nlines, int lg,
-                                                int ldl, int ldp) {
+                                                int ldl, int ldp, Pre &&pre = Pre(),
+                                                Post &&post = Post()) {
   const int L = 1 << lg, Q = L >> 2, N = L >> 1;
   const int G = 64 >> (lg - 2);   // complex lines per wave
   const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
@@ -568,6 +576,9 @@ __device__ __forceinline__ void plane_dst_pairs(R *pl, Cx<R> *wbuf, const Cx<R> 
     const int p = p0 + g;
     const bool act = p < npairs;
     const bool hasb = act && 2 * p + 1 < nlines;
+    const int e0 = 2 * p0 * ldl, e1 = min(2 * (p0 + G), nlines) * ldl;
+    pre(e0, e1);
+    wave_lds_sync();
     R *la = pl + (size_t)(act ? 2 * p : 0) * ldl;
     R *lb = la + ldl;
     Cx<R> a[4];
@@ -583,6 +594,8 @@ __device__ __forceinline__ void plane_dst_pairs(R *pl, Cx<R> *wbuf, const Cx<R> 
         if (hasb) lb[(k - 1) * ldp] = v.y;
       }
     }
+    wave_lds_sync();
+    post(e0, e1);
   }
 }
 
@@ -668,8 +681,10 @@ __device__ __forceinline__ void half_out(const Cx<double> (&a)[4], Cx<double> *w
 // Sine transform, in place, of the nlines real FP64 lines of a plane (line l
 // at pl[l ldl + r ldp]) through FFTs of N = 2^lgN points, lines 2p and 2p + 1
 // as one complex line.
+template <class Pre = PlaneNoHook, class Post = PlaneNoHook>
 __device__ __forceinline__ void plane_dst_pairs_half(double *pl, Cx<double> *wbuf, const Cx<double> *twl,
-                                                     int nlines, int lgN, int ldl, int ldp) {
+                                                     int nlines, int lgN, int ldl, int ldp,
+                                                     Pre &&pre = Pre(), Post &&post = Post()) {
   const int N = 1 << lgN, Q = N >> 2;
   const int G = 64 >> (lgN - 2);   // complex lines per wave
   const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
@@ -684,6 +699,9 @@ __device__ __forceinline__ void plane_dst_pairs_half(double *pl, Cx<double> *wbu
     const int p = p0 + g;
     const bool act = p < npairs;
     const bool hasb = act && 2 * p + 1 < nlines;
+    const int e0 = 2 * p0 * ldl, e1 = min(2 * (p0 + G), nlines) * ldl;
+    pre(e0, e1);
+    wave_lds_sync();
     double *la = pl + (size_t)(act ? 2 * p : 0) * ldl;
     double *lb = la + ldl;
     Cx<double> a[4];
@@ -700,6 +718,8 @@ __device__ __forceinline__ void plane_dst_pairs_half(double *pl, Cx<double> *wbu
         if (hasb) lb[(k - 1) * ldp] = x[u].y;
       }
     }
+    wave_lds_sync();
+    post(e0, e1);
   }
 }
 
@@ -961,46 +981,58 @@ __device__ __forceinline__ void tile_YP(const SysDesc &S, int iter, int tile, ch
   if (lg1 != lg0) load_twiddles<R>(tw1, lg1);
   const size_t off = (size_t)comp * S.M + (size_t)c * rows;
   const int j = iter;
-  if (j == 0) {
-    const CSL_G double *__restrict__ v1 = reinterpret_cast<const CSL_G double *>(gbl(S.Tv[1])) + off;
-    for (int e = threadIdx.x; e < rows; e += NT) pl[e] = (R)v1[e];
-  } else {
+  const int lane = threadIdx.x & 63;
+  // the plane's rows, each wave its own just before it transforms them:
+  // Tv_1 at iteration 0, else the Lanczos update
+  const CSL_G double *__restrict__ v1 = reinterpret_cast<const CSL_G double *>(gbl(S.Tv[1])) + off;
+  const CSL_G double *__restrict__ tq = reinterpret_cast<const CSL_G double *>(gbl(S.Tq)) + off;
+  const CSL_G double *__restrict__ vj = reinterpret_cast<const CSL_G double *>(gbl(S.Tv[j & 1])) + off;
+  // holds Tv_{j-1}
+  CSL_G double *__restrict__ vout = reinterpret_cast<CSL_G double *>(gbl(S.Tv[(j + 1) & 1])) + off;
+  double cd = 0.0, cg = 0.0;
+  if (j > 0) {
     const Ctl *C = S.ctl;
     const double g = ld_ctl(&C->gamma), go = ld_ctl(&C->gamma_old);
     const double dl = ld_ctl(&C->delta);
-    const double cd = dl / g, cg = g / go;
-    const CSL_G double *__restrict__ tq = reinterpret_cast<const CSL_G double *>(gbl(S.Tq)) + off;
-    const CSL_G double *__restrict__ vj = reinterpret_cast<const CSL_G double *>(gbl(S.Tv[j & 1])) + off;
-    // holds Tv_{j-1}
-    CSL_G double *__restrict__ vout = reinterpret_cast<CSL_G double *>(gbl(S.Tv[(j + 1) & 1])) + off;
-    const bool has_vm1 = j >= 2;
-    constexpr int U = 8;
-    for (int e0 = 0; e0 < rows; e0 += NT * U) {
+    cd = dl / g;
+    cg = g / go;
+  }
+  const bool has_vm1 = j >= 2;
+  auto fill = [&](int e0, int e1) {
+    constexpr int U = 4;
+    for (int b = e0; b < e1; b += 64 * U) {
       double q[U], a1[U], a0[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int e = e0 + u * NT + (int)threadIdx.x;
-        if (e < rows) {
-          q[u] = tq[e];
-          a1[u] = vj[e];
-          a0[u] = has_vm1 ? vout[e] : 0.0;
+        const int e = b + u * 64 + lane;
+        if (e < e1) {
+          if (j == 0) {
+            q[u] = v1[e];
+          } else {
+            q[u] = tq[e];
+            a1[u] = vj[e];
+            a0[u] = has_vm1 ? vout[e] : 0.0;
+          }
         }
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int e = e0 + u * NT + (int)threadIdx.x;
-        if (e < rows) {
-          const double v = q[u] - cd * a1[u] - cg * a0[u];
-          st_nt(vout + e, v);
-          pl[e] = (R)v;
+        const int e = b + u * 64 + lane;
+        if (e < e1) {
+          if (j == 0) {
+            pl[e] = (R)q[u];
+          } else {
+            const double v = q[u] - cd * a1[u] - cg * a0[u];
+            st_nt(vout + e, v);
+            pl[e] = (R)v;
+          }
         }
       }
     }
-  }
-  __syncthreads();
+  };
   // axis 1 forward: n0 lines of n1 points, contiguous in the plane
-  if constexpr (kHalf) plane_dst_pairs_half(pl, wbuf, tw1, n0, lg1, n1, 1);
-  else plane_dst_pairs<R>(pl, wbuf, tw1, n0, lg1, n1, 1);
+  if constexpr (kHalf) plane_dst_pairs_half(pl, wbuf, tw1, n0, lg1, n1, 1, fill);
+  else plane_dst_pairs<R>(pl, wbuf, tw1, n0, lg1, n1, 1, fill);
   __syncthreads();
   // axis 0: n1 lines of n0 points at stride n1, neighbouring columns in
   // pairs; forward transform, the per-mode factor of each column's own mode
@@ -1145,12 +1177,13 @@ __device__ __forceinline__ void tile_YP(const SysDesc &S, int iter, int tile, ch
     }
   }
   __syncthreads();
-  // axis 1 inverse
-  if constexpr (kHalf) plane_dst_pairs_half(pl, wbuf, tw1, n0, lg1, n1, 1);
-  else plane_dst_pairs<R>(pl, wbuf, tw1, n0, lg1, n1, 1);
-  __syncthreads();
+  // axis 1 inverse, each wave storing its rows of T' once it has them
   CSL_G R *Tr = reinterpret_cast<CSL_G R *>(gbl(S.T)) + off;
-  for (int e = threadIdx.x; e < rows; e += NT) st_nt(Tr + e, pl[e]);
+  auto store = [&](int e0, int e1) {
+    for (int e = e0 + lane; e < e1; e += 64) st_nt(Tr + e, pl[e]);
+  };
+  if constexpr (kHalf) plane_dst_pairs_half(pl, wbuf, tw1, n0, lg1, n1, 1, PlaneNoHook(), store);
+  else plane_dst_pairs<R>(pl, wbuf, tw1, n0, lg1, n1, 1, PlaneNoHook(), store);
   const double sg = wg_sum(gacc, red);
   if (threadIdx.x == 0) S.part[tile] = sg;
 }
