@@ -807,8 +807,8 @@ __device__ __forceinline__ void tile_XW(const SysDesc &S, int iter, int tile, ch
 
 // Phase Z of a plane solve with rows of n2 = N - 1 <= 127 points, per wave as
 // tile_XW: a round's rows of T' (plane layout) are read rows-fastest into LDS,
-// then every wave transforms its rows (FP32: the odd extension, one row a
-// wave; FP64: FFTs of N points, two rows a wave) and applies the step's
+// then every wave transforms its rows (FP32: the odd extension, 128 / N rows
+// a wave; FP64: FFTs of N points, 256 / N rows a wave) and applies the step's
 // update to its outputs itself, so the update's loads and stores of some
 // waves run under the transforms of others.  Same values as tile_Z up to the
 // transform's rounding; the flush of a deferred step (no transform) is
