@@ -1599,10 +1599,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(CSL_WAVES_PE
   const long long t0 = wall_clock64();
   int backoff = 0;
   // Longest back-off, in rounds of s_sleep(8): a single system leaves every
-  // workgroup idle between its phases, and a short cap (about 0.9 us) takes
-  // up the next phase sooner; a batch keeps workgroups busy with other
+  // workgroup idle between its phases, and one round (about 0.2 us) takes up
+  // the next phase soonest; a batch keeps workgroups busy with other
   // systems, and polls less (about 14 us).
-  const int bcap = nsys > 1 ? 64 : 4;
+  const int bcap = nsys > 1 ? 64 : 1;
   // a single system: once every workgroup has started, phases are published
   // with tiles 0 .. min(grid, tiles) - 1 owned by workgroups, one each
   // (xcd_tile)
