@@ -216,8 +216,10 @@ def test_plane_batch(csl, fp32):
     # phase: each system against the FP64 oracle's iterate after the GPU's
     # number of steps (the precision's bar), with the schedule kept by the
     # batch
+    # (7, 15, 255): rows longer than a wave's transform, so its phases X and Z
+    # run workgroup-wide beside the per-wave ones of the others
     cases = [((15, 31, 15), -20.0 + 45.0j, None), ((31, 15, 7), 10.0 + 100.0j, None),
-             ((7, 7, 63), 5.0 + 20.0j, [1.0, 0.5, 2.0])]
+             ((7, 7, 63), 5.0 + 20.0j, [1.0, 0.5, 2.0]), ((7, 15, 255), 2.0 + 60.0j, None)]
     probs, fs, olds = [], [], []
     for i, (shape, lam, lengths) in enumerate(cases):
         a = _coef(shape, 81 + i)
