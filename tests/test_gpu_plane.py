@@ -241,13 +241,14 @@ def test_plane_batch(csl, fp32):
         p.close()
 
 
-def test_plane_batch_adjoint(csl):
+@pytest.mark.parametrize("fp32", [True, False], ids=["fp32", "fp64"])
+def test_plane_batch_adjoint(csl, fp32):
     # the batched adjoint on the plane phase (one grid, two shifts) against
     # each problem's own adjoint on the plane schedule, all at tol 1e-12:
     # per-system gradients in f and alpha, the summed one in a (1e-9)
     shape = (15, 31, 15)
     a = _coef(shape, 95)
-    probs = [csl.Problem(cuda(a), lam.real, lam.imag, pinv_fp32=True, dst="fft")
+    probs = [csl.Problem(cuda(a), lam.real, lam.imag, pinv_fp32=fp32, dst="fft")
              for lam in (-20.0 + 45.0j, 10.0 + 100.0j)]
     fs = [cuda(_crand(shape, 96 + i)) for i in range(2)]
     b = csl.Batch(probs, tol=1e-12, block_threads=1024)
